@@ -1,0 +1,41 @@
+"""Small seeded cases shared by the tests (inputs only)."""
+import numpy as np
+
+from workloads import Plate, build_system, make_small
+
+
+def homogeneous(nx, ny, nz, neumann=True, plates=()):
+    lnk = np.zeros((nz, ny, nx))
+    return build_system(nx, ny, nz, lnk, list(plates), 100.0, neumann=neumann)
+
+
+def hat_1d(n, c):
+    """Closed-form 1D interpolants on n cells with coarse nodes from
+    oracle-independent arithmetic: nodes at block centres, linear between
+    consecutive nodes, constant beyond the outermost ones."""
+    starts = np.arange(0, n, c)
+    nodes = starts + (np.minimum(starts + c, n) - starts) // 2
+    H = np.zeros((n, len(nodes)))
+    for x in range(n):
+        if x <= nodes[0]:
+            H[x, 0] = 1.0
+        elif x >= nodes[-1]:
+            H[x, -1] = 1.0
+        else:
+            k = np.searchsorted(nodes, x, side="right") - 1
+            a, b = nodes[k], nodes[k + 1]
+            H[x, k] = (b - x) / (b - a)
+            H[x, k + 1] = (x - a) / (b - a)
+    return H
+
+
+SMALL = {
+    "2d": dict(kind="2d", coarse=(4, 4, 1), d_min=4, r_z=1),
+    "3d": dict(kind="3d", coarse=(4, 4, 4), d_min=4, r_z=4),
+}
+
+
+def small_case(name, seed=0, neumann=False, **kw):
+    spec = SMALL[name]
+    s = make_small(spec["kind"], seed=seed, neumann=neumann, **kw)
+    return s, spec

@@ -1,0 +1,133 @@
+"""Pins of the oracle's coarse system, ILU(0), iteration (Table 1) and flux."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+from oracle import fams, flux, grids
+from tests._cases import homogeneous, small_case
+
+VARIANTS = [fams.DECOUPLED, fams.FRAC, fams.ROCK, fams.COUPLED]
+
+
+def _setup(name, variant, seed=0, alpha=0.0, **kw):
+    s, spec = small_case(name, seed=seed, **kw)
+    wb, primal, vertex, ncm = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    F = fams.FAMS(s.csr(), wb, vertex, s.n_matrix, variant, alpha)
+    return s, F, wb, primal, vertex
+
+
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_ilu0_defining_property(name):
+    """ILU(0): L unit lower, U upper, both on pattern(A), and (LU)_ij = A_ij
+    for every (i, j) in pattern(A)."""
+    s, _ = small_case(name)
+    A = s.csr()
+    L, U = fams.ILU0(A).factors()
+    pat = (abs(A) > 0).astype(int)
+    assert ((abs(L) > 0).astype(int) - pat).max() <= 0
+    assert ((abs(U) > 0).astype(int) - pat).max() <= 0
+    LU = (L @ U).tocsr()
+    r, c = A.nonzero()
+    err = np.abs(np.asarray(LU[r, c]).ravel() - np.asarray(A[r, c]).ravel())
+    assert err.max() <= 1e-12 * abs(A).max()
+
+
+def test_ilu0_exact_on_tridiagonal():
+    """On a tridiagonal matrix ILU(0) is the exact LU: the smoother solves."""
+    s = homogeneous(40, 1, 1, neumann=False)
+    A = s.csr()
+    b = np.random.default_rng(1).standard_normal(40)
+    x = fams.ILU0(A).solve(b)
+    assert np.abs(x - spl.spsolve(A.tocsc(), b)).max() < 1e-12 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_coarse_operator_spd(variant):
+    """MSFE restriction R = P^T gives a symmetric positive definite A_c (Sec. 3)."""
+    s, F, *_ = _setup("3d", variant)
+    Ac = F.Ac
+    assert np.abs(Ac - Ac.T).max() <= 1e-12 * np.abs(Ac).max()
+    np.linalg.cholesky(Ac)
+
+
+def test_coarsening_one_is_identity():
+    """Every cell a coarse node: P = I, A_c = A, and one F-AMS step is exact."""
+    s, _ = small_case("2d")
+    wb, primal, vertex, ncm = grids.full_grid(s, (1, 1, 1), d_min=1, r_z=1)
+    assert np.all(wb == 3)
+    F = fams.FAMS(s.csr(), wb, vertex, s.n_matrix, fams.DECOUPLED)
+    perm = sp.csr_matrix((np.ones(s.n), (vertex, np.arange(s.n))), shape=(s.n, s.n))
+    assert abs(F.P - perm).max() == 0
+    assert np.abs(F.Ac - (perm.T @ s.csr() @ perm).toarray()).max() < 1e-12 * np.abs(F.Ac).max()
+    p, info = F.richardson(s.q, rtol=1e-12, max_iter=1)
+    assert info["status"] == fams.OK and info["iterations"] == 1
+
+
+def test_closed_form_linear_pressure():
+    """Homogeneous matrix, no fractures, p = 1 on x = 0 and p = 0 on x = 1
+    (half-cell boundary transmissibility): p_i = 1 - x_i exactly."""
+    nx, ny, nz = 20, 6, 5
+    s = homogeneous(nx, ny, nz, neumann=False)
+    wb, _, vertex = grids.structured_grid(nx, ny, nz, 4, 3, 3)
+    F = fams.FAMS(s.csr(), wb, vertex, s.n_matrix, fams.DECOUPLED)
+    p, info = F.gmres(s.q, rtol=1e-13)
+    x = (np.arange(nx) + 0.5) / nx
+    expect = np.broadcast_to(1.0 - x, (nz, ny, nx)).ravel()
+    assert np.abs(p - expect).max() < 1e-10
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_converges_to_direct_solve(name, variant):
+    """Table 1 is a stationary iteration with fixed point A p = q: both the
+    Richardson loop and GMRES reach the sparse direct solution."""
+    s, F, *_ = _setup(name, variant, alpha=1e-2 if name == "3d" else 0.0)
+    pref = spl.spsolve(s.csr().tocsc(), s.q)
+    for p, info in (F.richardson(s.q, rtol=1e-12, max_iter=400), F.gmres(s.q, rtol=1e-12)):
+        assert info["status"] == fams.OK
+        assert np.linalg.norm(p - pref) <= 1e-9 * np.linalg.norm(pref)
+
+
+def test_single_sweep_is_galerkin_projection():
+    """Stopping after step 5 of the first iteration (Sec. 4.2) gives
+    p' = P (P^T A P)^{-1} P^T q."""
+    s, F, *_ = _setup("2d", fams.COUPLED)
+    P = F.P.toarray()
+    Ad = s.csr().toarray()
+    expect = P @ np.linalg.solve(P.T @ Ad @ P, P.T @ s.q)
+    F.ilu = None
+    p, info = F.richardson(s.q, rtol=0.0, max_iter=1)
+    assert np.abs(p - expect).max() < 1e-10 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_flux_reconstruction_conservative(name, variant):
+    """After the FV stage every primal block conserves mass, and the
+    reconstructed flux balances every cell (target 1e-10)."""
+    s, F, wb, primal, vertex = _setup(name, variant)
+    p, _ = F.gmres(s.q, rtol=1e-6)
+    A = F.A
+    fl, p1, p2, imb = flux.reconstruct_flux(A, F.P, primal, vertex, s.q, p)
+    Rfv = flux.fv_restriction(primal, len(vertex))
+    rc = Rfv @ (s.q - A @ p1)
+    assert np.abs(rc).max() <= 1e-12 * np.abs(Rfv @ np.abs(A) @ np.abs(p1)).max()
+    assert imb <= 1e-10
+    # antisymmetry of the off-diagonal fluxes
+    Fm = sp.csr_matrix((fl, A.indices, A.indptr), shape=A.shape)
+    off = Fm - sp.diags(Fm.diagonal())
+    assert abs(off + off.T).max() <= 1e-13 * abs(off).max()
+
+
+def test_flux_exact_pressure_gives_tpfa_fluxes():
+    """With the exact pressure the FV stage and local solves change nothing:
+    F_ij = T_ij (p_i - p_j)."""
+    s, F, wb, primal, vertex = _setup("3d", fams.DECOUPLED)
+    A = F.A
+    p = spl.spsolve(A.tocsc(), s.q)
+    fl, p1, p2, imb = flux.reconstruct_flux(A, F.P, primal, vertex, s.q, p)
+    r = np.repeat(np.arange(s.n), np.diff(A.indptr))
+    off = r != A.indices
+    expect = -A.data[off] * (p[r[off]] - p[A.indices[off]])
+    assert np.abs(fl[off] - expect).max() <= 1e-8 * np.abs(expect).max()
