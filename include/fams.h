@@ -1,0 +1,234 @@
+/*
+ * fams.h -- C ABI of the MI355X F-AMS pressure solver.
+ *
+ * F-AMS (Tene, Al Kobaisi, Hajibeygi, "Algebraic multiscale method for flow in
+ * heterogeneous porous media with embedded discrete fractures") solves the
+ * fine-scale EDFM system A p = q of the paper's Eq. (A-dis-mf): rows ordered
+ * [matrix cells | fracture cells].  Given coarse grids for both media (Sec. 3,
+ * Fig. 2) it builds the prolongation P column by column from local basis
+ * functions in wirebasket order (Sec. 3.1, App. A) for one of four coupling
+ * strategies, the coarse operator A_c = R A P with R = P^T (Sec. 3, App. A),
+ * and iterates the two-stage scheme of Table 1 (multiscale stage + ILU(0)
+ * smoothing) either as a Richardson loop or as the preconditioner of GMRES
+ * (Sec. 4.4-4.5).  After any iterate a conservative flux field can be
+ * reconstructed through a finite-volume stage (Sec. 3.2, Sec. 4.5).
+ *
+ * Memory and ownership
+ *   - Every array argument marked "device" is caller-owned GPU memory (e.g. a
+ *     torch tensor on the current device), read during the call only.
+ *     fams_setup copies everything it keeps into handle-owned device memory.
+ *   - Every array marked "host" is caller-owned host memory.
+ *   - All device work of a call is issued on the stream given to fams_setup
+ *     (NULL = the default stream); calls that return host scalars synchronise
+ *     that stream before returning.
+ *   - A handle is used by one host thread / stream at a time; distinct handles
+ *     are independent and may run concurrently on different streams.
+ *
+ * Errors: no exceptions cross the ABI.  Negative status = error (on a setup
+ * error *out is NULL and nothing is leaked; on a solve error the handle stays
+ * valid); positive status = the iteration stopped without meeting rtol, with
+ * the info record filled in.
+ */
+#ifndef FAMS_H_
+#define FAMS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fams_handle_s* fams_handle_t;
+
+typedef enum {
+  FAMS_OK = 0,
+  FAMS_NOT_CONVERGED = 1,        /* max_iter reached; info filled in */
+  FAMS_DIVERGED = 2,             /* ||r|| > 1e8 ||r0|| or not finite */
+  FAMS_ERR_INVALID_ARG = -1,     /* NULL/size/option error, NaN in q */
+  FAMS_ERR_BAD_GRID = -2,        /* inconsistent wb_type / primal / vertex */
+  FAMS_ERR_SINGULAR_LOCAL = -3,  /* a local block has no higher-rank neighbour,
+                                    or a non-positive pivot in its solve */
+  FAMS_ERR_SINGULAR_COARSE = -4, /* zero pivot in the coarse LU */
+  FAMS_ERR_ZERO_PIVOT_ILU = -5,  /* non-positive ILU(0) pivot */
+  FAMS_ERR_OOM = -6,             /* device allocation failed */
+  FAMS_ERR_DEVICE = -7,          /* a HIP runtime call failed */
+  FAMS_ERR_CAPACITY = -8         /* an internal per-block limit was exceeded */
+} fams_status_t;
+
+/* Coupling strategy of the basis functions (Sec. 3, the four definitions;
+ * App. A.1-A.4). */
+typedef enum { FAMS_DECOUPLED = 0, FAMS_FRAC = 1, FAMS_ROCK = 2, FAMS_COUPLED = 3 } fams_variant_t;
+
+/* FP64 = everything in double.  MIXED = basis construction, ILU(0) storage
+ * and the whole preconditioner in float; residual, Krylov vectors, solution
+ * update, coarse solve and flux in double (a flexible outer loop). */
+typedef enum { FAMS_PREC_FP64 = 0, FAMS_PREC_MIXED = 1 } fams_precision_t;
+
+/* Outer iteration: the Table 1 loop, or GMRES with Table 1 steps 5-7 as a
+ * right preconditioner (flexible GMRES, Sec. 4.4). */
+typedef enum { FAMS_RICHARDSON = 0, FAMS_GMRES = 1 } fams_outer_t;
+
+/* Fine system A (Eq. A-dis-mf).  Rows/columns: matrix cells 0..n_matrix-1 in
+ * natural grid order, then fracture cells.  CSR with columns sorted within
+ * each row and the diagonal stored.  A must be symmetric positive definite
+ * with non-positive off-diagonals (TPFA + EDFM connectivity). */
+typedef struct {
+  int64_t n;                  /* total fine cells (< 2^31) */
+  int64_t n_matrix;           /* matrix cells; rows >= n_matrix are fracture cells */
+  int64_t nnz;                /* stored entries (< 2^31) */
+  const int64_t* row_ptr;     /* device [n+1] */
+  const int32_t* col_idx;     /* device [nnz] */
+  const double* val;          /* device [nnz] */
+} fams_csr_t;
+
+/* Coarse grids of both media (Sec. 3, Fig. 2).  wb_type is the wirebasket
+ * class of each cell (0 = interior, 1 = face, 2 = edge, 3 = vertex; fracture
+ * cells are never 0, App. A); vertex[K] is the coarse node of primal block K,
+ * the only cell of class 3 in it; primal[i] is the primal block of cell i
+ * (used by the finite-volume restriction, Sec. 3.2). */
+typedef struct {
+  int64_t n_coarse;           /* coarse nodes, matrix and fracture */
+  const int8_t* wb_type;      /* device [n] */
+  const int32_t* primal;      /* device [n], values in [0, n_coarse) */
+  const int64_t* vertex;      /* device [n_coarse] */
+} fams_grid_t;
+
+/* Optional device-memory hook (e.g. a framework's caching allocator).  NULL
+ * in fams_setup = hipMalloc/hipFree. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} fams_allocator_t;
+
+typedef struct {
+  int32_t variant;            /* fams_variant_t */
+  int32_t precision;          /* fams_precision_t */
+  double trunc_alpha;         /* drop |P_ij| < alpha, rescale row (Sec. 4.3); 0 = off */
+  int64_t merge_cap;          /* Coupled-AMS: max cells of a merged block (Sec. 3.1) */
+  int32_t smoother;           /* 1 = ILU(0) post-smoothing (Table 1 step 7), 0 = none */
+  int32_t reserved;
+} fams_setup_opts_t;
+
+typedef struct {
+  int32_t outer;              /* fams_outer_t */
+  int32_t restart;            /* GMRES restart length (e.g. 30) */
+  double rtol;                /* stop when ||q - A p||_2 <= rtol ||q - A p0||_2 */
+  int32_t max_iter;           /* preconditioner applications (Table 1 sweeps) */
+  int32_t use_initial_guess;  /* 0: p0 = 0; 1: p holds p0 on entry */
+} fams_solve_opts_t;
+
+typedef struct {
+  int32_t status;             /* fams_status_t of this right-hand side */
+  int32_t iterations;
+  double rel_residual;        /* true ||q - A p|| / ||q - A p0|| at exit */
+  double ms;                  /* wall time of this right-hand side */
+} fams_info_t;
+
+typedef struct {
+  int64_t n, n_matrix, nnz;
+  int64_t n_coarse;
+  int64_t nnz_P;              /* after truncation */
+  int64_t n_blocks;           /* local blocks (components) solved */
+  int64_t max_block;          /* largest local block (cells) */
+  int64_t fp32_fallback_blocks; /* MIXED: blocks re-solved in FP64 */
+  int64_t ilu_levels_lower, ilu_levels_upper;
+  double ms_setup;
+  int64_t device_bytes;       /* device memory held by the handle */
+} fams_setup_info_t;
+
+/* ---- lifecycle -------------------------------------------------------- */
+
+/* Upper bound of the device memory a handle for this system will hold
+ * (host-only estimate from sizes; used for admission).  max_nrhs and
+ * restart size the solve workspace. */
+fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t precision,
+                             int32_t restart, size_t* bytes_upper_bound);
+
+/* Setup (Table 1 step 4 and the coarse system of step 5, plus the ILU(0)
+ * factors): ranks and local blocks, basis functions in wirebasket order
+ * (App. A), optional truncation (Sec. 4.3), R = P^T, A_c = P^T A P (dense
+ * FP64), its LU with partial pivoting and inverse, ILU(0) of A in natural
+ * order.  Everything stays device resident in the handle.  Blocking. */
+fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* grid,
+                         const fams_setup_opts_t* opts, const fams_allocator_t* allocator,
+                         void* hip_stream, fams_handle_t* out);
+
+/* Solve A p = q for nrhs right-hand sides (device, column-major [n x nrhs]).
+ * info (host, [nrhs], may be NULL).  Returns the worst status. */
+fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nrhs,
+                         const fams_solve_opts_t* opts, fams_info_t* info);
+
+/* Conservative flux reconstruction after an FV stage (Sec. 3.2, Sec. 4.5):
+ * flux (device [nnz], in A's CSR slots): off-diagonal slot (i,j) holds the
+ * flux F_ij from i to j; the diagonal slot holds E_i, the boundary/source
+ * exchange, so that sum_j F_ij + E_i = 0 for every cell.  p_fv (device [n],
+ * may be NULL) receives the FV-stage pressure.  *max_rel_imbalance (host) =
+ * max_i |sum_j F_ij + E_i| / max_i (sum_j |F_ij| + |E_i|). */
+fams_status_t fams_reconstruct_flux(fams_handle_t h, const double* q, const double* p,
+                                    double* flux, double* p_fv, double* max_rel_imbalance);
+
+fams_status_t fams_get_setup_info(fams_handle_t h, fams_setup_info_t* info);
+fams_status_t fams_destroy(fams_handle_t h);
+const char* fams_status_string(fams_status_t s);
+
+/* ---- inspection (tests, profiling) ------------------------------------ */
+
+/* P (CSR n x n_coarse, after truncation) copied to host; pass NULL arrays to
+ * query nnz first.  row_ptr [n+1], col [nnz], val [nnz] (host). */
+fams_status_t fams_get_prolongation(fams_handle_t h, int64_t* nnz, int64_t* row_ptr,
+                                    int32_t* col, double* val);
+/* Dense A_c = P^T A P, column-major [n_coarse^2] (host). */
+fams_status_t fams_get_coarse_matrix(fams_handle_t h, double* ac);
+/* ILU(0) factors in A's CSR slots (L unit lower below the diagonal, U on and
+ * above), FP64 [nnz] (host). */
+fams_status_t fams_get_ilu(fams_handle_t h, double* lu_val);
+/* One application of Table 1 steps 5-7 to a residual r: z = dp_{1/2} +
+ * dp_{2/2} (device [n] each). */
+fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
+/* Per-kernel timing with HIP events on the handle's stream: enable (1) or
+ * disable (0); then read total milliseconds and launch counts per kernel
+ * name (host strings valid until the handle is destroyed). */
+fams_status_t fams_set_profiling(fams_handle_t h, int32_t on);
+fams_status_t fams_get_kernel_stats(fams_handle_t h, int32_t max_entries, int32_t* n_entries,
+                                    const char** names, double* total_ms, int64_t* launches);
+
+/* ---- host helpers for coarse grids (not timed) ------------------------ */
+
+/* Structured matrix grid nx*ny*nz with coarsening cx*cy*cz (Sec. 3,
+ * Fig. 2): the coarse node of each primal block is its centre cell per axis
+ * (start + floor(len/2)); a cell's class is the number of its coordinates
+ * lying on a coarse-node plane.  Host arrays: wb_type [n], primal [n],
+ * vertex [ceil(nx/cx)*ceil(ny/cy)*ceil(nz/cz)]; blocks numbered x fastest. */
+fams_status_t fams_grid_structured(int32_t nx, int32_t ny, int32_t nz, int32_t cx, int32_t cy,
+                                   int32_t cz, int8_t* wb_type, int32_t* primal, int64_t* vertex,
+                                   int64_t* n_coarse);
+
+/* Fracture coarse grid: the distance-based coarsening of Table 2 run on the
+ * x-y projection of each network (projected columns and their adjacency),
+ * extruded along z with coarse layers k mod r_z == r_z/2 (or a plate's middle
+ * layer when it has none) (Sec. 4.3).  A fracture cell is a vertex when its
+ * column is a vertex column and its layer a coarse layer, an edge when
+ * exactly one holds, a face otherwise.  Edge blocks without a vertex
+ * neighbour and face blocks without an edge/vertex neighbour get their
+ * lowest cell promoted to vertex.  Primal block of a fracture cell = nearest
+ * vertex by graph distance (ties: lower coarse id).  Inputs (host):
+ * A's CSR (to read fracture-fracture connections), cell_col/cell_z [n_f],
+ * col_plate [n_cols], column graph col_ptr [n_cols+1]/col_adj, plate_zlo/
+ * plate_zhi [n_plates]; d_min <= 0 means infinity.  Outputs (host): wb_type
+ * and primal [n_f] for the fracture cells, vertex [n_f] (capacity) with the
+ * fine indices of the fracture coarse nodes in ascending order, their count
+ * in *n_coarse_frac; fracture coarse ids start at n_coarse_matrix. */
+fams_status_t fams_grid_fracture(int64_t n_matrix, int64_t n, const int64_t* row_ptr,
+                                 const int32_t* col_idx, const int32_t* cell_col,
+                                 const int32_t* cell_z, int64_t n_cols, const int32_t* col_plate,
+                                 const int64_t* col_ptr, const int32_t* col_adj, int64_t n_plates,
+                                 const int32_t* plate_zlo, const int32_t* plate_zhi, int32_t d_min,
+                                 int32_t r_z, int64_t n_coarse_matrix, int8_t* wb_type,
+                                 int32_t* primal, int64_t* vertex, int64_t* n_coarse_frac);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAMS_H_ */

@@ -1,0 +1,403 @@
+// The C ABI of include/fams.h: argument checks, ownership, error mapping and
+// the setup orchestration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace fams {
+
+static thread_local std::string g_last_error;
+
+[[noreturn]] void hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" +
+                  std::to_string(line) + ")";
+  throw Error(e == hipErrorOutOfMemory ? FAMS_ERR_OOM : FAMS_ERR_DEVICE, m);
+}
+
+void* Allocator::alloc(size_t bytes) {
+  void* p = nullptr;
+  if (has_hook) {
+    p = hook.alloc(hook.ctx, bytes, stream);
+    if (!p) throw Error(FAMS_ERR_OOM, "allocator hook returned NULL");
+  } else {
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(FAMS_ERR_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  live_bytes += static_cast<int64_t>(bytes);
+  peak_bytes = std::max(peak_bytes, live_bytes);
+  return p;
+}
+
+void Allocator::release(void* p, size_t bytes) {
+  if (!p) return;
+  if (has_hook) hook.free(hook.ctx, p, stream);
+  else (void)hipFreeAsync(p, stream);
+  live_bytes -= static_cast<int64_t>(bytes);
+}
+
+int Prof::begin(const char* name) {
+  if (!on) return -1;
+  Pending pe;
+  pe.name = name;
+  HIPX(hipEventCreate(&pe.a));
+  HIPX(hipEventCreate(&pe.b));
+  HIPX(hipEventRecord(pe.a, stream));
+  pending.push_back(pe);
+  return static_cast<int>(pending.size()) - 1;
+}
+
+void Prof::end(int token) {
+  if (token < 0) return;
+  HIPX(hipEventRecord(pending[token].b, stream));
+  if (pending.size() > 20000) collect();
+}
+
+void Prof::collect() {
+  if (pending.empty()) return;
+  HIPX(hipStreamSynchronize(stream));
+  for (auto& pe : pending) {
+    float ms = 0.f;
+    HIPX(hipEventElapsedTime(&ms, pe.a, pe.b));
+    auto& t = totals[pe.name];
+    t.first += ms;
+    t.second += 1;
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  pending.clear();
+}
+
+Prof::~Prof() {
+  for (auto& pe : pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+}
+
+namespace {
+
+__global__ void k_rowptr_i32(int64_t n, const int64_t* src, int* dst, int* err) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  int64_t v = src[i];
+  if (v < 0 || v > INT32_MAX) atomicOr(err, 1);
+  dst[i] = static_cast<int>(v);
+  if (i < n && src[i + 1] < v) atomicOr(err, 2);
+}
+
+__global__ void k_vertex_i32(int64_t n, const int64_t* src, int* dst) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = static_cast<int>(src[i]);
+}
+
+__global__ void k_cols_check(int64_t nnz, int n, const int* ci, int* err) {
+  int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < nnz && (ci[p] < 0 || ci[p] >= n)) atomicOr(err, 4);
+}
+
+__global__ void k_d2f_api(int64_t n, const double* a, float* b) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<float>(a[i]);
+}
+
+fams_status_t fail(const Error& e) {
+  g_last_error = e.what();
+  return e.status;
+}
+
+template <class F>
+fams_status_t guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return FAMS_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return FAMS_ERR_DEVICE;
+  }
+}
+
+void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = A->n;
+  Allocator* al = &h->alloc;
+  DBuf<int> err(al, 1);
+  HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+  h->rp.reset(al, n + 1);
+  h->ci.reset(al, A->nnz);
+  h->val.reset(al, A->nnz);
+  LAUNCH(h, "copy_in", k_rowptr_i32, blocks_for(n + 1, 256), 256, 0, n, A->row_ptr, h->rp.get(),
+         err.get());
+  HIPX(hipMemcpyAsync(h->ci, A->col_idx, A->nnz * sizeof(int), hipMemcpyDeviceToDevice,
+                      h->stream));
+  HIPX(hipMemcpyAsync(h->val, A->val, A->nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                      h->stream));
+  LAUNCH(h, "copy_in", k_cols_check, blocks_for(A->nnz, 256), 256, 0, A->nnz, (int)n, h->ci.get(),
+         err.get());
+  DBuf<int8_t> wb(al, n);
+  HIPX(hipMemcpyAsync(wb, G->wb_type, n, hipMemcpyDeviceToDevice, h->stream));
+  h->primal.reset(al, n);
+  HIPX(hipMemcpyAsync(h->primal, G->primal, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+  h->vertex.reset(al, h->nc);
+  LAUNCH(h, "copy_in", k_vertex_i32, blocks_for(h->nc, 256), 256, 0, (int64_t)h->nc, G->vertex,
+         h->vertex.get());
+  int e = 0;
+  int64_t last = 0;
+  HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipMemcpyAsync(&last, A->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(e == 0 && last == A->nnz, FAMS_ERR_INVALID_ARG, "malformed CSR");
+
+  build_ilu(h);                 // diagonal positions (+ ILU(0) factors)
+  build_prolongation(h, wb);    // P, R = P^T
+  const int nc = h->nc;
+  h->Ac.reset(al, static_cast<size_t>(nc) * nc);
+  build_coarse_operator(h, h->r_rp, h->r_ci, h->r_val, nc, h->Ac);
+  {
+    DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
+    HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
+                        h->stream));
+    h->Ainv.reset(al, static_cast<size_t>(nc) * nc);
+    lu_inverse(h, lu, h->Ainv, nc);
+    HIPX(hipStreamSynchronize(h->stream));
+  }
+  if (h->precision == FAMS_PREC_MIXED) {
+    h->val32.reset(al, h->nnz);
+    LAUNCH(h, "d2f", k_d2f_api, blocks_for(h->nnz, 256), 256, 0, h->nnz, h->val.get(),
+           h->val32.get());
+  }
+  HIPX(hipStreamSynchronize(h->stream));
+  h->info.n = n;
+  h->info.n_matrix = h->nm;
+  h->info.nnz = h->nnz;
+  h->info.n_coarse = nc;
+  h->info.ms_setup =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace fams
+
+using fams::Error;
+using fams::Handle;
+
+extern "C" {
+
+const char* fams_status_string(fams_status_t s) {
+  switch (s) {
+    case FAMS_OK: return "ok";
+    case FAMS_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case FAMS_DIVERGED: return "diverged";
+    case FAMS_ERR_INVALID_ARG: return "invalid argument";
+    case FAMS_ERR_BAD_GRID: return "inconsistent coarse grid";
+    case FAMS_ERR_SINGULAR_LOCAL: return "singular local (basis) problem";
+    case FAMS_ERR_SINGULAR_COARSE: return "singular coarse system";
+    case FAMS_ERR_ZERO_PIVOT_ILU: return "non-positive ILU(0) pivot";
+    case FAMS_ERR_OOM: return "out of device memory";
+    case FAMS_ERR_DEVICE: return "HIP runtime error";
+    case FAMS_ERR_CAPACITY: return "internal per-block capacity exceeded";
+  }
+  return "unknown status";
+}
+
+/* Last error message of the calling thread (diagnostics; not in fams.h). */
+const char* fams_last_error(void) { return fams::g_last_error.c_str(); }
+
+fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t precision,
+                             int32_t restart, size_t* bytes) {
+  if (!bytes || n <= 0 || nnz <= 0 || n_coarse <= 0) return FAMS_ERR_INVALID_ARG;
+  const double zp = 16.0 * n;  // nnz(P) bound used for admission (<= 16 per row)
+  double b = 0;
+  b += nnz * (4 + 8 + 8) + (n + 1) * 4 + n * (4 + 4 + 4);       // A, ILU, diag, primal
+  b += 2 * zp * (4 + 8) + (n + n_coarse + 2) * 4;                // P and R
+  b += 2.0 * 8 * n_coarse * n_coarse;                            // A_c and its inverse
+  b += 8.0 * n * (6 + 2 * std::max(restart, 1) + 1);             // iteration vectors
+  if (precision == FAMS_PREC_MIXED) b += nnz * 8.0 + 2 * zp * 4 + 16.0 * n;
+  b *= 1.10;
+  *bytes = static_cast<size_t>(b) + (64u << 20);
+  return FAMS_OK;
+}
+
+fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_setup_opts_t* o,
+                         const fams_allocator_t* allocator, void* stream, fams_handle_t* out) {
+  if (out) *out = nullptr;
+  if (!A || !G || !o || !out || !A->row_ptr || !A->col_idx || !A->val || !G->wb_type ||
+      !G->primal || !G->vertex)
+    return FAMS_ERR_INVALID_ARG;
+  if (A->n <= 0 || A->n >= (int64_t(1) << 31) || A->nnz < A->n || A->nnz >= (int64_t(1) << 31) ||
+      A->n_matrix < 0 || A->n_matrix > A->n || G->n_coarse <= 0 || G->n_coarse > A->n ||
+      G->n_coarse > 65536)
+    return FAMS_ERR_INVALID_ARG;
+  if (o->variant < 0 || o->variant > 3 || o->precision < 0 || o->precision > 1 ||
+      !(o->trunc_alpha >= 0.0 && o->trunc_alpha < 1.0) || o->merge_cap < 1)
+    return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    std::unique_ptr<fams_handle_s> h(new fams_handle_s());
+    h->stream = static_cast<hipStream_t>(stream);
+    h->alloc.stream = h->stream;
+    h->prof.stream = h->stream;
+    if (allocator && allocator->alloc && allocator->free) {
+      h->alloc.hook = *allocator;
+      h->alloc.has_hook = true;
+    }
+    h->variant = o->variant;
+    h->precision = o->precision;
+    h->alpha = o->trunc_alpha;
+    h->merge_cap = o->merge_cap;
+    h->smoother = o->smoother ? 1 : 0;
+    h->n = static_cast<int>(A->n);
+    h->nm = static_cast<int>(A->n_matrix);
+    h->nnz = A->nnz;
+    h->nc = static_cast<int>(G->n_coarse);
+    fams::setup_impl(h.get(), A, G);
+    h->info.device_bytes = h->alloc.live_bytes;
+    *out = h.release();
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nrhs,
+                         const fams_solve_opts_t* o, fams_info_t* info) {
+  if (!h || !q || !p || nrhs < 0 || !o) return FAMS_ERR_INVALID_ARG;
+  if (o->outer != FAMS_RICHARDSON && o->outer != FAMS_GMRES) return FAMS_ERR_INVALID_ARG;
+  if (o->outer == FAMS_GMRES && (o->restart < 1 || o->restart > 60)) return FAMS_ERR_INVALID_ARG;
+  if (!(o->rtol >= 0.0) || o->max_iter < 0) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    fams_status_t worst = FAMS_OK;
+    const int64_t n = h->n;
+    for (int r = 0; r < nrhs; ++r) {
+      const double* qr = q + r * n;
+      double* pr = p + r * n;
+      fams_info_t inf{};
+      double qq = fams::dev_dot(h, qr, qr, n);
+      if (!std::isfinite(qq)) {
+        inf.status = FAMS_ERR_INVALID_ARG;
+        if (info) info[r] = inf;
+        return FAMS_ERR_INVALID_ARG;
+      }
+      fams_status_t st = fams::solve_one(h, qr, pr, o, &inf);
+      if (info) info[r] = inf;
+      if (st > worst) worst = st;
+    }
+    return worst;
+  });
+}
+
+fams_status_t fams_reconstruct_flux(fams_handle_t h, const double* q, const double* p,
+                                    double* flux, double* p_fv, double* imbalance) {
+  if (!h || !q || !p || !flux) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    double imb = fams::reconstruct_flux(h, q, p, flux, p_fv);
+    if (imbalance) *imbalance = imb;
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_get_setup_info(fams_handle_t h, fams_setup_info_t* info) {
+  if (!h || !info) return FAMS_ERR_INVALID_ARG;
+  *info = h->info;
+  info->device_bytes = h->alloc.live_bytes;
+  return FAMS_OK;
+}
+
+fams_status_t fams_destroy(fams_handle_t h) {
+  if (!h) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_get_prolongation(fams_handle_t h, int64_t* nnz, int64_t* row_ptr, int32_t* col,
+                                    double* val) {
+  if (!h || !nnz) return FAMS_ERR_INVALID_ARG;
+  *nnz = h->p_nnz;
+  if (!row_ptr && !col && !val) return FAMS_OK;
+  return fams::guard([&]() -> fams_status_t {
+    std::vector<int> rp(h->n + 1);
+    HIPX(hipMemcpyAsync(rp.data(), h->p_rp.get(), (h->n + 1) * sizeof(int),
+                        hipMemcpyDeviceToHost, h->stream));
+    if (col)
+      HIPX(hipMemcpyAsync(col, h->p_ci.get(), h->p_nnz * sizeof(int), hipMemcpyDeviceToHost,
+                          h->stream));
+    if (val)
+      HIPX(hipMemcpyAsync(val, h->p_val.get(), h->p_nnz * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    if (row_ptr)
+      for (int i = 0; i <= h->n; ++i) row_ptr[i] = rp[i];
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_get_coarse_matrix(fams_handle_t h, double* ac) {
+  if (!h || !ac) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    HIPX(hipMemcpyAsync(ac, h->Ac.get(), sizeof(double) * h->nc * h->nc, hipMemcpyDeviceToHost,
+                        h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_get_ilu(fams_handle_t h, double* lu_val) {
+  if (!h || !lu_val || !h->smoother) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    HIPX(hipMemcpyAsync(lu_val, h->ilu.get(), sizeof(double) * h->nnz, hipMemcpyDeviceToHost,
+                        h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z) {
+  if (!h || !r || !z) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    fams::apply_stage_fp64(h, r, z);
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_set_profiling(fams_handle_t h, int32_t on) {
+  if (!h) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    h->prof.collect();
+    h->prof.on = on != 0;
+    if (on) h->prof.totals.clear();
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_get_kernel_stats(fams_handle_t h, int32_t max_entries, int32_t* n_entries,
+                                    const char** names, double* total_ms, int64_t* launches) {
+  if (!h || !n_entries) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    h->prof.collect();
+    h->prof.names_cache.clear();
+    for (auto& kv : h->prof.totals) h->prof.names_cache.push_back(kv.first);
+    int k = 0;
+    for (auto& kv : h->prof.totals) {
+      if (k >= max_entries) break;
+      if (names) names[k] = h->prof.names_cache[k].c_str();
+      if (total_ms) total_ms[k] = kv.second.first;
+      if (launches) launches[k] = kv.second.second;
+      ++k;
+    }
+    *n_entries = static_cast<int32_t>(h->prof.totals.size());
+    return FAMS_OK;
+  });
+}
+
+}  // extern "C"

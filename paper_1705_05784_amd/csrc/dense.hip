@@ -1,0 +1,321 @@
+// Setup, part 2, and the coarse solve of the iteration: the dense coarse
+// operator A_c = R A P (App. A, "(R A P)"; Table 1 step 5), its LU
+// factorisation with partial pivoting and its inverse, and y = A_c^{-1} x.
+//
+// The paper factors A_c with a direct LU (Sec. 4, PETSc).  Here the LU is a
+// blocked right-looking getrf on the GPU; the per-iteration coarse solve then
+// uses the explicit inverse (computed once from the LU factors by blocked
+// triangular solves), which turns two sequential triangular sweeps into one
+// bandwidth-bound, fully parallel matrix-vector product.
+//
+// All dense matrices are column-major with leading dimension n.
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace fams {
+namespace {
+
+constexpr int kNb = 32;  // panel width of the blocked LU
+
+// ---- A_c = R A P ------------------------------------------------------------
+// One wavefront per coarse row I: walk the row of R (fine rows i ascending),
+// the row of A, and the row of P; lanes own distinct coarse columns of one P
+// row, rows are walked sequentially, so every sum has a fixed order.
+__global__ void __launch_bounds__(64)
+k_rap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int* rp,
+      const int* ci, const double* av, const int* p_rp, const int* p_ci, const double* p_val,
+      double* out, int jt) {
+  extern __shared__ double acc[];
+  const int I = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int j0 = 0; j0 < nc; j0 += jt) {
+    const int j1 = min(nc, j0 + jt);
+    for (int t = lane; t < j1 - j0; t += 64) acc[t] = 0.0;
+    __syncthreads();
+    for (int e = R_rp[I]; e < R_rp[I + 1]; ++e) {
+      const int i = R_ci[e];
+      const double w = R_val ? R_val[e] : 1.0;
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        const double wa = w * av[p];
+        for (int q = p_rp[j] + lane; q < p_rp[j + 1]; q += 64) {
+          const int J = p_ci[q];
+          if (J >= j0 && J < j1) acc[J - j0] += wa * p_val[q];
+        }
+        __syncthreads();
+      }
+    }
+    for (int t = lane; t < j1 - j0; t += 64) out[static_cast<int64_t>(j0 + t) * nc + I] = acc[t];
+    __syncthreads();
+  }
+}
+
+// ---- LU with partial pivoting ----------------------------------------------
+// Panel [k0, k0+nb) of rows [k0, n): pivot = first row of maximal |a|.
+__global__ void __launch_bounds__(1024)
+k_panel(double* a, int n, int k0, int nb, int* ipiv, int* info) {
+  __shared__ double s_val[1024];
+  __shared__ int s_idx[1024];
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  for (int j = k0; j < k0 + nb; ++j) {
+    double* colj = a + static_cast<int64_t>(j) * n;
+    double best = -1.0;
+    int bi = n;
+    for (int r = j + tid; r < n; r += nt) {
+      double v = fabs(colj[r]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    s_val[tid] = best;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        double v2 = s_val[tid + s];
+        int i2 = s_idx[tid + s];
+        if (v2 > s_val[tid] || (v2 == s_val[tid] && i2 < s_idx[tid])) {
+          s_val[tid] = v2;
+          s_idx[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = s_idx[0];
+    const double pval = s_val[0];
+    __syncthreads();
+    if (tid == 0) {
+      ipiv[j] = piv;
+      if (!(pval > 0.0) && *info == 0) *info = j + 1;
+    }
+    if (piv != j) {
+      for (int c = k0 + tid; c < k0 + nb; c += nt) {
+        double* cc = a + static_cast<int64_t>(c) * n;
+        double t = cc[j];
+        cc[j] = cc[piv];
+        cc[piv] = t;
+      }
+    }
+    __syncthreads();
+    const double d = colj[j];
+    const double rd = d != 0.0 ? 1.0 / d : 0.0;
+    for (int r = j + 1 + tid; r < n; r += nt) colj[r] *= rd;
+    __syncthreads();
+    const int w = k0 + nb - (j + 1);
+    const int64_t rows = n - (j + 1);
+    for (int64_t idx = tid; idx < rows * w; idx += nt) {
+      int c = j + 1 + static_cast<int>(idx / rows);
+      int r = j + 1 + static_cast<int>(idx % rows);
+      double* cc = a + static_cast<int64_t>(c) * n;
+      cc[r] -= colj[r] * cc[j];
+    }
+    __syncthreads();
+  }
+}
+
+// apply the panel's row interchanges to the columns outside the panel
+__global__ void k_laswp(double* a, int n, int k0, int nb, const int* ipiv) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || (c >= k0 && c < k0 + nb)) return;
+  double* cc = a + static_cast<int64_t>(c) * n;
+  for (int j = k0; j < k0 + nb; ++j) {
+    int p = ipiv[j];
+    if (p != j) {
+      double t = cc[j];
+      cc[j] = cc[p];
+      cc[p] = t;
+    }
+  }
+}
+
+// B[k0:k0+nb, c] <- L11^{-1} B[...] (unit lower L11 at (k0, k0) of `l`), for
+// columns c in [c0, c1) of `b`; one thread per column
+__global__ void k_trsm_lower_unit(const double* l, int n, int k0, int nb, double* b, int c0,
+                                  int c1) {
+  __shared__ double L[kNb * kNb];
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    int r = t % nb, c = t / nb;
+    L[t] = l[static_cast<int64_t>(k0 + c) * n + k0 + r];
+  }
+  __syncthreads();
+  int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  double x[kNb];
+  double* col = b + static_cast<int64_t>(c) * n + k0;
+  for (int r = 0; r < nb; ++r) x[r] = col[r];
+  for (int r = 0; r < nb; ++r) {
+    double s = x[r];
+    for (int t = 0; t < r; ++t) s -= L[t * nb + r] * x[t];
+    x[r] = s;
+  }
+  for (int r = 0; r < nb; ++r) col[r] = x[r];
+}
+
+// B[k0:k0+nb, c] <- U11^{-1} B[...] (upper, non-unit U11 at (k0, k0) of `u`)
+__global__ void k_trsm_upper(const double* u, int n, int k0, int nb, double* b, int c0, int c1) {
+  __shared__ double U[kNb * kNb];
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    int r = t % nb, c = t / nb;
+    U[t] = u[static_cast<int64_t>(k0 + c) * n + k0 + r];
+  }
+  __syncthreads();
+  int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  double x[kNb];
+  double* col = b + static_cast<int64_t>(c) * n + k0;
+  for (int r = 0; r < nb; ++r) x[r] = col[r];
+  for (int r = nb - 1; r >= 0; --r) {
+    double s = x[r];
+    for (int t = r + 1; t < nb; ++t) s -= U[t * nb + r] * x[t];
+    x[r] = s / U[r * nb + r];
+  }
+  for (int r = 0; r < nb; ++r) col[r] = x[r];
+}
+
+// C[m x p] -= A[m x k] * B[k x p], column-major with leading dimension ld.
+// 64 x 64 tiles, 256 threads, 4 x 4 outputs per thread, k in steps of 16.
+__global__ void __launch_bounds__(256)
+k_gemm_sub(int m, int p, int k, const double* A, const double* B, double* C, int ld) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+      int kk = t / 64, r = t % 64;
+      int gr = row0 + r, gk = k0 + kk;
+      As[kk][r] = (gr < m && gk < k) ? A[static_cast<int64_t>(gk) * ld + gr] : 0.0;
+      int c = t % 64, kb = t / 64;
+      int gc = col0 + c, gk2 = k0 + kb;
+      Bs[kb][c] = (gc < p && gk2 < k) ? B[static_cast<int64_t>(gc) * ld + gk2] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = As[kk][tx + 16 * u];
+        bv[u] = Bs[kk][ty + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int r = row0 + tx + 16 * u, c = col0 + ty + 16 * v;
+      if (r < m && c < p) C[static_cast<int64_t>(c) * ld + r] -= acc[u][v];
+    }
+}
+
+__global__ void k_perm_identity(int n, const int* perm, double* x) {
+  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(n) * n) return;
+  int r = static_cast<int>(t % n), c = static_cast<int>(t / n);
+  x[t] = perm[r] == c ? 1.0 : 0.0;
+}
+
+// y = M x, M column-major n x n: partial sums over column chunks, then a
+// fixed-order reduction across chunks
+constexpr int kGemvChunk = 64;
+__global__ void k_gemv_part(int n, const double* M, const double* x, double* part) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int c0 = blockIdx.y * kGemvChunk;
+  if (I >= n) return;
+  int c1 = min(n, c0 + kGemvChunk);
+  double s = 0.0;
+  for (int c = c0; c < c1; ++c) s += M[static_cast<int64_t>(c) * n + I] * x[c];
+  part[static_cast<int64_t>(blockIdx.y) * n + I] = s;
+}
+
+__global__ void k_gemv_reduce(int n, int nchunks, const double* part, double* y) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += part[static_cast<int64_t>(c) * n + I];
+  y[I] = s;
+}
+
+void gemm_sub(Handle* h, int m, int p, int k, const double* A, const double* B, double* C,
+              int ld) {
+  if (m <= 0 || p <= 0 || k <= 0) return;
+  dim3 grid(blocks_for(m, 64), blocks_for(p, 64));
+  LAUNCH(h, "gemm_f64", k_gemm_sub, grid, 256, 0, m, p, k, A, B, C, ld);
+}
+
+}  // namespace
+
+void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const double* R_val,
+                           int rows, double* out) {
+  const int nc = h->nc;
+  const int jt = std::min(nc, 4096);
+  LAUNCH(h, "rap", k_rap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val, h->rp.get(),
+         h->ci.get(), h->val.get(), h->p_rp.get(), h->p_ci.get(), h->p_val.get(), out, jt);
+}
+
+// LU of `a` (n x n, overwritten) and inv = A^{-1}
+void lu_inverse(Handle* h, double* a, double* inv, int n) {
+  DBuf<int> ipiv(&h->alloc, n), info(&h->alloc, 1);
+  HIPX(hipMemsetAsync(info, 0, sizeof(int), h->stream));
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    int nb = std::min(kNb, n - k0);
+    LAUNCH(h, "lu_panel", k_panel, 1, 1024, 0, a, n, k0, nb, ipiv.get(), info.get());
+    LAUNCH(h, "lu_laswp", k_laswp, blocks_for(n, 256), 256, 0, a, n, k0, nb, ipiv.get());
+    int c0 = k0 + nb;
+    if (c0 < n) {
+      LAUNCH(h, "lu_trsm", k_trsm_lower_unit, blocks_for(n - c0, 64), 64, 0, a, n, k0, nb, a, c0,
+             n);
+      gemm_sub(h, n - c0, n - c0, nb, a + static_cast<int64_t>(k0) * n + c0,
+               a + static_cast<int64_t>(c0) * n + k0, a + static_cast<int64_t>(c0) * n + c0, n);
+    }
+  }
+  int hinfo = 0;
+  std::vector<int> hp(n);
+  HIPX(hipMemcpyAsync(&hinfo, info.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipMemcpyAsync(hp.data(), ipiv.get(), n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(hinfo == 0, FAMS_ERR_SINGULAR_COARSE, "zero pivot in the coarse LU");
+  // P A = L U  =>  A^{-1} = U^{-1} L^{-1} P
+  std::vector<int> perm(n);
+  for (int r = 0; r < n; ++r) perm[r] = r;
+  for (int j = 0; j < n; ++j) std::swap(perm[j], perm[hp[j]]);
+  DBuf<int> dperm(&h->alloc, n);
+  HIPX(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  LAUNCH(h, "perm_identity", k_perm_identity, blocks_for(static_cast<int64_t>(n) * n, 256), 256, 0,
+         n, dperm.get(), inv);
+  for (int k0 = 0; k0 < n; k0 += kNb) {  // L Y = P
+    int nb = std::min(kNb, n - k0);
+    LAUNCH(h, "inv_trsm_l", k_trsm_lower_unit, blocks_for(n, 64), 64, 0, a, n, k0, nb, inv, 0, n);
+    int r0 = k0 + nb;
+    if (r0 < n)
+      gemm_sub(h, n - r0, n, nb, a + static_cast<int64_t>(k0) * n + r0, inv + k0, inv + r0, n);
+  }
+  for (int k0 = ((n - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {  // U X = Y
+    int nb = std::min(kNb, n - k0);
+    LAUNCH(h, "inv_trsm_u", k_trsm_upper, blocks_for(n, 64), 64, 0, a, n, k0, nb, inv, 0, n);
+    if (k0 > 0) gemm_sub(h, k0, n, nb, a + static_cast<int64_t>(k0) * n, inv + k0, inv, n);
+  }
+}
+
+// part: [ceil(nc / 64) * nc] partial sums
+void coarse_apply(Handle* h, const double* inv, int nc, const double* x, double* y,
+                  double* part) {
+  static_assert(kGemvChunk == 64, "partial buffer is sized for 64-column chunks");
+  int nch = (nc + kGemvChunk - 1) / kGemvChunk;
+  dim3 grid(blocks_for(nc, 256), nch);
+  LAUNCH(h, "coarse_gemv", k_gemv_part, grid, 256, 0, nc, inv, x, part);
+  LAUNCH(h, "coarse_gemv_red", k_gemv_reduce, blocks_for(nc, 256), 256, 0, nc, nch, part, y);
+}
+
+}  // namespace fams

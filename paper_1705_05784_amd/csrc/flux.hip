@@ -1,0 +1,331 @@
+// Conservative fine-scale flux reconstruction (Sec. 3.2: after any stage with
+// the finite-volume restriction R^FV a mass-conservative flux field can be
+// reconstructed; Sec. 4.5).  The paper gives no algorithm; this is the
+// standard multiscale finite-volume reconstruction:
+//
+//  1. FV stage: A_FV = R^FV A P (dense; R^FV sums the cells of a primal
+//     block), x = A_FV^{-1} R^FV (q - A p) with two steps of iterative
+//     refinement, p' = p + P x: every primal block then conserves mass.
+//  2. One Neumann problem per primal block K (one workgroup each, banded
+//     LDL^T): fluxes across K's boundary from p', inside from p''
+//         sum_{j in K} T_ij (p''_i - p''_j) + s_i p''_i
+//             = q_i - sum_{j not in K} T_ij (p'_i - p'_j),     T_ij = -A_ij,
+//     s_i = sum_j A_ij.  If no cell of K has s_i > 0 the problem is singular
+//     but compatible and p'' is pinned to p' at K's coarse node.
+//  3. F_ij = T_ij (p''_i - p''_j) inside a block, T_ij (p'_i - p'_j) across;
+//     E_i = s_i p''_i - q_i in the diagonal slot; sum_j F_ij + E_i = 0.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "band.hpp"
+#include "internal.hpp"
+
+namespace fams {
+namespace {
+
+constexpr int kT = 256;
+constexpr double kSingularRowsum = 1e-10;  // s_i <= this * max A_ii counts as zero
+constexpr int kLdsDoubles = 6144;
+
+__global__ void k_rowsum_diag(int n, const int* rp, const int* ci, const double* av, double* s,
+                              double* dmax_part) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double dmax = 0.0;
+  if (i < n) {
+    double t = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      t += av[p];
+      if (ci[p] == i) dmax = av[p];
+    }
+    s[i] = t;
+  }
+  __shared__ double red[kT];
+  red[threadIdx.x] = dmax;
+  __syncthreads();
+  for (int k = kT / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dmax_part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_reduce(int m, const double* part, double* out) {
+  __shared__ double red[kT];
+  double v = 0.0;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) v = fmax(v, part[k]);
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = kT / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_iota_f(int n, int* v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+__global__ void k_block_ptr(int n, int nb, const int* key_sorted, int* ptr) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int k = key_sorted[t];
+  if (t == 0 || key_sorted[t - 1] != k) ptr[k] = t;
+  if (t == n - 1) ptr[nb] = n;
+}
+
+__global__ void k_block_local(int n, const int* cells, const int* primal, const int* ptr,
+                              int* local) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) local[cells[t]] = t - ptr[primal[cells[t]]];
+}
+
+// per primal block: bandwidth of its within-block couplings and whether the
+// local Neumann problem is singular (no cell with a positive row sum)
+__global__ void k_fv_symbolic(const int* ptr, const int* cells, const int* rp, const int* ci,
+                              const int* primal, const int* local, const double* s,
+                              const double* dmax, int* band, int* singular) {
+  __shared__ int s_b, s_pos;
+  int K = blockIdx.x;
+  if (threadIdx.x == 0) {
+    s_b = 0;
+    s_pos = 0;
+  }
+  __syncthreads();
+  int beg = ptr[K], n = ptr[K + 1] - beg;
+  double thr = kSingularRowsum * *dmax;
+  int bm = 0, pos = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    if (s[i] > thr) pos = 1;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      if (j != i && primal[j] == K) bm = max(bm, abs(local[j] - l));
+    }
+  }
+  atomicMax(&s_b, bm);
+  atomicOr(&s_pos, pos);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    band[K] = s_b;
+    singular[K] = s_pos ? 0 : 1;
+  }
+}
+
+__global__ void k_block_sum(int nb, const int* ptr, const int* cells, const double* r,
+                            double* out) {
+  int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nb) return;
+  double t = 0.0;
+  for (int k = ptr[K]; k < ptr[K + 1]; ++k) t += r[cells[k]];
+  out[K] = t;
+}
+
+__global__ void k_sub(int n, const double* a, const double* b, double* y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] - b[i];
+}
+
+__global__ void k_add_to(int n, const double* a, double* y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a[i];
+}
+
+__global__ void k_resid_f(int n, const int* rp, const int* ci, const double* av, const double* x,
+                          const double* b, double* y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = b[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p) t -= av[p] * x[ci[p]];
+  y[i] = t;
+}
+
+__global__ void k_prolong_add(int n, const int* prp, const int* pci, const double* pv,
+                              const double* x, const double* p, double* y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int q = prp[i]; q < prp[i + 1]; ++q) t += pv[q] * x[pci[q]];
+  y[i] = p[i] + t;
+}
+
+__global__ void __launch_bounds__(kT)
+k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const double* av,
+          const int* primal, const int* local, const int* vertex, const int* band,
+          const int* singular, const int64_t* band_off, double* band_glob, int lds_elems,
+          const double* q, const double* p1, double* xs, double* p2, int* err) {
+  extern __shared__ double lds[];
+  int K = blockIdx.x;
+  int beg = ptr[K], n = ptr[K + 1] - beg;
+  int b = band[K], w = b + 1;
+  int64_t bsz = static_cast<int64_t>(n) * w;
+  double* B = bsz <= lds_elems ? lds : band_glob + band_off[K];
+  double* X = xs + beg;
+  const bool pin = singular[K] != 0;
+  const int lv = pin ? local[vertex[K]] : -1;
+  const double pv = pin ? p1[vertex[K]] : 0.0;
+  for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = 0.0;
+  __syncthreads();
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    double dg = 0.0, rhs = q[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      double a = av[p];
+      if (j == i) {
+        dg += a;
+      } else if (primal[j] == K) {
+        int lj = local[j];
+        if (pin && lj == lv) rhs -= a * pv;           // pinned value moves to the RHS
+        else if (lj < l && l != lv) B[static_cast<int64_t>(l) * w + b - (l - lj)] = a;
+      } else {
+        dg += a;
+        rhs += a * (p1[i] - p1[j]);
+      }
+    }
+    if (l == lv) {
+      dg = 1.0;
+      rhs = pv;
+    }
+    B[static_cast<int64_t>(l) * w + b] = dg;
+    X[l] = rhs;
+  }
+  __syncthreads();
+  bool bad = band_ldlt_solve<double>(B, n, b, X, 1);
+  for (int l = threadIdx.x; l < n; l += blockDim.x) p2[cells[beg + l]] = X[l];
+  if (bad && threadIdx.x == 0) atomicOr(err, 1);
+}
+
+__global__ void k_flux(int n, const int* rp, const int* ci, const double* av, const int* primal,
+                       const double* p1, const double* p2, const double* q, const double* s,
+                       double* flux, double* bal_part, double* scale_part) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double bal = 0.0, sc = 0.0;
+  if (i < n) {
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      double f;
+      if (j == i) f = s[i] * p2[i] - q[i];
+      else if (primal[i] == primal[j]) f = -av[p] * (p2[i] - p2[j]);
+      else f = -av[p] * (p1[i] - p1[j]);
+      flux[p] = f;
+      bal += f;
+      sc += fabs(f);
+    }
+  }
+  __shared__ double rb[kT], rs[kT];
+  rb[threadIdx.x] = fabs(bal);
+  rs[threadIdx.x] = sc;
+  __syncthreads();
+  for (int k = kT / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      rb[threadIdx.x] = fmax(rb[threadIdx.x], rb[threadIdx.x + k]);
+      rs[threadIdx.x] = fmax(rs[threadIdx.x], rs[threadIdx.x + k]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bal_part[blockIdx.x] = rb[0];
+    scale_part[blockIdx.x] = rs[0];
+  }
+}
+
+}  // namespace
+
+double reconstruct_flux(Handle* h, const double* q, const double* p, double* flux,
+                        double* p_fv) {
+  const int n = h->n, nc = h->nc;
+  Allocator* A = &h->alloc;
+  const unsigned g = blocks_for(n, kT);
+  ensure_workspace(h, 1);
+  // ---- lazy FV setup (kept in the handle) ----
+  DBuf<double> s(A, n), dpart(A, g), dmax(A, 1);
+  LAUNCH(h, "flux_rowsum", k_rowsum_diag, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(),
+         s.get(), dpart.get());
+  LAUNCH(h, "flux_max", k_max_reduce, 1, kT, 0, (int)g, dpart.get(), dmax.get());
+  DBuf<int> local(A, n), band(A, nc), singular(A, nc);
+  if (!h->fv_ready) {
+    DBuf<int> keys(A, n), iota(A, n);
+    h->fv_order.reset(A, n);
+    h->fv_ptr.reset(A, nc + 1);
+    LAUNCH(h, "flux_iota", k_iota_f, g, kT, 0, n, iota.get());
+    int bits = 1;
+    while ((int64_t(1) << bits) <= nc) ++bits;
+    sort_pairs_i32(h, h->primal, keys, iota, h->fv_order, n, bits);
+    LAUNCH(h, "flux_block_ptr", k_block_ptr, g, kT, 0, n, nc, keys.get(), h->fv_ptr.get());
+    h->Afv.reset(A, static_cast<size_t>(nc) * nc);
+    build_coarse_operator(h, h->fv_ptr, h->fv_order, nullptr, nc, h->Afv);
+    DBuf<double> lu(A, static_cast<size_t>(nc) * nc);
+    HIPX(hipMemcpyAsync(lu, h->Afv.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
+                        h->stream));
+    h->Afv_inv.reset(A, static_cast<size_t>(nc) * nc);
+    lu_inverse(h, lu, h->Afv_inv, nc);
+    HIPX(hipStreamSynchronize(h->stream));
+    h->fv_ready = true;
+  }
+  LAUNCH(h, "flux_block_local", k_block_local, g, kT, 0, n, h->fv_order.get(), h->primal.get(),
+         h->fv_ptr.get(), local.get());
+  LAUNCH(h, "flux_symbolic", k_fv_symbolic, nc, kT, 0, h->fv_ptr.get(), h->fv_order.get(),
+         h->rp.get(), h->ci.get(), h->primal.get(), local.get(), s.get(), dmax.get(), band.get(),
+         singular.get());
+  std::vector<int> hb(nc), hp(nc + 1);
+  HIPX(hipMemcpyAsync(hb.data(), band.get(), nc * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipMemcpyAsync(hp.data(), h->fv_ptr.get(), (nc + 1) * sizeof(int), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+
+  // ---- FV stage ----
+  DBuf<double> r(A, n), rc(A, nc), x(A, nc), t(A, nc), t2(A, nc), p1(A, n), p2(A, n), xs(A, n);
+  LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(), p, q,
+         r.get());
+  LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
+         h->fv_order.get(), r.get(), rc.get());
+  coarse_apply(h, h->Afv_inv, nc, rc, x, h->gpart);
+  for (int it = 0; it < 2; ++it) {  // iterative refinement of the coarse solve
+    coarse_apply(h, h->Afv, nc, x, t, h->gpart);
+    LAUNCH(h, "flux_sub", k_sub, blocks_for(nc, kT), kT, 0, nc, rc.get(), t.get(), t.get());
+    coarse_apply(h, h->Afv_inv, nc, t, t2, h->gpart);
+    LAUNCH(h, "flux_add", k_add_to, blocks_for(nc, kT), kT, 0, nc, t2.get(), x.get());
+  }
+  LAUNCH(h, "flux_prolong", k_prolong_add, g, kT, 0, n, h->p_rp.get(), h->p_ci.get(),
+         h->p_val.get(), x.get(), p, p1.get());
+
+  // ---- Neumann problems per primal block ----
+  std::vector<int64_t> off(nc, 0);
+  int64_t total = 0, lds_need = 0;
+  for (int K = 0; K < nc; ++K) {
+    int64_t sz = static_cast<int64_t>(hp[K + 1] - hp[K]) * (hb[K] + 1);
+    off[K] = total;
+    if (sz <= kLdsDoubles) lds_need = std::max(lds_need, sz);
+    else total += sz;
+  }
+  DBuf<int64_t> d_off(A, nc);
+  HIPX(hipMemcpyAsync(d_off, off.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+  DBuf<double> scratch(A, std::max<int64_t>(total, 1));
+  DBuf<int> err(A, 1);
+  HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+  LAUNCH(h, "flux_neumann", k_neumann, nc, kT, lds_need * sizeof(double), h->fv_ptr.get(),
+         h->fv_order.get(), h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(),
+         h->vertex.get(), band.get(), singular.get(), d_off.get(), scratch.get(),
+         static_cast<int>(lds_need), q, p1.get(), xs.get(), p2.get(), err.get());
+
+  // ---- fluxes and balance ----
+  DBuf<double> bpart(A, g), spart(A, g), mx(A, 2);
+  LAUNCH(h, "flux_eval", k_flux, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(),
+         h->primal.get(), p1.get(), p2.get(), q, s.get(), flux, bpart.get(), spart.get());
+  LAUNCH(h, "flux_max", k_max_reduce, 1, kT, 0, (int)g, bpart.get(), mx.get());
+  LAUNCH(h, "flux_max", k_max_reduce, 1, kT, 0, (int)g, spart.get(), mx.get() + 1);
+  if (p_fv)
+    HIPX(hipMemcpyAsync(p_fv, p1.get(), n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  double hm[2];
+  int he = 0;
+  HIPX(hipMemcpyAsync(hm, mx.get(), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipMemcpyAsync(&he, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(he == 0, FAMS_ERR_SINGULAR_LOCAL, "non-positive pivot in a block Neumann problem");
+  return hm[1] > 0 ? hm[0] / hm[1] : 0.0;
+}
+
+}  // namespace fams

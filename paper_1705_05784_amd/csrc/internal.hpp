@@ -1,0 +1,216 @@
+// Internal declarations of the F-AMS library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fams.h"
+
+namespace fams {
+
+// ---- errors: thrown inside the library, converted to a status at the ABI --
+struct Error : std::runtime_error {
+  fams_status_t status;
+  Error(fams_status_t s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] void hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define HIPX(call)                                                   \
+  do {                                                               \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) ::fams::hip_fail(e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define FAMS_REQUIRE(cond, status, msg)                              \
+  do {                                                               \
+    if (!(cond)) throw ::fams::Error((status), (msg));               \
+  } while (0)
+
+// ---- device memory ---------------------------------------------------------
+struct Allocator {
+  fams_allocator_t hook{};
+  bool has_hook = false;
+  hipStream_t stream = nullptr;
+  int64_t live_bytes = 0;
+  int64_t peak_bytes = 0;
+  void* alloc(size_t bytes);
+  void release(void* p, size_t bytes);
+};
+
+template <class T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(Allocator* a, size_t n) { reset(a, n); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { swap(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      free();
+      swap(o);
+    }
+    return *this;
+  }
+  ~DBuf() { free(); }
+  void reset(Allocator* a, size_t n) {
+    free();
+    a_ = a;
+    n_ = n;
+    p_ = n ? static_cast<T*>(a->alloc(n * sizeof(T))) : nullptr;
+  }
+  void free() {
+    if (p_ && a_) a_->release(p_, n_ * sizeof(T));
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  operator T*() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  void swap(DBuf& o) {
+    std::swap(a_, o.a_);
+    std::swap(p_, o.p_);
+    std::swap(n_, o.n_);
+  }
+  Allocator* a_ = nullptr;
+  T* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// ---- per-kernel profiling with HIP events ----------------------------------
+struct Prof {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<double, int64_t>> totals;
+  std::vector<std::string> names_cache;
+  int begin(const char* name);
+  void end(int token);
+  void collect();  // synchronises the stream, folds pending events into totals
+  ~Prof();
+};
+
+#define LAUNCH(H, NAME, KERNEL, GRID, BLOCK, SHMEM, ...)                          \
+  do {                                                                            \
+    int tok_ = (H)->prof.begin(NAME);                                             \
+    hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), SHMEM, (H)->stream, __VA_ARGS__); \
+    HIPX(hipGetLastError());                                                      \
+    (H)->prof.end(tok_);                                                          \
+  } while (0)
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+// ---- level-scheduled triangular structure ---------------------------------
+struct Levels {
+  std::vector<int> ptr;  // host: row ranges per level in `rows`
+  DBuf<int> rows;        // device: rows grouped by level, ascending within level
+  int count() const { return ptr.empty() ? 0 : static_cast<int>(ptr.size()) - 1; }
+};
+
+// ---- the handle ------------------------------------------------------------
+struct Handle {
+  Allocator alloc;
+  hipStream_t stream = nullptr;
+  Prof prof;
+
+  // options
+  int variant = FAMS_DECOUPLED;
+  int precision = FAMS_PREC_FP64;
+  double alpha = 0.0;
+  int64_t merge_cap = 4096;
+  int smoother = 1;
+
+  // sizes
+  int n = 0, nm = 0, nc = 0;
+  int64_t nnz = 0;
+
+  // fine system (int32 indices)
+  DBuf<int> rp, ci, diag;
+  DBuf<double> val;
+  DBuf<float> val32;
+  DBuf<int> primal, vertex;
+
+  // prolongation / restriction (CSR)
+  int64_t p_nnz = 0;
+  DBuf<int> p_rp, p_ci, r_rp, r_ci;
+  DBuf<double> p_val, r_val;
+  DBuf<float> p_val32, r_val32;
+
+  // coarse system: dense column-major A_c and its inverse
+  DBuf<double> Ac, Ainv;
+
+  // ILU(0): factors in A's slots, level schedules of the two sweeps
+  DBuf<double> ilu;
+  DBuf<float> ilu32;
+  Levels lvl_lo, lvl_up;
+
+  // finite-volume stage (built lazily by fams_reconstruct_flux)
+  bool fv_ready = false;
+  DBuf<double> Afv, Afv_inv;
+  DBuf<int> fv_order, fv_ptr;  // cells grouped by primal block
+  int fv_max_block = 0;
+
+  // scratch of the iteration
+  DBuf<double> wk;      // FP64 work vectors
+  DBuf<float> wk32;     // FP32 work vectors (MIXED)
+  DBuf<double> red;     // reduction partials
+  DBuf<double> hred;    // small host-readable results
+  DBuf<double> gpart;   // partial sums of the coarse matrix-vector product
+  size_t wk_vectors = 0;
+
+  fams_setup_info_t info{};
+};
+
+// ---- launchers implemented in the .hip files --------------------------------
+// prims.hip (rocPRIM)
+void sort_pairs_i32(Handle* h, const int* keys_in, int* keys_out, const int* vals_in,
+                    int* vals_out, int64_t n, int key_bits);
+void exclusive_scan_i32(Handle* h, const int* in, int* out, int64_t n);
+void exclusive_scan_i64(Handle* h, const int64_t* in, int64_t* out, int64_t n);
+
+// setup.hip
+void build_prolongation(Handle* h, const int8_t* wb);
+// dense.hip
+void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const double* R_val,
+                           int rows, double* out);
+void lu_inverse(Handle* h, double* a, double* inv, int n);
+void coarse_apply(Handle* h, const double* inv, int nc, const double* x, double* y, double* part);
+// ilu.hip
+void build_ilu(Handle* h);
+template <class T>
+void ilu_apply(Handle* h, const T* lu, const T* b, T* x);
+// solve.hip
+fams_status_t solve_one(Handle* h, const double* q, double* p, const fams_solve_opts_t* o,
+                        fams_info_t* info);
+void apply_stage_fp64(Handle* h, const double* r, double* z);
+void ensure_workspace(Handle* h, int restart);
+// flux.hip
+double reconstruct_flux(Handle* h, const double* q, const double* p, double* flux,
+                        double* p_fv);
+
+// small helpers (solve.hip)
+double dev_dot(Handle* h, const double* a, const double* b, int64_t n);
+void dev_copy_d(Handle* h, double* dst, const double* src, int64_t n);
+
+}  // namespace fams
+
+// the opaque handle of the C ABI is the library's Handle
+struct fams_handle_s : fams::Handle {};

@@ -1,0 +1,949 @@
+// Setup, part 1: the F-AMS prolongation P and restriction R = P^T on the GPU.
+//
+// One rule covers the four coupling strategies of App. A (Decoupled, Frac,
+// Rock, Coupled-AMS): every cell has a rank rho (its wirebasket class
+// I=0 < F=1 < E=2 < V=3, lifted by 4 for the medium solved first in Frac- and
+// Rock-AMS); in a non-vertex row a coupling is
+//   lumped  when cut (cross-media in Decoupled-AMS, or between unmerged
+//           same-class blocks in Coupled-AMS) or when rho(j) < rho(i) -- the
+//           localisation assumption, with the entry moved to the diagonal
+//           (the over/underlined blocks of App. A);
+//   RHS     when rho(j) > rho(i): -A_ij P_j, higher-rank rows of P acting as
+//           boundary data (App. A.1, last paragraph);
+//   kept    when rho(j) = rho(i) and not cut.
+// Local blocks = connected components of the kept couplings (dual edges,
+// faces, interiors; merged across media in Coupled-AMS).  Blocks are solved
+// level by level from the highest rank down, each by one workgroup with a
+// banded LDL^T factorisation (the local matrices are symmetric M-matrices),
+// many right-hand sides at once -- one per coarse column the block touches.
+//
+// Determinism: every ordering is fixed (stable sorts, per-thread sequential
+// sums in CSR order), so repeated setups are bitwise identical.
+#include <algorithm>
+#include <climits>
+#include <numeric>
+#include <type_traits>
+
+#include "band.hpp"
+#include "internal.hpp"
+
+namespace fams {
+namespace {
+
+enum : int8_t { C_NONE = 0, C_KEPT = 1, C_LUMPED = 2, C_RHS = 3 };
+
+constexpr int kThreads = 256;
+constexpr int kMaxSources = 2048;   // distinct higher-rank neighbour blocks per block
+constexpr int kMaxCand = 8192;      // candidate coarse columns before de-duplication
+constexpr int kMaxCols = 2048;      // coarse columns per block (RHS count)
+constexpr int kLdsBandDoubles = 6144;  // band kept in LDS up to 48 KiB
+
+enum ErrBits : int {
+  E_VERTEX_RANGE = 1, E_VERTEX_CLASS = 2, E_VERTEX_DUP = 4, E_V_NOT_LISTED = 8,
+  E_CLASS_RANGE = 16, E_FRAC_INTERIOR = 32, E_PRIMAL_RANGE = 64,
+  E_NO_HIGHER = 128, E_PIVOT = 256, E_SOURCES = 512, E_CAND = 1024, E_COLS = 2048,
+};
+
+__device__ __forceinline__ int rank_of(int wb, int i, int nm, int variant) {
+  bool frac = i >= nm;
+  if (variant == FAMS_FRAC) return wb + (frac ? 4 : 0);
+  if (variant == FAMS_ROCK) return wb + (frac ? 0 : 4);
+  return wb;
+}
+
+__global__ void k_validate(int n, int nm, int nc, const int8_t* wb, const int* primal,
+                           const int64_t* vertex, int* coarse_of, int8_t* rho, int variant,
+                           int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) {
+    int64_t v = vertex[i];
+    if (v < 0 || v >= n) {
+      atomicOr(err, E_VERTEX_RANGE);
+    } else {
+      if (wb[v] != 3) atomicOr(err, E_VERTEX_CLASS);
+      if (atomicCAS(&coarse_of[v], -1, i) != -1) atomicOr(err, E_VERTEX_DUP);
+    }
+  }
+  if (i < n) {
+    int w = wb[i];
+    if (w < 0 || w > 3) atomicOr(err, E_CLASS_RANGE);
+    if (i >= nm && w == 0) atomicOr(err, E_FRAC_INTERIOR);
+    if (primal[i] < 0 || primal[i] >= nc) atomicOr(err, E_PRIMAL_RANGE);
+    rho[i] = static_cast<int8_t>(rank_of(w, i, nm, variant));
+  }
+}
+
+__global__ void k_check_vertices(int n, const int8_t* wb, const int* coarse_of, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && wb[i] == 3 && coarse_of[i] < 0) atomicOr(err, E_V_NOT_LISTED);
+}
+
+// Class of every stored entry.  `mode` = the variant whose rule is applied;
+// `group` (Coupled only) = merged block label of each cell.
+__global__ void k_classify(int n, int nm, const int* rp, const int* ci, const int8_t* wb,
+                           const int8_t* rho, int mode, const int* group, int8_t* ecls) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool vi = wb[i] == 3;
+  bool fi = i >= nm;
+  int ri = rho[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    int j = ci[p];
+    int8_t c = C_NONE;
+    if (!vi && j != i) {
+      bool cross = fi != (j >= nm);
+      bool cut = false;
+      if (mode == FAMS_DECOUPLED) cut = cross;
+      else if (mode == FAMS_COUPLED) cut = cross && wb[i] == wb[j] && group[i] != group[j];
+      int rj = rho[j];
+      if (cut || rj < ri) c = C_LUMPED;
+      else if (rj > ri) c = C_RHS;
+      else c = C_KEPT;
+    }
+    ecls[p] = c;
+  }
+}
+
+__global__ void k_label_init(int n, const int8_t* wb, int* label) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) label[i] = wb[i] == 3 ? -1 : i;
+}
+
+// hook: pull the smallest label over kept neighbours, and hook the old root
+__global__ void k_label_hook(int n, const int* rp, const int* ci, const int8_t* ecls, int* label,
+                             int* changed) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int li = label[i];
+  if (li < 0) return;
+  int m = li;
+  for (int p = rp[i]; p < rp[i + 1]; ++p)
+    if (ecls[p] == C_KEPT) m = min(m, label[ci[p]]);
+  if (m < li) {
+    atomicMin(&label[li], m);
+    atomicMin(&label[i], m);
+    *changed = 1;
+  }
+}
+
+// compress: follow the label chain (strictly decreasing) to its root
+__global__ void k_label_jump(int n, int* label) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int l = label[i];
+  if (l < 0) return;
+  while (true) {
+    int nl = label[l];
+    if (nl == l) break;
+    l = nl;
+  }
+  label[i] = l;
+}
+
+// Coupled-AMS: cross-media couplings between non-vertex cells of one class, i < j
+__global__ void k_cross_count(int n, int nm, const int* rp, const int* ci, const int8_t* wb,
+                              int* cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  if (wb[i] != 3) {
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      if (j > i && wb[j] == wb[i] && ((i >= nm) != (j >= nm))) ++c;
+    }
+  }
+  cnt[i] = c;
+}
+
+__global__ void k_cross_fill(int n, int nm, const int* rp, const int* ci, const int8_t* wb,
+                             const int* off, int* pairs) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || wb[i] == 3) return;
+  int o = off[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    int j = ci[p];
+    if (j > i && wb[j] == wb[i] && ((i >= nm) != (j >= nm))) {
+      pairs[2 * o] = i;
+      pairs[2 * o + 1] = j;
+      ++o;
+    }
+  }
+}
+
+__global__ void k_root_flags(int n, const int* label, int* flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = label[i] == i ? 1 : 0;
+}
+
+__global__ void k_root_keys(int n, const int* label, const int8_t* rho, const int* pos, int* keys,
+                            int* vals) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && label[i] == i) {
+    keys[pos[i]] = 7 - rho[i];
+    vals[pos[i]] = i;
+  }
+}
+
+__global__ void k_comp_index(int ncomp, const int* root_sorted, int* croot) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ncomp) croot[root_sorted[k]] = k;
+}
+
+__global__ void k_comp_of(int n, const int* label, const int* croot, int* comp_of, int* flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int l = label[i];
+  comp_of[i] = l < 0 ? -1 : croot[l];
+  flag[i] = l < 0 ? 0 : 1;
+}
+
+__global__ void k_cell_keys(int n, const int* comp_of, const int* pos, int* keys, int* vals) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && comp_of[i] >= 0) {
+    keys[pos[i]] = comp_of[i];
+    vals[pos[i]] = i;
+  }
+}
+
+__global__ void k_comp_ptr(int m, int ncomp, const int* key_sorted, const int* cells,
+                           int* comp_ptr, int* local_idx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  int k = key_sorted[t];
+  if (t == 0 || key_sorted[t - 1] != k) comp_ptr[k] = t;
+  if (t == m - 1) comp_ptr[ncomp] = m;
+  (void)cells;
+}
+
+__global__ void k_local_idx(int m, const int* key_sorted, const int* cells, const int* comp_ptr,
+                            int* local_idx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) local_idx[cells[t]] = t - comp_ptr[key_sorted[t]];
+}
+
+// ---- block-wide helpers (256 threads) ---------------------------------------
+__device__ void block_bitonic_sort(int* a, int cnt) {
+  int m = 1;
+  while (m < cnt) m <<= 1;
+  for (int t = cnt + threadIdx.x; t < m; t += blockDim.x) a[t] = INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        int u = t ^ j;
+        if (u > t) {
+          bool up = (t & k) == 0;
+          int x = a[t], y = a[u];
+          if ((x > y) == up) {
+            a[t] = y;
+            a[u] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// de-duplicate a sorted LDS array in place; returns the unique count
+__device__ int block_unique(int* a, int cnt, int* scratch /* blockDim+1 */) {
+  int per = (cnt + blockDim.x - 1) / blockDim.x;
+  int lo = threadIdx.x * per, hi = min(cnt, lo + per);
+  int mine = 0;
+  for (int t = lo; t < hi; ++t)
+    if (t == 0 || a[t] != a[t - 1]) ++mine;
+  scratch[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      int v = scratch[t];
+      scratch[t] = s;
+      s += v;
+    }
+    scratch[blockDim.x] = s;
+  }
+  __syncthreads();
+  int o = scratch[threadIdx.x];
+  // values to keep, collected before any write (in-place compaction is safe
+  // because output positions never exceed input positions, but other threads
+  // may still read a[t-1] -- so stage through registers chunk by chunk)
+  int vals[32];
+  int nv = 0;
+  int total = scratch[blockDim.x];
+  __syncthreads();
+  for (int t = lo; t < hi; ++t) {
+    if (t == 0 || a[t] != a[t - 1]) {
+      if (nv < 32) vals[nv] = a[t];
+      ++nv;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < nv && k < 32; ++k) a[o + k] = vals[k];
+  __syncthreads();
+  return total;
+}
+
+__device__ __forceinline__ int bsearch_i32(const int* a, int n, int key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Symbolic pass of one rank level: the coarse columns each block's
+// right-hand side touches (union over its higher-rank neighbours' columns),
+// and the block's bandwidth in its local (ascending cell) order.
+__global__ void __launch_bounds__(kThreads)
+k_colset(int c0, const int* comp_ptr, const int* cells, const int* rp, const int* ci,
+         const int8_t* ecls, const int8_t* wb, const int* coarse_of, const int* comp_of,
+         const int* local_idx, const int64_t* col_ptr, const int* cols, int* tmp_cols,
+         int* ncols_out, int* band_out, int* err) {
+  __shared__ int src[kMaxSources];
+  __shared__ int cand[kMaxCand];
+  __shared__ int scratch[kThreads + 1];
+  __shared__ int s_cnt, s_band, s_over;
+  int K = c0 + blockIdx.x;
+  int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
+  if (threadIdx.x == 0) {
+    s_cnt = 0;
+    s_band = 0;
+    s_over = 0;
+  }
+  __syncthreads();
+  int bmax = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int8_t c = ecls[p];
+      int j = ci[p];
+      if (c == C_KEPT) {
+        bmax = max(bmax, abs(local_idx[j] - l));
+      } else if (c == C_RHS) {
+        int s = wb[j] == 3 ? -(coarse_of[j] + 1) : comp_of[j];
+        int k = atomicAdd(&s_cnt, 1);
+        if (k < kMaxSources) src[k] = s;
+      }
+    }
+  }
+  atomicMax(&s_band, bmax);
+  __syncthreads();
+  int nsrc = s_cnt;
+  if (nsrc > kMaxSources) {
+    if (threadIdx.x == 0) atomicOr(err, E_SOURCES);
+    return;
+  }
+  block_bitonic_sort(src, nsrc);
+  nsrc = block_unique(src, nsrc, scratch);
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nsrc; t += blockDim.x) {
+    int s = src[t];
+    if (s < 0) {
+      int k = atomicAdd(&s_cnt, 1);
+      if (k < kMaxCand) cand[k] = -s - 1;
+    } else {
+      int64_t a = col_ptr[s], b = col_ptr[s + 1];
+      int k = atomicAdd(&s_cnt, static_cast<int>(b - a));
+      for (int64_t q = a; q < b; ++q, ++k)
+        if (k < kMaxCand) cand[k] = cols[q];
+    }
+  }
+  __syncthreads();
+  int ncand = s_cnt;
+  if (ncand > kMaxCand) {
+    if (threadIdx.x == 0) atomicOr(err, E_CAND);
+    return;
+  }
+  block_bitonic_sort(cand, ncand);
+  int nu = block_unique(cand, ncand, scratch);
+  if (nu > kMaxCols) {
+    if (threadIdx.x == 0) atomicOr(err, E_COLS);
+    return;
+  }
+  if (nu == 0 && threadIdx.x == 0) atomicOr(err, E_NO_HIGHER);
+  int* out = tmp_cols + static_cast<int64_t>(blockIdx.x) * kMaxCols;
+  for (int t = threadIdx.x; t < nu; t += blockDim.x) out[t] = cand[t];
+  if (threadIdx.x == 0) {
+    ncols_out[K] = nu;
+    band_out[K] = s_band;
+  }
+}
+
+__global__ void k_colcopy(int c0, int ncomp_level, const int* tmp_cols, const int64_t* col_ptr,
+                          int* cols) {
+  int K = c0 + blockIdx.x;
+  int64_t a = col_ptr[K], b = col_ptr[K + 1];
+  const int* src = tmp_cols + static_cast<int64_t>(blockIdx.x) * kMaxCols;
+  for (int64_t t = threadIdx.x; t < b - a; t += blockDim.x) cols[a + t] = src[t];
+  (void)ncomp_level;
+}
+
+// Numeric pass of one rank level: assemble A'_KK (band) and B_K, factor
+// A'_KK = L D L^T (L unit lower, stored unscaled as L*D), solve for all
+// right-hand sides.  TS = storage type of the P value pool, TC = arithmetic
+// type.  With TS == TC the solution overwrites B_K in the pool; otherwise it
+// is computed in `xwork` and rounded into the pool.  `list` (optional)
+// selects the blocks: block = list[blockIdx.x], else c0 + blockIdx.x.
+template <class TS, class TC>
+__global__ void __launch_bounds__(kThreads)
+k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, const int* rp,
+              const int* ci, const double* av, const int8_t* ecls, const int8_t* wb,
+              const int* coarse_of, const int* comp_of, const int* local_idx,
+              const int64_t* col_ptr, const int* cols, const int* ncols, const int* band,
+              const int64_t* pval_off, TS* pvals, const int64_t* work_off, TC* band_glob,
+              TC* xwork, int lds_elems, int* err, int* bad_block) {
+  extern __shared__ double lds_d[];
+  int slot = blockIdx.x;
+  int K = list ? list[slot] : c0 + slot;
+  int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
+  int b = band[K], w = b + 1;
+  int nck = ncols[K];
+  const int* kcols = cols + col_ptr[K];
+  TC* X;
+  if constexpr (std::is_same<TS, TC>::value) X = xwork ? xwork + work_off[2 * slot + 1] : pvals + pval_off[K];
+  else X = xwork + work_off[2 * slot + 1];
+  int64_t bsz = static_cast<int64_t>(n) * w;
+  TC* B = (bsz <= lds_elems) ? reinterpret_cast<TC*>(lds_d) : band_glob + work_off[2 * slot];
+
+  for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = TC(0);
+  __syncthreads();
+  // assemble: one thread per block row, entries in CSR order
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    TC* xl = X + static_cast<int64_t>(l) * nck;
+    for (int c = 0; c < nck; ++c) xl[c] = TC(0);
+    double dg = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      double a = av[p];
+      int8_t c = ecls[p];
+      if (j == i) {
+        dg += a;
+      } else if (c == C_LUMPED) {
+        dg += a;
+      } else if (c == C_KEPT) {
+        int lj = local_idx[j];
+        if (lj < l) B[static_cast<int64_t>(l) * w + b - (l - lj)] = static_cast<TC>(a);
+      } else if (c == C_RHS) {
+        if (wb[j] == 3) {
+          int pos = bsearch_i32(kcols, nck, coarse_of[j]);
+          xl[pos] -= static_cast<TC>(a);
+        } else {
+          int cj = comp_of[j];
+          int ncj = ncols[cj];
+          const TS* src = pvals + pval_off[cj] + static_cast<int64_t>(local_idx[j]) * ncj;
+          const int* cc = cols + col_ptr[cj];
+          for (int t = 0; t < ncj; ++t) {
+            int pos = bsearch_i32(kcols, nck, cc[t]);
+            xl[pos] -= static_cast<TC>(a) * static_cast<TC>(src[t]);
+          }
+        }
+      }
+    }
+    B[static_cast<int64_t>(l) * w + b] = static_cast<TC>(dg);
+  }
+  __syncthreads();
+  bool bad = band_ldlt_solve<TC>(B, n, b, X, nck);
+  if (!std::is_same<TS, TC>::value || xwork) {
+    TS* out = pvals + pval_off[K];
+    for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x)
+      out[t] = static_cast<TS>(X[t]);
+  }
+  if (bad && threadIdx.x == 0) {
+    atomicOr(err, E_PIVOT);
+    if (bad_block) bad_block[K] = 1;
+  }
+}
+
+// ---- P in CSR (with the optional truncation of Sec. 4.3) -------------------
+template <class T>
+__global__ void k_p_count(int n, const int8_t* wb, const int* comp_of, const int* local_idx,
+                          const int* ncols, const int64_t* pval_off, const T* pvals, double alpha,
+                          int* cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (wb[i] == 3) {
+    cnt[i] = 1;
+    return;
+  }
+  int K = comp_of[i];
+  int nck = ncols[K];
+  if (alpha <= 0.0) {
+    cnt[i] = nck;
+    return;
+  }
+  const T* v = pvals + pval_off[K] + static_cast<int64_t>(local_idx[i]) * nck;
+  int c = 0;
+  for (int t = 0; t < nck; ++t)
+    if (fabs(static_cast<double>(v[t])) >= alpha) ++c;
+  cnt[i] = c ? c : 1;
+}
+
+template <class T>
+__global__ void k_p_fill(int n, const int8_t* wb, const int* coarse_of, const int* comp_of,
+                         const int* local_idx, const int* ncols, const int64_t* col_ptr,
+                         const int* cols, const int64_t* pval_off, const T* pvals, double alpha,
+                         const int* p_rp, int* p_ci, double* p_val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = p_rp[i];
+  if (wb[i] == 3) {
+    p_ci[o] = coarse_of[i];
+    p_val[o] = 1.0;
+    return;
+  }
+  int K = comp_of[i];
+  int nck = ncols[K];
+  const T* v = pvals + pval_off[K] + static_cast<int64_t>(local_idx[i]) * nck;
+  const int* cc = cols + col_ptr[K];
+  int kept = p_rp[i + 1] - o;
+  if (alpha <= 0.0 || kept == nck) {
+    bool all = true;
+    if (alpha > 0.0)
+      for (int t = 0; t < nck; ++t) all = all && fabs(static_cast<double>(v[t])) >= alpha;
+    if (all) {
+      for (int t = 0; t < nck; ++t) {
+        p_ci[o + t] = cc[t];
+        p_val[o + t] = static_cast<double>(v[t]);
+      }
+      return;
+    }
+  }
+  double s0 = 0.0, s1 = 0.0;
+  int nk = 0;
+  for (int t = 0; t < nck; ++t) {
+    double x = static_cast<double>(v[t]);
+    s0 += x;
+    if (fabs(x) >= alpha) {
+      s1 += x;
+      ++nk;
+    }
+  }
+  if (nk == 0) {  // keep the largest entry (lowest column on ties)
+    int best = 0;
+    for (int t = 1; t < nck; ++t)
+      if (fabs(static_cast<double>(v[t])) > fabs(static_cast<double>(v[best]))) best = t;
+    double x = static_cast<double>(v[best]);
+    p_ci[o] = cc[best];
+    p_val[o] = s0 != 0.0 && x != 0.0 ? x * (s0 / x) : x;
+    return;
+  }
+  double scale = s1 != 0.0 ? s0 / s1 : 1.0;
+  for (int t = 0; t < nck; ++t) {
+    double x = static_cast<double>(v[t]);
+    if (fabs(x) >= alpha) {
+      p_ci[o] = cc[t];
+      p_val[o] = x * scale;
+      ++o;
+    }
+  }
+}
+
+__global__ void k_entry_rows(int n, const int* rp, int* erow, int* iota) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    erow[p] = i;
+    iota[p] = p;
+  }
+}
+
+__global__ void k_r_fill(int64_t nnz, int nc, const int* key_sorted, const int* perm,
+                         const int* erow, const double* p_val, int* r_rp, int* r_ci,
+                         double* r_val) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  int e = perm[k];
+  r_ci[k] = erow[e];
+  r_val[k] = p_val[e];
+  int J = key_sorted[k];
+  int Jprev = k == 0 ? -1 : key_sorted[k - 1];
+  for (int c = Jprev + 1; c <= J; ++c) r_rp[c] = static_cast<int>(k);
+  if (k == nnz - 1)
+    for (int c = J + 1; c <= nc; ++c) r_rp[c] = static_cast<int>(nnz);
+}
+
+__global__ void k_d2f(int64_t n, const double* a, float* b) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<float>(a[i]);
+}
+
+int bits_for(int64_t v) {
+  int b = 1;
+  while ((int64_t(1) << b) <= v) ++b;
+  return b;
+}
+
+template <class T>
+int64_t read1(Handle* h, const T* dev) {
+  T v{};
+  HIPX(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  return static_cast<int64_t>(v);
+}
+
+std::string grid_error_text(int e) {
+  std::string s = "grid:";
+  if (e & E_VERTEX_RANGE) s += " vertex index out of range;";
+  if (e & E_VERTEX_CLASS) s += " a listed vertex is not of class V;";
+  if (e & E_VERTEX_DUP) s += " a cell listed twice as vertex;";
+  if (e & E_V_NOT_LISTED) s += " a class-V cell missing from the vertex list;";
+  if (e & E_CLASS_RANGE) s += " wirebasket class outside 0..3;";
+  if (e & E_FRAC_INTERIOR) s += " fracture cell of class I;";
+  if (e & E_PRIMAL_RANGE) s += " primal id out of range;";
+  return s;
+}
+
+// connected components of the kept couplings (hook and compress)
+void components(Handle* h, const int8_t* wb, const int8_t* ecls, int* label) {
+  int n = h->n;
+  unsigned g = blocks_for(n, kThreads);
+  LAUNCH(h, "label_init", k_label_init, g, kThreads, 0, n, wb, label);
+  DBuf<int> changed(&h->alloc, 1);
+  for (int it = 0; it < 100000; ++it) {
+    HIPX(hipMemsetAsync(changed, 0, sizeof(int), h->stream));
+    LAUNCH(h, "label_hook", k_label_hook, g, kThreads, 0, n, h->rp.get(), h->ci.get(), ecls, label,
+           changed.get());
+    LAUNCH(h, "label_jump", k_label_jump, g, kThreads, 0, n, label);
+    if (!read1(h, changed.get())) return;
+  }
+  throw Error(FAMS_ERR_DEVICE, "component labelling did not converge");
+}
+
+// Coupled-AMS merge of same-class blocks across media, in CSR order, under
+// the merge cap (host union-find over the short list of cross couplings)
+void coupled_groups(Handle* h, const int8_t* wb, const int* base, int* group) {
+  int n = h->n, nm = h->nm;
+  unsigned g = blocks_for(n, kThreads);
+  DBuf<int> cnt(&h->alloc, n), off(&h->alloc, n);
+  LAUNCH(h, "cross_count", k_cross_count, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+         cnt.get());
+  exclusive_scan_i32(h, cnt, off, n);
+  int64_t m = read1(h, off.get() + n - 1) + read1(h, cnt.get() + n - 1);
+  std::vector<int> hb(n), pairs(2 * m);
+  if (m) {
+    DBuf<int> dp(&h->alloc, 2 * m);
+    LAUNCH(h, "cross_fill", k_cross_fill, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+           off.get(), dp.get());
+    HIPX(hipMemcpyAsync(pairs.data(), dp.get(), 2 * m * sizeof(int), hipMemcpyDeviceToHost,
+                        h->stream));
+  }
+  HIPX(hipMemcpyAsync(hb.data(), base, n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  std::vector<int> parent(n), size(n, 0);
+  std::iota(parent.begin(), parent.end(), 0);
+  for (int i = 0; i < n; ++i)
+    if (hb[i] >= 0) ++size[hb[i]];
+  auto find = [&](int a) {
+    while (parent[a] != a) {
+      parent[a] = parent[parent[a]];
+      a = parent[a];
+    }
+    return a;
+  };
+  for (int64_t e = 0; e < m; ++e) {
+    int a = find(hb[pairs[2 * e]]), b = find(hb[pairs[2 * e + 1]]);
+    if (a == b) continue;
+    if (static_cast<int64_t>(size[a]) + size[b] <= h->merge_cap) {
+      int lo = std::min(a, b), hi = std::max(a, b);
+      parent[hi] = lo;
+      size[lo] += size[hi];
+    }
+  }
+  for (int i = 0; i < n; ++i) hb[i] = hb[i] >= 0 ? find(hb[i]) : -1;
+  HIPX(hipMemcpyAsync(group, hb.data(), n * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
+// Launch the local solves of blocks `blocks` (all of one rank level).
+template <class TS, class TC>
+void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, const int* comp_ptr,
+                  const int* cells, const int8_t* ecls, const int8_t* wb, const int* coarse_of,
+                  const int* comp_of, const int* local_idx, const int64_t* col_ptr,
+                  const int* cols, const int* ncols, const int* band, const int64_t* pval_off,
+                  TS* pvals, const std::vector<int>& h_comp_ptr, const std::vector<int>& h_band,
+                  const std::vector<int>& h_ncols, int* err, int* bad_block) {
+  int nb = static_cast<int>(blocks.size());
+  if (nb == 0) return;
+  const bool separate_x = !std::is_same<TS, TC>::value;
+  std::vector<int64_t> off(2 * nb, 0);
+  int64_t band_total = 0, x_total = 0, lds_need = 0;
+  const int lds_cap = kLdsBandDoubles * 8 / static_cast<int>(sizeof(TC));
+  for (int k = 0; k < nb; ++k) {
+    int K = blocks[k];
+    int64_t nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
+    int64_t sz = nk * (h_band[K] + 1);
+    off[2 * k] = band_total;
+    if (sz <= lds_cap) lds_need = std::max(lds_need, sz);
+    else band_total += sz;
+    off[2 * k + 1] = x_total;
+    if (separate_x) x_total += nk * h_ncols[K];
+  }
+  DBuf<int64_t> d_off(&h->alloc, 2 * nb);
+  HIPX(hipMemcpyAsync(d_off, off.data(), 2 * nb * sizeof(int64_t), hipMemcpyHostToDevice,
+                      h->stream));
+  DBuf<int> d_list;
+  if (use_list) {
+    d_list.reset(&h->alloc, nb);
+    HIPX(hipMemcpyAsync(d_list, blocks.data(), nb * sizeof(int), hipMemcpyHostToDevice,
+                        h->stream));
+  }
+  DBuf<TC> scratch(&h->alloc, std::max<int64_t>(band_total, 1));
+  DBuf<TC> xw;
+  if (separate_x) xw.reset(&h->alloc, std::max<int64_t>(x_total, 1));
+  int lds_elems = static_cast<int>(lds_need);
+  LAUNCH(h, "local_solve", (k_local_solve<TS, TC>), nb, kThreads, lds_elems * sizeof(TC),
+         static_cast<const int*>(d_list.get()), blocks[0], comp_ptr, cells, h->rp.get(),
+         h->ci.get(), h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols,
+         ncols, band, pval_off, pvals, d_off.get(), scratch.get(), xw.get(), lds_elems, err,
+         bad_block);
+  HIPX(hipStreamSynchronize(h->stream));  // scratch is freed on return
+}
+
+}  // namespace
+
+void build_prolongation(Handle* h, const int8_t* wb) {
+  const int n = h->n, nm = h->nm, nc = h->nc;
+  unsigned g = blocks_for(n, kThreads);
+  Allocator* A = &h->alloc;
+
+  DBuf<int> coarse_of(A, n), err(A, 1);
+  DBuf<int8_t> rho(A, n), ecls(A, h->nnz);
+  HIPX(hipMemsetAsync(coarse_of, 0xff, n * sizeof(int), h->stream));
+  HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+  // the validate kernel reads vertex as int64 from the handle's int copy
+  DBuf<int64_t> vtx64(A, nc);
+  {
+    std::vector<int> hv(nc);
+    HIPX(hipMemcpyAsync(hv.data(), h->vertex.get(), nc * sizeof(int), hipMemcpyDeviceToHost,
+                        h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    std::vector<int64_t> hv64(hv.begin(), hv.end());
+    HIPX(hipMemcpyAsync(vtx64, hv64.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice,
+                        h->stream));
+  }
+  LAUNCH(h, "validate", k_validate, blocks_for(std::max(n, nc), kThreads), kThreads, 0, n, nm, nc,
+         wb, h->primal.get(), vtx64.get(), coarse_of.get(), rho.get(), h->variant, err.get());
+  LAUNCH(h, "check_vertices", k_check_vertices, g, kThreads, 0, n, wb, coarse_of.get(), err.get());
+  int e = static_cast<int>(read1(h, err.get()));
+  FAMS_REQUIRE(e == 0, FAMS_ERR_BAD_GRID, grid_error_text(e));
+
+  // entry classes and local blocks
+  DBuf<int> label(A, n);
+  if (h->variant == FAMS_COUPLED) {
+    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+           rho.get(), static_cast<int>(FAMS_DECOUPLED), static_cast<const int*>(nullptr),
+           ecls.get());
+    DBuf<int> base(A, n);
+    components(h, wb, ecls, base);
+    coupled_groups(h, wb, base, label);
+    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+           rho.get(), static_cast<int>(FAMS_COUPLED), static_cast<const int*>(label.get()),
+           ecls.get());
+  } else {
+    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+           rho.get(), h->variant, static_cast<const int*>(nullptr), ecls.get());
+    components(h, wb, ecls, label);
+  }
+
+  // blocks in level order (rank descending, then ascending root cell)
+  DBuf<int> flag(A, n), pos(A, n);
+  LAUNCH(h, "root_flags", k_root_flags, g, kThreads, 0, n, label.get(), flag.get());
+  exclusive_scan_i32(h, flag, pos, n);
+  const int ncomp = static_cast<int>(read1(h, pos.get() + n - 1) + read1(h, flag.get() + n - 1));
+  FAMS_REQUIRE(ncomp > 0 || n == nc, FAMS_ERR_BAD_GRID, "no non-vertex cells");
+  DBuf<int> ck(A, std::max(ncomp, 1)), cv(A, std::max(ncomp, 1)), cks(A, std::max(ncomp, 1)),
+      cvs(A, std::max(ncomp, 1)), croot(A, n);
+  LAUNCH(h, "root_keys", k_root_keys, g, kThreads, 0, n, label.get(), rho.get(), pos.get(),
+         ck.get(), cv.get());
+  sort_pairs_i32(h, ck, cks, cv, cvs, ncomp, 3);
+  LAUNCH(h, "comp_index", k_comp_index, blocks_for(ncomp, kThreads), kThreads, 0, ncomp, cvs.get(),
+         croot.get());
+  DBuf<int> comp_of(A, n);
+  LAUNCH(h, "comp_of", k_comp_of, g, kThreads, 0, n, label.get(), croot.get(), comp_of.get(),
+         flag.get());
+  exclusive_scan_i32(h, flag, pos, n);
+  const int m = n - nc;  // non-vertex cells
+  DBuf<int> kk(A, std::max(m, 1)), kv(A, std::max(m, 1)), kks(A, std::max(m, 1)),
+      cells(A, std::max(m, 1));
+  LAUNCH(h, "cell_keys", k_cell_keys, g, kThreads, 0, n, comp_of.get(), pos.get(), kk.get(),
+         kv.get());
+  sort_pairs_i32(h, kk, kks, kv, cells, m, bits_for(ncomp));
+  DBuf<int> comp_ptr(A, ncomp + 1), local_idx(A, n);
+  if (m) {
+    LAUNCH(h, "comp_ptr", k_comp_ptr, blocks_for(m, kThreads), kThreads, 0, m, ncomp, kks.get(),
+           cells.get(), comp_ptr.get(), local_idx.get());
+    LAUNCH(h, "local_idx", k_local_idx, blocks_for(m, kThreads), kThreads, 0, m, kks.get(),
+           cells.get(), comp_ptr.get(), local_idx.get());
+  }
+  std::vector<int> h_cks(ncomp), h_comp_ptr(ncomp + 1, 0);
+  if (ncomp) {
+    HIPX(hipMemcpyAsync(h_cks.data(), cks.get(), ncomp * sizeof(int), hipMemcpyDeviceToHost,
+                        h->stream));
+    HIPX(hipMemcpyAsync(h_comp_ptr.data(), comp_ptr.get(), (ncomp + 1) * sizeof(int),
+                        hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPX(hipStreamSynchronize(h->stream));
+  // level ranges (key = 7 - rank)
+  std::vector<std::pair<int, int>> levels;
+  for (int k = 0; k < ncomp;) {
+    int e2 = k;
+    while (e2 < ncomp && h_cks[e2] == h_cks[k]) ++e2;
+    levels.emplace_back(k, e2);
+    k = e2;
+  }
+  int max_block = 0;
+  for (int k = 0; k < ncomp; ++k) max_block = std::max(max_block, h_comp_ptr[k + 1] - h_comp_ptr[k]);
+  h->info.n_blocks = ncomp;
+  h->info.max_block = max_block;
+
+  // symbolic: coarse columns per block, level by level
+  DBuf<int> ncols(A, std::max(ncomp, 1)), band(A, std::max(ncomp, 1));
+  DBuf<int64_t> col_ptr(A, ncomp + 1);
+  std::vector<int64_t> h_col_ptr(ncomp + 1, 0);
+  std::vector<int> h_ncols(ncomp, 0), h_band(ncomp, 0);
+  DBuf<int> cols(A, 1);
+  int64_t cols_size = 0;
+  HIPX(hipMemsetAsync(col_ptr, 0, (ncomp + 1) * sizeof(int64_t), h->stream));
+  for (auto [c0, c1] : levels) {
+    int nl = c1 - c0;
+    DBuf<int> tmp(A, static_cast<size_t>(nl) * kMaxCols);
+    LAUNCH(h, "colset", k_colset, nl, kThreads, 0, c0, comp_ptr.get(), cells.get(), h->rp.get(),
+           h->ci.get(), ecls.get(), wb, coarse_of.get(), comp_of.get(), local_idx.get(),
+           col_ptr.get(), cols.get(), tmp.get(), ncols.get(), band.get(), err.get());
+    HIPX(hipMemcpyAsync(h_ncols.data() + c0, ncols.get() + c0, nl * sizeof(int),
+                        hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipMemcpyAsync(h_band.data() + c0, band.get() + c0, nl * sizeof(int),
+                        hipMemcpyDeviceToHost, h->stream));
+    int ev = static_cast<int>(read1(h, err.get()));
+    FAMS_REQUIRE(!(ev & E_NO_HIGHER), FAMS_ERR_SINGULAR_LOCAL,
+                 "a local block has no higher-rank neighbour");
+    FAMS_REQUIRE(!(ev & (E_SOURCES | E_CAND | E_COLS)), FAMS_ERR_CAPACITY,
+                 "a local block touches too many coarse columns");
+    for (int K = c0; K < c1; ++K) h_col_ptr[K + 1] = h_col_ptr[K] + h_ncols[K];
+    int64_t new_size = h_col_ptr[c1];
+    DBuf<int> grown(A, std::max<int64_t>(new_size, 1));
+    if (cols_size)
+      HIPX(hipMemcpyAsync(grown, cols.get(), cols_size * sizeof(int), hipMemcpyDeviceToDevice,
+                          h->stream));
+    HIPX(hipMemcpyAsync(col_ptr.get() + c0 + 1, h_col_ptr.data() + c0 + 1, nl * sizeof(int64_t),
+                        hipMemcpyHostToDevice, h->stream));
+    LAUNCH(h, "colcopy", k_colcopy, nl, kThreads, 0, c0, nl, tmp.get(), col_ptr.get(),
+           grown.get());
+    HIPX(hipStreamSynchronize(h->stream));
+    cols = std::move(grown);
+    cols_size = new_size;
+  }
+
+  // numeric: solve the blocks level by level
+  std::vector<int64_t> h_pval_off(ncomp + 1, 0);
+  for (int K = 0; K < ncomp; ++K)
+    h_pval_off[K + 1] =
+        h_pval_off[K] + static_cast<int64_t>(h_comp_ptr[K + 1] - h_comp_ptr[K]) * h_ncols[K];
+  DBuf<int64_t> pval_off(A, ncomp + 1);
+  HIPX(hipMemcpyAsync(pval_off, h_pval_off.data(), (ncomp + 1) * sizeof(int64_t),
+                      hipMemcpyHostToDevice, h->stream));
+  const bool mixed = h->precision == FAMS_PREC_MIXED;
+  DBuf<double> pv64;
+  DBuf<float> pv32;
+  DBuf<int> bad_block;
+  if (mixed) {
+    pv32.reset(A, std::max<int64_t>(h_pval_off[ncomp], 1));
+    bad_block.reset(A, std::max(ncomp, 1));
+    HIPX(hipMemsetAsync(bad_block, 0, std::max(ncomp, 1) * sizeof(int), h->stream));
+  } else {
+    pv64.reset(A, std::max<int64_t>(h_pval_off[ncomp], 1));
+  }
+  int64_t fallbacks = 0;
+  for (auto [c0, c1] : levels) {
+    HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+    std::vector<int> blocks(c1 - c0);
+    std::iota(blocks.begin(), blocks.end(), c0);
+    if (mixed) {
+      local_solves<float, float>(h, blocks, false, comp_ptr, cells, ecls, wb, coarse_of, comp_of,
+                                 local_idx, col_ptr, cols, ncols, band, pval_off, pv32.get(),
+                                 h_comp_ptr, h_band, h_ncols, err, bad_block);
+    } else {
+      local_solves<double, double>(h, blocks, false, comp_ptr, cells, ecls, wb, coarse_of,
+                                   comp_of, local_idx, col_ptr, cols, ncols, band, pval_off,
+                                   pv64.get(), h_comp_ptr, h_band, h_ncols, err, nullptr);
+    }
+    int ev = static_cast<int>(read1(h, err.get()));
+    if ((ev & E_PIVOT) && mixed) {
+      // FP32 breakdown: re-solve the affected blocks of this level in FP64
+      std::vector<int> hb(c1 - c0);
+      HIPX(hipMemcpyAsync(hb.data(), bad_block.get() + c0, (c1 - c0) * sizeof(int),
+                          hipMemcpyDeviceToHost, h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+      std::vector<int> redo;
+      for (int k = 0; k < c1 - c0; ++k)
+        if (hb[k]) redo.push_back(c0 + k);
+      fallbacks += static_cast<int64_t>(redo.size());
+      HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+      local_solves<float, double>(h, redo, true, comp_ptr, cells, ecls, wb, coarse_of, comp_of,
+                                  local_idx, col_ptr, cols, ncols, band, pval_off, pv32.get(),
+                                  h_comp_ptr, h_band, h_ncols, err, nullptr);
+      ev = static_cast<int>(read1(h, err.get()));
+    }
+    FAMS_REQUIRE(!(ev & E_PIVOT), FAMS_ERR_SINGULAR_LOCAL, "non-positive pivot in a local block");
+  }
+  h->info.fp32_fallback_blocks = fallbacks;
+
+  // P as CSR (truncated), then R = P^T by a stable sort on the column
+  DBuf<int> cnt(A, n);
+  h->p_rp.reset(A, n + 1);
+  if (mixed)
+    LAUNCH(h, "p_count", k_p_count<float>, g, kThreads, 0, n, wb, comp_of.get(), local_idx.get(),
+           ncols.get(), pval_off.get(), static_cast<const float*>(pv32.get()), h->alpha,
+           cnt.get());
+  else
+    LAUNCH(h, "p_count", k_p_count<double>, g, kThreads, 0, n, wb, comp_of.get(), local_idx.get(),
+           ncols.get(), pval_off.get(), static_cast<const double*>(pv64.get()), h->alpha,
+           cnt.get());
+  exclusive_scan_i32(h, cnt, h->p_rp, n);
+  int64_t pnnz = read1(h, h->p_rp.get() + n - 1) + read1(h, cnt.get() + n - 1);
+  FAMS_REQUIRE(pnnz < (int64_t(1) << 31), FAMS_ERR_CAPACITY, "nnz(P) >= 2^31");
+  {
+    int v = static_cast<int>(pnnz);
+    HIPX(hipMemcpyAsync(h->p_rp.get() + n, &v, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+  }
+  h->p_nnz = pnnz;
+  h->p_ci.reset(A, pnnz);
+  h->p_val.reset(A, pnnz);
+  if (mixed)
+    LAUNCH(h, "p_fill", k_p_fill<float>, g, kThreads, 0, n, wb, coarse_of.get(), comp_of.get(),
+           local_idx.get(), ncols.get(), col_ptr.get(), cols.get(), pval_off.get(),
+           static_cast<const float*>(pv32.get()), h->alpha, h->p_rp.get(), h->p_ci.get(),
+           h->p_val.get());
+  else
+    LAUNCH(h, "p_fill", k_p_fill<double>, g, kThreads, 0, n, wb, coarse_of.get(), comp_of.get(),
+           local_idx.get(), ncols.get(), col_ptr.get(), cols.get(), pval_off.get(),
+           static_cast<const double*>(pv64.get()), h->alpha, h->p_rp.get(), h->p_ci.get(),
+           h->p_val.get());
+  h->info.nnz_P = pnnz;
+
+  DBuf<int> erow(A, pnnz), iota(A, pnnz), keys(A, pnnz), perm(A, pnnz);
+  LAUNCH(h, "entry_rows", k_entry_rows, g, kThreads, 0, n, h->p_rp.get(), erow.get(), iota.get());
+  sort_pairs_i32(h, h->p_ci, keys, iota, perm, pnnz, bits_for(nc));
+  h->r_rp.reset(A, nc + 1);
+  h->r_ci.reset(A, pnnz);
+  h->r_val.reset(A, pnnz);
+  LAUNCH(h, "r_fill", k_r_fill, blocks_for(pnnz, kThreads), kThreads, 0, pnnz, nc, keys.get(),
+         perm.get(), erow.get(), h->p_val.get(), h->r_rp.get(), h->r_ci.get(), h->r_val.get());
+  if (mixed) {
+    h->p_val32.reset(A, pnnz);
+    h->r_val32.reset(A, pnnz);
+    LAUNCH(h, "d2f", k_d2f, blocks_for(pnnz, kThreads), kThreads, 0, pnnz, h->p_val.get(),
+           h->p_val32.get());
+    LAUNCH(h, "d2f", k_d2f, blocks_for(pnnz, kThreads), kThreads, 0, pnnz, h->r_val.get(),
+           h->r_val32.get());
+  }
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
+}  // namespace fams

@@ -1,0 +1,311 @@
+"""Python binding of libfams.so (include/fams.h): argument marshalling only.
+
+Device arrays are torch tensors on the current HIP device; the library runs
+on torch's current stream.  Every computation happens inside libfams.so; if
+the library is missing this module raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfams.so")
+
+DECOUPLED, FRAC, ROCK, COUPLED = 0, 1, 2, 3
+VARIANTS = {"decoupled": DECOUPLED, "frac": FRAC, "rock": ROCK, "coupled": COUPLED}
+FP64, MIXED = 0, 1
+RICHARDSON, GMRES = 0, 1
+OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
+
+
+class FamsError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        msg = f"{where}: {status_string(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class CSR(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_matrix", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_coarse", C.c_int64), ("wb_type", C.c_void_p), ("primal", C.c_void_p),
+                ("vertex", C.c_void_p)]
+
+
+class SetupOpts(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("precision", C.c_int32), ("trunc_alpha", C.c_double),
+                ("merge_cap", C.c_int64), ("smoother", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("outer", C.c_int32), ("restart", C.c_int32), ("rtol", C.c_double),
+                ("max_iter", C.c_int32), ("use_initial_guess", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_residual", C.c_double),
+                ("ms", C.c_double)]
+
+
+class SetupInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_matrix", C.c_int64), ("nnz", C.c_int64),
+                ("n_coarse", C.c_int64), ("nnz_P", C.c_int64), ("n_blocks", C.c_int64),
+                ("max_block", C.c_int64), ("fp32_fallback_blocks", C.c_int64),
+                ("ilu_levels_lower", C.c_int64), ("ilu_levels_upper", C.c_int64),
+                ("ms_setup", C.c_double), ("device_bytes", C.c_int64)]
+
+
+EXPORTS = {
+    "fams_status_string": ([C.c_int], C.c_char_p),
+    "fams_last_error": ([], C.c_char_p),
+    "fams_footprint": ([C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                        C.POINTER(C.c_size_t)], C.c_int),
+    "fams_setup": ([C.POINTER(CSR), C.POINTER(Grid), C.POINTER(SetupOpts), C.c_void_p,
+                    C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "fams_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(SolveOpts),
+                    C.POINTER(Info)], C.c_int),
+    "fams_reconstruct_flux": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.POINTER(C.c_double)], C.c_int),
+    "fams_get_setup_info": ([C.c_void_p, C.POINTER(SetupInfo)], C.c_int),
+    "fams_destroy": ([C.c_void_p], C.c_int),
+    "fams_get_prolongation": ([C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p,
+                               C.c_void_p], C.c_int),
+    "fams_get_coarse_matrix": ([C.c_void_p, C.c_void_p], C.c_int),
+    "fams_get_ilu": ([C.c_void_p, C.c_void_p], C.c_int),
+    "fams_apply_stage": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "fams_set_profiling": ([C.c_void_p, C.c_int32], C.c_int),
+    "fams_get_kernel_stats": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                               C.POINTER(C.c_int64)], C.c_int),
+    "fams_grid_structured": ([C.c_int32] * 6 + [C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.POINTER(C.c_int64)], C.c_int),
+    "fams_grid_fracture": ([C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                            C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.POINTER(C.c_int64)], C.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libfams.so (built by paper_1705_05784_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1705_05784_amd.build` (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().fams_status_string(int(s)).decode()
+
+
+def _check(st, where):
+    if st < 0:
+        raise FamsError(st, where, lib().fams_last_error().decode())
+    return st
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def footprint(n, nnz, n_coarse, precision=FP64, restart=30) -> int:
+    out = C.c_size_t()
+    _check(lib().fams_footprint(n, nnz, n_coarse, precision, restart, C.byref(out)), "footprint")
+    return int(out.value)
+
+
+class Solver:
+    """An F-AMS setup resident on the GPU (one fams_handle_t)."""
+
+    def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
+                 precision=FP64, alpha=0.0, merge_cap=4096, smoother=True):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def on(a, dt):
+            t = torch.as_tensor(a)
+            return t.to(device=dev, dtype=dt).contiguous()
+        self._keep = [on(row_ptr, torch.int64), on(col, torch.int32), on(val, torch.float64),
+                      on(wb_type, torch.int8), on(primal, torch.int32), on(vertex, torch.int64)]
+        rp, ci, va, wb, pr, vx = self._keep
+        self.n = int(rp.numel() - 1)
+        self.nnz = int(ci.numel())
+        self.n_matrix = int(n_matrix)
+        self.n_coarse = int(vx.numel())
+        csr = CSR(self.n, self.n_matrix, self.nnz, _ptr(rp), _ptr(ci), _ptr(va))
+        grid = Grid(self.n_coarse, _ptr(wb), _ptr(pr), _ptr(vx))
+        if isinstance(variant, str):
+            variant = VARIANTS[variant]
+        opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
+                         1 if smoother else 0, 0)
+        h = C.c_void_p()
+        self._h = None
+        _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, _stream(),
+                                C.byref(h)), "fams_setup")
+        self._h = h
+        self._keep = None   # the handle owns copies of everything it needs
+        self.device = dev
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fams_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, q, p=None, outer=GMRES, restart=30, rtol=1e-6, max_iter=1000,
+              use_initial_guess=False):
+        """q: [n] or [nrhs, n] float64 (row nrhs-major == column-major [n x nrhs])."""
+        import torch
+        q = torch.as_tensor(q).to(self.device, torch.float64).contiguous()
+        nrhs = 1 if q.dim() == 1 else q.shape[0]
+        if p is None:
+            p = torch.zeros_like(q)
+            use_initial_guess = False
+        if isinstance(outer, str):
+            outer = {"richardson": RICHARDSON, "gmres": GMRES}[outer]
+        opts = SolveOpts(int(outer), int(restart), float(rtol), int(max_iter),
+                         1 if use_initial_guess else 0)
+        infos = (Info * nrhs)()
+        st = lib().fams_solve(self._h, _ptr(q), _ptr(p), nrhs, C.byref(opts), infos)
+        _check(st, "fams_solve")
+        return p, [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
+                        ms=i.ms) for i in infos]
+
+    def reconstruct_flux(self, q, p):
+        import torch
+        q = torch.as_tensor(q).to(self.device, torch.float64).contiguous()
+        p = torch.as_tensor(p).to(self.device, torch.float64).contiguous()
+        flux = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        pfv = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        imb = C.c_double()
+        _check(lib().fams_reconstruct_flux(self._h, _ptr(q), _ptr(p), _ptr(flux), _ptr(pfv),
+                                           C.byref(imb)), "fams_reconstruct_flux")
+        return flux, pfv, float(imb.value)
+
+    def apply_stage(self, r):
+        import torch
+        r = torch.as_tensor(r).to(self.device, torch.float64).contiguous()
+        z = torch.empty_like(r)
+        _check(lib().fams_apply_stage(self._h, _ptr(r), _ptr(z)), "fams_apply_stage")
+        return z
+
+    def setup_info(self) -> dict:
+        si = SetupInfo()
+        _check(lib().fams_get_setup_info(self._h, C.byref(si)), "fams_get_setup_info")
+        return {k: getattr(si, k) for k, _ in SetupInfo._fields_}
+
+    def prolongation(self):
+        """(row_ptr, col, val) of P on the host."""
+        nnz = C.c_int64()
+        _check(lib().fams_get_prolongation(self._h, C.byref(nnz), None, None, None), "P")
+        rp = np.empty(self.n + 1, dtype=np.int64)
+        ci = np.empty(nnz.value, dtype=np.int32)
+        va = np.empty(nnz.value, dtype=np.float64)
+        _check(lib().fams_get_prolongation(self._h, C.byref(nnz), rp.ctypes.data, ci.ctypes.data,
+                                           va.ctypes.data), "P")
+        return rp, ci, va
+
+    def coarse_matrix(self):
+        a = np.empty(self.n_coarse * self.n_coarse, dtype=np.float64)
+        _check(lib().fams_get_coarse_matrix(self._h, a.ctypes.data), "A_c")
+        return a.reshape(self.n_coarse, self.n_coarse).T.copy()   # column-major -> [I, J]
+
+    def ilu(self):
+        a = np.empty(self.nnz, dtype=np.float64)
+        _check(lib().fams_get_ilu(self._h, a.ctypes.data), "ILU")
+        return a
+
+    def profiling(self, on=True):
+        _check(lib().fams_set_profiling(self._h, 1 if on else 0), "profiling")
+
+    def kernel_stats(self) -> dict:
+        n = C.c_int32()
+        _check(lib().fams_get_kernel_stats(self._h, 0, C.byref(n), None, None, None), "stats")
+        k = n.value
+        names = (C.c_char_p * k)()
+        ms = (C.c_double * k)()
+        cnt = (C.c_int64 * k)()
+        _check(lib().fams_get_kernel_stats(self._h, k, C.byref(n), names, ms, cnt), "stats")
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(k)}
+
+
+# ---- coarse-grid host helpers -----------------------------------------------
+
+def grid_structured(nx, ny, nz, cx, cy, cz):
+    nc = C.c_int64()
+    _check(lib().fams_grid_structured(nx, ny, nz, cx, cy, cz, None, None, None, C.byref(nc)),
+           "grid")
+    n = nx * ny * nz
+    wb = np.empty(n, dtype=np.int8)
+    pr = np.empty(n, dtype=np.int32)
+    vx = np.empty(nc.value, dtype=np.int64)
+    _check(lib().fams_grid_structured(nx, ny, nz, cx, cy, cz, wb.ctypes.data, pr.ctypes.data,
+                                      vx.ctypes.data, C.byref(nc)), "grid")
+    return wb, pr, vx
+
+
+def grid_fracture(sysm, n_coarse_matrix, d_min, r_z):
+    """Fracture classes/primal/vertices for a workloads.FracturedSystem."""
+    nf = sysm.n - sysm.n_matrix
+    wb = np.empty(nf, dtype=np.int8)
+    pr = np.empty(nf, dtype=np.int32)
+    vx = np.empty(max(nf, 1), dtype=np.int64)
+    ncf = C.c_int64()
+    a = lambda x, dt: np.ascontiguousarray(x, dtype=dt)  # noqa: E731
+    rp, ci = a(sysm.row_ptr, np.int64), a(sysm.col, np.int32)
+    cc, cz = a(sysm.cell_col, np.int32), a(sysm.cell_z, np.int32)
+    cp, cptr, cadj = a(sysm.col_plate, np.int32), a(sysm.col_ptr, np.int64), a(sysm.col_adj, np.int32)
+    zlo, zhi = a(sysm.plate_zlo, np.int32), a(sysm.plate_zhi, np.int32)
+    _check(lib().fams_grid_fracture(sysm.n_matrix, sysm.n, rp.ctypes.data, ci.ctypes.data,
+                                    cc.ctypes.data, cz.ctypes.data, len(cp), cp.ctypes.data,
+                                    cptr.ctypes.data, cadj.ctypes.data, len(zlo), zlo.ctypes.data,
+                                    zhi.ctypes.data, int(d_min), int(r_z), int(n_coarse_matrix),
+                                    wb.ctypes.data, pr.ctypes.data, vx.ctypes.data,
+                                    C.byref(ncf)), "grid_fracture")
+    return wb, pr, vx[:ncf.value]
+
+
+def full_grid(sysm, coarse, d_min, r_z):
+    """Matrix + fracture grid of a workloads.FracturedSystem through the library."""
+    wbm, pm, vm = grid_structured(sysm.nx, sysm.ny, sysm.nz, *coarse)
+    wbf, pf, vf = grid_fracture(sysm, len(vm), d_min, r_z)
+    return (np.concatenate([wbm, wbf]), np.concatenate([pm, pf]), np.concatenate([vm, vf]),
+            len(vm))
+
+
+def setup(sysm, coarse, d_min, r_z, **kw) -> Solver:
+    wb, pr, vx, _ = full_grid(sysm, coarse, d_min, r_z)
+    return Solver(sysm.row_ptr, sysm.col, sysm.val, sysm.n_matrix, wb, pr, vx, **kw)
