@@ -108,7 +108,8 @@ typedef struct {
   double trunc_alpha;         /* drop |P_ij| < alpha, rescale row (Sec. 4.3); 0 = off */
   int64_t merge_cap;          /* Coupled-AMS: max cells of a merged block (Sec. 3.1) */
   int32_t smoother;           /* 1 = ILU(0) post-smoothing (Table 1 step 7), 0 = none */
-  int32_t reserved;
+  int32_t profile;            /* 1 = time every kernel launch of this handle with HIP
+                                 events from setup on (see fams_get_kernel_stats) */
 } fams_setup_opts_t;
 
 typedef struct {

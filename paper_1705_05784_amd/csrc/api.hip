@@ -256,6 +256,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->alpha = o->trunc_alpha;
     h->merge_cap = o->merge_cap;
     h->smoother = o->smoother ? 1 : 0;
+    h->prof.on = o->profile != 0;
     h->n = static_cast<int>(A->n);
     h->nm = static_cast<int>(A->n_matrix);
     h->nnz = A->nnz;

@@ -33,15 +33,13 @@ namespace {
 enum : int8_t { C_NONE = 0, C_KEPT = 1, C_LUMPED = 2, C_RHS = 3 };
 
 constexpr int kThreads = 256;
-constexpr int kMaxSources = 2048;   // distinct higher-rank neighbour blocks per block
-constexpr int kMaxCand = 8192;      // candidate coarse columns before de-duplication
 constexpr int kMaxCols = 2048;      // coarse columns per block (RHS count)
 constexpr int kLdsBandDoubles = 6144;  // band kept in LDS up to 48 KiB
 
 enum ErrBits : int {
   E_VERTEX_RANGE = 1, E_VERTEX_CLASS = 2, E_VERTEX_DUP = 4, E_V_NOT_LISTED = 8,
   E_CLASS_RANGE = 16, E_FRAC_INTERIOR = 32, E_PRIMAL_RANGE = 64,
-  E_NO_HIGHER = 128, E_PIVOT = 256, E_SOURCES = 512, E_CAND = 1024, E_COLS = 2048,
+  E_NO_HIGHER = 128, E_PIVOT = 256, E_SOURCES = 512, E_COLS = 2048,
 };
 
 __device__ __forceinline__ int rank_of(int wb, int i, int nm, int variant) {
@@ -245,43 +243,75 @@ __device__ void block_bitonic_sort(int* a, int cnt) {
   }
 }
 
-// de-duplicate a sorted LDS array in place; returns the unique count
-__device__ int block_unique(int* a, int cnt, int* scratch /* blockDim+1 */) {
-  int per = (cnt + blockDim.x - 1) / blockDim.x;
-  int lo = threadIdx.x * per, hi = min(cnt, lo + per);
-  int mine = 0;
-  for (int t = lo; t < hi; ++t)
-    if (t == 0 || a[t] != a[t - 1]) ++mine;
-  scratch[threadIdx.x] = mine;
-  __syncthreads();
+// Local order of a block: breadth-first levels from its lowest cell, cells of
+// one level by ascending natural position.  Irregular blocks (fracture
+// regions, merged Coupled-AMS blocks) get a bandwidth tens of times smaller
+// than in ascending-index order; structured dual blocks keep their natural
+// order, which is narrower for them.  The order used is the narrower one.
+constexpr int kOrderMax = 6144;
+__global__ void __launch_bounds__(kThreads)
+k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, const int8_t* ecls,
+              int* local_idx) {
+  __shared__ int lvl[kOrderMax];
+  __shared__ int key[8192];
+  __shared__ int s_changed, s_bnat, s_bbfs;
+  int K = blockIdx.x;
+  int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
+  if (n <= 2 || n > kOrderMax) return;
   if (threadIdx.x == 0) {
-    int s = 0;
-    for (int t = 0; t < (int)blockDim.x; ++t) {
-      int v = scratch[t];
-      scratch[t] = s;
-      s += v;
-    }
-    scratch[blockDim.x] = s;
+    s_bnat = 0;
+    s_bbfs = 0;
   }
   __syncthreads();
-  int o = scratch[threadIdx.x];
-  // values to keep, collected before any write (in-place compaction is safe
-  // because output positions never exceed input positions, but other threads
-  // may still read a[t-1] -- so stage through registers chunk by chunk)
-  int vals[32];
-  int nv = 0;
-  int total = scratch[blockDim.x];
-  __syncthreads();
-  for (int t = lo; t < hi; ++t) {
-    if (t == 0 || a[t] != a[t - 1]) {
-      if (nv < 32) vals[nv] = a[t];
-      ++nv;
-    }
+  int bnat = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (ecls[p] == C_KEPT) bnat = max(bnat, abs(local_idx[ci[p]] - l));
+    lvl[l] = l == 0 ? 0 : -1;
   }
+  atomicMax(&s_bnat, bnat);
   __syncthreads();
-  for (int k = 0; k < nv && k < 32; ++k) a[o + k] = vals[k];
+  for (int d = 0; d < n; ++d) {
+    if (threadIdx.x == 0) s_changed = 0;
+    __syncthreads();
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+      if (lvl[l] != d) continue;
+      int i = cells[beg + l];
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (ecls[p] != C_KEPT) continue;
+        int lj = local_idx[ci[p]];
+        if (lvl[lj] < 0) {
+          lvl[lj] = d + 1;
+          s_changed = 1;
+        }
+      }
+    }
+    __syncthreads();
+    const int changed = s_changed;
+    __syncthreads();  // every thread has read the flag before it is reset
+    if (!changed) break;
+  }
+  for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = (lvl[l] << 13) | l;
   __syncthreads();
-  return total;
+  block_bitonic_sort(key, n);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) lvl[key[t] & 8191] = t;  // lvl := position
+  __syncthreads();
+  int bb = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (ecls[p] == C_KEPT) bb = max(bb, abs(lvl[local_idx[ci[p]]] - lvl[l]));
+  }
+  atomicMax(&s_bbfs, bb);
+  __syncthreads();
+  if (s_bbfs >= s_bnat) return;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = cells[beg + l];
+  __syncthreads();
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    cells[beg + lvl[l]] = key[l];
+    local_idx[key[l]] = lvl[l];
+  }
 }
 
 __device__ __forceinline__ int bsearch_i32(const int* a, int n, int key) {
@@ -294,79 +324,118 @@ __device__ __forceinline__ int bsearch_i32(const int* a, int n, int key) {
   return lo;
 }
 
+// Insert-if-absent into an open-addressing LDS hash set (EMPTY = INT_MIN);
+// returns false when the table is full.
+constexpr int kEmpty = INT_MIN;
+__device__ __forceinline__ bool hset_insert(int* tab, int mask, int key, int* count) {
+  unsigned h = (static_cast<unsigned>(key) * 2654435761u) & static_cast<unsigned>(mask);
+  for (int probe = 0; probe <= mask; ++probe) {
+    int prev = atomicCAS(&tab[h], kEmpty, key);
+    if (prev == kEmpty) {
+      atomicAdd(count, 1);
+      return true;
+    }
+    if (prev == key) return true;
+    h = (h + 1) & static_cast<unsigned>(mask);
+  }
+  return false;
+}
+
+// move the set's keys into out[0..count) and sort them ascending
+__device__ void hset_collect_sorted(const int* tab, int size, int* out, int count, int* cursor) {
+  if (threadIdx.x == 0) *cursor = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < size; t += blockDim.x)
+    if (tab[t] != kEmpty) out[atomicAdd(cursor, 1)] = tab[t];
+  __syncthreads();
+  block_bitonic_sort(out, count);
+}
+
+constexpr int kSrcSlots = 2048;   // hash slots for distinct higher-rank neighbour blocks
+constexpr int kColSlots = 4096;   // hash slots for distinct coarse columns
+
 // Symbolic pass of one rank level: the coarse columns each block's
 // right-hand side touches (union over its higher-rank neighbours' columns),
-// and the block's bandwidth in its local (ascending cell) order.
+// and the block's bandwidth in its local order.
 __global__ void __launch_bounds__(kThreads)
 k_colset(int c0, const int* comp_ptr, const int* cells, const int* rp, const int* ci,
          const int8_t* ecls, const int8_t* wb, const int* coarse_of, const int* comp_of,
          const int* local_idx, const int64_t* col_ptr, const int* cols, int* tmp_cols,
-         int* ncols_out, int* band_out, int* err) {
-  __shared__ int src[kMaxSources];
-  __shared__ int cand[kMaxCand];
-  __shared__ int scratch[kThreads + 1];
-  __shared__ int s_cnt, s_band, s_over;
+         int* ncols_out, int* band_out, int* err, int* diag) {
+  __shared__ int src_tab[kSrcSlots];
+  __shared__ int src[kSrcSlots];
+  __shared__ int col_tab[kColSlots];
+  __shared__ int colv[kColSlots];
+  __shared__ int s_nsrc, s_ncol, s_band, s_over, s_cur;
   int K = c0 + blockIdx.x;
   int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
+  for (int t = threadIdx.x; t < kSrcSlots; t += blockDim.x) src_tab[t] = kEmpty;
+  for (int t = threadIdx.x; t < kColSlots; t += blockDim.x) col_tab[t] = kEmpty;
   if (threadIdx.x == 0) {
-    s_cnt = 0;
+    s_nsrc = 0;
+    s_ncol = 0;
     s_band = 0;
     s_over = 0;
   }
   __syncthreads();
   int bmax = 0;
+  bool over = false;
   for (int l = threadIdx.x; l < n; l += blockDim.x) {
     int i = cells[beg + l];
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
       int8_t c = ecls[p];
       int j = ci[p];
       if (c == C_KEPT) {
-        bmax = max(bmax, abs(local_idx[j] - l));
+        bmax = max(bmax, abs(local_idx[j] - local_idx[i]));
       } else if (c == C_RHS) {
-        int s = wb[j] == 3 ? -(coarse_of[j] + 1) : comp_of[j];
-        int k = atomicAdd(&s_cnt, 1);
-        if (k < kMaxSources) src[k] = s;
+        int sk = wb[j] == 3 ? -(coarse_of[j] + 1) : comp_of[j];
+        if (!hset_insert(src_tab, kSrcSlots - 1, sk, &s_nsrc)) over = true;
       }
     }
   }
   atomicMax(&s_band, bmax);
+  if (over) atomicOr(&s_over, E_SOURCES);
   __syncthreads();
-  int nsrc = s_cnt;
-  if (nsrc > kMaxSources) {
-    if (threadIdx.x == 0) atomicOr(err, E_SOURCES);
+  const int nsrc = s_nsrc;
+  if (s_over || nsrc > kSrcSlots / 2) {
+    if (threadIdx.x == 0) {
+      atomicOr(err, E_SOURCES);
+      if (atomicCAS(&diag[0], -1, K) == -1) {
+        diag[1] = nsrc;
+        diag[2] = n;
+      }
+    }
     return;
   }
-  block_bitonic_sort(src, nsrc);
-  nsrc = block_unique(src, nsrc, scratch);
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
+  hset_collect_sorted(src_tab, kSrcSlots, src, nsrc, &s_cur);
+  over = false;
   for (int t = threadIdx.x; t < nsrc; t += blockDim.x) {
-    int s = src[t];
-    if (s < 0) {
-      int k = atomicAdd(&s_cnt, 1);
-      if (k < kMaxCand) cand[k] = -s - 1;
+    int sk = src[t];
+    if (sk < 0) {
+      if (!hset_insert(col_tab, kColSlots - 1, -sk - 1, &s_ncol)) over = true;
     } else {
-      int64_t a = col_ptr[s], b = col_ptr[s + 1];
-      int k = atomicAdd(&s_cnt, static_cast<int>(b - a));
-      for (int64_t q = a; q < b; ++q, ++k)
-        if (k < kMaxCand) cand[k] = cols[q];
+      for (int64_t q = col_ptr[sk]; q < col_ptr[sk + 1]; ++q)
+        if (!hset_insert(col_tab, kColSlots - 1, cols[q], &s_ncol)) over = true;
     }
   }
+  if (over) atomicOr(&s_over, E_COLS);
   __syncthreads();
-  int ncand = s_cnt;
-  if (ncand > kMaxCand) {
-    if (threadIdx.x == 0) atomicOr(err, E_CAND);
-    return;
-  }
-  block_bitonic_sort(cand, ncand);
-  int nu = block_unique(cand, ncand, scratch);
-  if (nu > kMaxCols) {
-    if (threadIdx.x == 0) atomicOr(err, E_COLS);
+  const int nu = s_ncol;
+  if (s_over || nu > kMaxCols) {
+    if (threadIdx.x == 0) {
+      atomicOr(err, E_COLS);
+      if (atomicCAS(&diag[0], -1, K) == -1) {
+        diag[1] = nsrc;
+        diag[2] = n;
+        diag[3] = nu;
+      }
+    }
     return;
   }
   if (nu == 0 && threadIdx.x == 0) atomicOr(err, E_NO_HIGHER);
+  hset_collect_sorted(col_tab, kColSlots, colv, nu, &s_cur);
   int* out = tmp_cols + static_cast<int64_t>(blockIdx.x) * kMaxCols;
-  for (int t = threadIdx.x; t < nu; t += blockDim.x) out[t] = cand[t];
+  for (int t = threadIdx.x; t < nu; t += blockDim.x) out[t] = colv[t];
   if (threadIdx.x == 0) {
     ncols_out[K] = nu;
     band_out[K] = s_band;
@@ -780,6 +849,9 @@ void build_prolongation(Handle* h, const int8_t* wb) {
     LAUNCH(h, "local_idx", k_local_idx, blocks_for(m, kThreads), kThreads, 0, m, kks.get(),
            cells.get(), comp_ptr.get(), local_idx.get());
   }
+  if (ncomp)
+    LAUNCH(h, "local_order", k_local_order, ncomp, kThreads, 0, comp_ptr.get(), cells.get(),
+           h->rp.get(), h->ci.get(), ecls.get(), local_idx.get());
   std::vector<int> h_cks(ncomp), h_comp_ptr(ncomp + 1, 0);
   if (ncomp) {
     HIPX(hipMemcpyAsync(h_cks.data(), cks.get(), ncomp * sizeof(int), hipMemcpyDeviceToHost,
@@ -809,12 +881,14 @@ void build_prolongation(Handle* h, const int8_t* wb) {
   DBuf<int> cols(A, 1);
   int64_t cols_size = 0;
   HIPX(hipMemsetAsync(col_ptr, 0, (ncomp + 1) * sizeof(int64_t), h->stream));
+  DBuf<int> diag(A, 4);
+  HIPX(hipMemsetAsync(diag, 0xff, 4 * sizeof(int), h->stream));
   for (auto [c0, c1] : levels) {
     int nl = c1 - c0;
     DBuf<int> tmp(A, static_cast<size_t>(nl) * kMaxCols);
     LAUNCH(h, "colset", k_colset, nl, kThreads, 0, c0, comp_ptr.get(), cells.get(), h->rp.get(),
            h->ci.get(), ecls.get(), wb, coarse_of.get(), comp_of.get(), local_idx.get(),
-           col_ptr.get(), cols.get(), tmp.get(), ncols.get(), band.get(), err.get());
+           col_ptr.get(), cols.get(), tmp.get(), ncols.get(), band.get(), err.get(), diag.get());
     HIPX(hipMemcpyAsync(h_ncols.data() + c0, ncols.get() + c0, nl * sizeof(int),
                         hipMemcpyDeviceToHost, h->stream));
     HIPX(hipMemcpyAsync(h_band.data() + c0, band.get() + c0, nl * sizeof(int),
@@ -822,8 +896,16 @@ void build_prolongation(Handle* h, const int8_t* wb) {
     int ev = static_cast<int>(read1(h, err.get()));
     FAMS_REQUIRE(!(ev & E_NO_HIGHER), FAMS_ERR_SINGULAR_LOCAL,
                  "a local block has no higher-rank neighbour");
-    FAMS_REQUIRE(!(ev & (E_SOURCES | E_CAND | E_COLS)), FAMS_ERR_CAPACITY,
-                 "a local block touches too many coarse columns");
+    if (ev & (E_SOURCES | E_COLS)) {
+      int hd[4];
+      HIPX(hipMemcpyAsync(hd, diag.get(), sizeof(hd), hipMemcpyDeviceToHost, h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+      throw Error(FAMS_ERR_CAPACITY,
+                  "local block " + std::to_string(hd[0]) + " (" + std::to_string(hd[2]) +
+                      " cells, " + std::to_string(hd[1]) + " higher-rank couplings/sources, " +
+                      std::to_string(hd[3]) + " columns) exceeds a per-block limit (flags " +
+                      std::to_string(ev) + ")");
+    }
     for (int K = c0; K < c1; ++K) h_col_ptr[K + 1] = h_col_ptr[K] + h_ncols[K];
     int64_t new_size = h_col_ptr[c1];
     DBuf<int> grown(A, std::max<int64_t>(new_size, 1));

@@ -42,7 +42,7 @@ class Grid(C.Structure):
 
 class SetupOpts(C.Structure):
     _fields_ = [("variant", C.c_int32), ("precision", C.c_int32), ("trunc_alpha", C.c_double),
-                ("merge_cap", C.c_int64), ("smoother", C.c_int32), ("reserved", C.c_int32)]
+                ("merge_cap", C.c_int64), ("smoother", C.c_int32), ("profile", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -146,7 +146,7 @@ class Solver:
     """An F-AMS setup resident on the GPU (one fams_handle_t)."""
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
-                 precision=FP64, alpha=0.0, merge_cap=4096, smoother=True):
+                 precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -165,7 +165,7 @@ class Solver:
         if isinstance(variant, str):
             variant = VARIANTS[variant]
         opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
-                         1 if smoother else 0, 0)
+                         1 if smoother else 0, 1 if profile else 0)
         h = C.c_void_p()
         self._h = None
         _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, _stream(),

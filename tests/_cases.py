@@ -32,10 +32,17 @@ def hat_1d(n, c):
 SMALL = {
     "2d": dict(kind="2d", coarse=(4, 4, 1), d_min=4, r_z=1),
     "3d": dict(kind="3d", coarse=(4, 4, 4), d_min=4, r_z=4),
+    # the full-size workload's shapes, shrunk: coarsening 10^3, d_min = r_z = 8
+    "cfg2s": dict(kind="cfg2s", coarse=(10, 10, 10), d_min=8, r_z=8),
 }
 
 
 def small_case(name, seed=0, neumann=False, **kw):
     spec = SMALL[name]
+    if spec["kind"] == "cfg2s":
+        from workloads import make_config
+        s = make_config(2, instance=100 + seed, dims=kw.get("dims", (42, 36, 22)),
+                        n_frac=kw.get("n_frac", 12), neumann=neumann)
+        return s, spec
     s = make_small(spec["kind"], seed=seed, neumann=neumann, **kw)
     return s, spec
