@@ -49,6 +49,22 @@ __global__ void k_resid(int n, const int* rp, const int* ci, const TV* val, cons
   y[i] = static_cast<TY>(s);
 }
 
+// y[r] = sum_k M[r,k] x[k] for short fat rows (R = P^T has ~N/n_c entries per
+// row): one wavefront per row, lanes stride over the row, fixed-order shuffle
+// reduction -- deterministic.
+template <class TV, class TX>
+__global__ void __launch_bounds__(256)
+k_spmv_wave(int nrows, const int* rp, const int* ci, const TV* val, const TX* x, double* y) {
+  int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  int lane = threadIdx.x % 64;
+  if (row >= nrows) return;
+  double s = 0.0;
+  for (int p = rp[row] + lane; p < rp[row + 1]; p += 64)
+    s += static_cast<double>(val[p]) * static_cast<double>(x[ci[p]]);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) y[row] = s;
+}
+
 __device__ double block_sum(double v) {
   __shared__ double s[kT / 64];
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -294,7 +310,7 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
     rh = k.rh32;
     x = k.x32;
   }
-  LAUNCH(h, "restrict", (k_spmv<T, T, double>), blocks_for(nc, kT), kT, 0, nc, h->r_rp.get(),
+  LAUNCH(h, "restrict", (k_spmv_wave<T, T>), blocks_for(nc, 4), 256, 0, nc, h->r_rp.get(),
          h->r_ci.get(), rv, rT, k.rc);
   coarse_apply(h, h->Ainv.get(), nc, k.rc, k.xc, h->gpart.get());
   LAUNCH(h, "prolong", (k_spmv<T, double, T>), blocks_for(n, kT), kT, 0, n, h->p_rp.get(),
