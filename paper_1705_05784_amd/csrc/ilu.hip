@@ -3,9 +3,11 @@
 // x = U^{-1} L^{-1} b by level-scheduled triangular sweeps.
 //
 // Level of row i in the lower sweep = 1 + max level of the rows j < i it
-// depends on (0 if none); the upper sweep uses j > i.  Rows of one level are
-// independent, so each level is one launch with a thread per row; the
-// natural ordering -- and hence the smoother itself -- is unchanged.
+// depends on (0 if none); the upper sweep uses j > i.  The factorisation runs
+// one launch per level (a thread per row).  Each sweep of the iteration is a
+// single launch that walks the rows in level order and lets every row wait
+// only for its own dependencies (see k_sweep_lower).  The natural ordering --
+// and hence the smoother itself -- is unchanged.
 #include <algorithm>
 #include <vector>
 
@@ -15,6 +17,7 @@ namespace fams {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kSweepGroups = 256;  // workgroups of a one-launch sweep
 
 __global__ void k_diag_pos(int n, const int* rp, const int* ci, int* diag, int* err) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,26 +84,119 @@ __global__ void k_ilu_rows(const int* rows, int r0, int r1, const int* rp, const
   if (!(lu[diag[i]] > 0.0)) atomicOr(err, 1);
 }
 
+// ---- one-launch sweeps: level-ordered chunks with point-to-point waits ------
+// Rows are taken in level order, in chunks that never straddle a level; a
+// workgroup takes the next chunk from an atomic ticket, so the workgroup that
+// holds the lowest unfinished ticket has every dependency (all in lower
+// levels, hence earlier tickets) already written and always progresses.  A
+// row waits only for its own dependencies: every output entry starts as a
+// sentinel NaN and the value itself is the ready flag (device-coherent atomic
+// 64/32-bit stores and loads, so no separate flag or fence is needed).  A wait
+// is bounded: past the spin limit the kernel flags an error and moves on, so
+// every wave always exits.
+template <class T> struct Sentinel;
+template <> struct Sentinel<double> {
+  using U = unsigned long long;
+  static constexpr U bits = 0x7FF4000000000BADull;
+};
+template <> struct Sentinel<float> {
+  using U = unsigned int;
+  static constexpr U bits = 0x7FA00BADu;
+};
+
 template <class T>
-__global__ void k_trsv_lower(const int* rows, int r0, int r1, const int* rp, const int* ci,
-                             const int* diag, const T* lu, const T* b, T* x) {
-  int t = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= r1) return;
-  int i = rows[t];
-  T s = b[i];
-  for (int p = rp[i]; p < diag[i]; ++p) s -= lu[p] * x[ci[p]];
-  x[i] = s;
+__device__ __forceinline__ void store_ready(T* p, T v) {
+  using U = typename Sentinel<T>::U;
+  U u;
+  __builtin_memcpy(&u, &v, sizeof(T));
+  if (u == Sentinel<T>::bits) u ^= 1;  // never publish the sentinel itself
+  __hip_atomic_store(reinterpret_cast<U*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *p is published.  Polls back off up to ~1.7 us; the wait gives
+// up after `limit` wall-clock ticks, or at once when another wait has given
+// up (err != 0), so a broken dependency order ends the kernel quickly.
+template <class T>
+__device__ __forceinline__ T wait_ready(const T* p, int* err, unsigned long long limit) {
+  using U = typename Sentinel<T>::U;
+  const U* q = reinterpret_cast<const U*>(p);
+  U u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (u == Sentinel<T>::bits) {
+    const unsigned long long t0 = wall_clock64();
+    int backoff = 1;
+    while (u == Sentinel<T>::bits) {
+      for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
+      backoff = backoff < 64 ? 2 * backoff : 64;
+      u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (u != Sentinel<T>::bits) break;
+      if (wall_clock64() - t0 > limit ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        atomicOr(err, 2);
+        u = 0;
+        break;
+      }
+    }
+  }
+  T v;
+  __builtin_memcpy(&v, &u, sizeof(T));
+  return v;
 }
 
 template <class T>
-__global__ void k_trsv_upper(const int* rows, int r0, int r1, const int* rp, const int* ci,
-                             const int* diag, const T* lu, T* x) {
-  int t = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= r1) return;
-  int i = rows[t];
-  T s = x[i];
-  for (int p = diag[i] + 1; p < rp[i + 1]; ++p) s -= lu[p] * x[ci[p]];
-  x[i] = s / lu[diag[i]];
+__global__ void k_fill_sentinel(int n, T* x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  using U = typename Sentinel<T>::U;
+  if (i < n) reinterpret_cast<U*>(x)[i] = Sentinel<T>::bits;
+}
+
+// forward sweep y = L^{-1} b (unit L); also arms z (the backward sweep's
+// output) with the sentinel
+template <class T>
+__global__ void __launch_bounds__(256)
+k_sweep_lower(const int* rows, const int* chunk, int nchunks, const int* rp, const int* ci,
+              const int* diag, const T* lu, const T* b, T* y, T* z, int* ticket, int* err,
+              unsigned long long limit) {
+  __shared__ int s_c;
+  while (true) {
+    if (threadIdx.x == 0) s_c = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int c = s_c;
+    __syncthreads();
+    if (c >= nchunks) break;
+    const int t = chunk[c] + threadIdx.x;
+    if (t < chunk[c + 1]) {
+      const int i = rows[t];
+      T s = b[i];
+      for (int p = rp[i]; p < diag[i]; ++p) s -= lu[p] * wait_ready<T>(y + ci[p], err, limit);
+      using U = typename Sentinel<T>::U;
+      reinterpret_cast<U*>(z)[i] = Sentinel<T>::bits;
+      store_ready<T>(y + i, s);
+    }
+  }
+}
+
+// backward sweep z = U^{-1} y
+template <class T>
+__global__ void __launch_bounds__(256)
+k_sweep_upper(const int* rows, const int* chunk, int nchunks, const int* rp, const int* ci,
+              const int* diag, const T* lu, const T* y, T* z, int* ticket, int* err,
+              unsigned long long limit) {
+  __shared__ int s_c;
+  while (true) {
+    if (threadIdx.x == 0) s_c = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int c = s_c;
+    __syncthreads();
+    if (c >= nchunks) break;
+    const int t = chunk[c] + threadIdx.x;
+    if (t < chunk[c + 1]) {
+      const int i = rows[t];
+      T s = y[i];
+      for (int p = diag[i] + 1; p < rp[i + 1]; ++p)
+        s -= lu[p] * wait_ready<T>(z + ci[p], err, limit);
+      store_ready<T>(z + i, s / lu[diag[i]]);
+    }
+  }
 }
 
 void levels(Handle* h, int upper, Levels* out) {
@@ -145,6 +241,19 @@ __global__ void k_d2f_ilu(int64_t n, const double* a, float* b) {
   if (i < n) b[i] = static_cast<float>(a[i]);
 }
 
+// chunks of at most 256 rows inside one level
+void chunk_table(Handle* h, Levels* L) {
+  std::vector<int> cb;
+  for (int l = 0; l < L->count(); ++l)
+    for (int s = L->ptr[l]; s < L->ptr[l + 1]; s += 256) cb.push_back(s);
+  cb.push_back(L->ptr.empty() ? 0 : L->ptr.back());
+  L->nchunks = static_cast<int>(cb.size()) - 1;
+  L->chunk.reset(&h->alloc, cb.size());
+  HIPX(hipMemcpyAsync(L->chunk, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
 }  // namespace
 
 void build_ilu(Handle* h) {
@@ -161,6 +270,8 @@ void build_ilu(Handle* h) {
   if (!h->smoother) return;
   levels(h, 0, &h->lvl_lo);
   levels(h, 1, &h->lvl_up);
+  chunk_table(h, &h->lvl_lo);
+  chunk_table(h, &h->lvl_up);
   h->info.ilu_levels_lower = h->lvl_lo.count();
   h->info.ilu_levels_upper = h->lvl_up.count();
   h->ilu.reset(&h->alloc, h->nnz);
@@ -181,21 +292,36 @@ void build_ilu(Handle* h) {
   }
 }
 
+// x = U^{-1} L^{-1} b.  `y` is scratch of n entries.
 template <class T>
-void ilu_apply(Handle* h, const T* lu, const T* b, T* x) {
-  for (int L = 0; L < h->lvl_lo.count(); ++L) {
-    int r0 = h->lvl_lo.ptr[L], r1 = h->lvl_lo.ptr[L + 1];
-    LAUNCH(h, "ilu_lower", k_trsv_lower<T>, blocks_for(r1 - r0, kT), kT, 0,
-           h->lvl_lo.rows.get(), r0, r1, h->rp.get(), h->ci.get(), h->diag.get(), lu, b, x);
+void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
+  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, 4);
+  if (!h->sweep_err.get()) {
+    h->sweep_err.reset(&h->alloc, 1);
+    HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
   }
-  for (int L = 0; L < h->lvl_up.count(); ++L) {
-    int r0 = h->lvl_up.ptr[L], r1 = h->lvl_up.ptr[L + 1];
-    LAUNCH(h, "ilu_upper", k_trsv_upper<T>, blocks_for(r1 - r0, kT), kT, 0,
-           h->lvl_up.rows.get(), r0, r1, h->rp.get(), h->ci.get(), h->diag.get(), lu, x);
+  HIPX(hipMemsetAsync(h->ilu_ticket, 0, 2 * sizeof(int), h->stream));
+  const int n = h->n;
+  LAUNCH(h, "ilu_arm", k_fill_sentinel<T>, blocks_for(n, kT), kT, 0, n, y);
+  if (!h->wait_ticks) {  // 2 s of the device's constant-rate wall clock
+    int dev = 0, khz = 0;
+    HIPX(hipGetDevice(&dev));
+    HIPX(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    h->wait_ticks = 2000ull * static_cast<unsigned long long>(khz > 0 ? khz : 100000);
   }
+  // a window of ~kSweepGroups chunks in flight: enough to overlap tens of
+  // levels, few enough that waiting rows do not flood the memory system
+  const int g_lo = std::min(h->lvl_lo.nchunks, kSweepGroups);
+  const int g_up = std::min(h->lvl_up.nchunks, kSweepGroups);
+  LAUNCH(h, "ilu_lower", k_sweep_lower<T>, g_lo, 256, 0, h->lvl_lo.rows.get(),
+         h->lvl_lo.chunk.get(), h->lvl_lo.nchunks, h->rp.get(), h->ci.get(), h->diag.get(), lu,
+         b, y, x, h->ilu_ticket.get(), h->sweep_err.get(), h->wait_ticks);
+  LAUNCH(h, "ilu_upper", k_sweep_upper<T>, g_up, 256, 0, h->lvl_up.rows.get(),
+         h->lvl_up.chunk.get(), h->lvl_up.nchunks, h->rp.get(), h->ci.get(), h->diag.get(), lu,
+         y, x, h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks);
 }
 
-template void ilu_apply<double>(Handle*, const double*, const double*, double*);
-template void ilu_apply<float>(Handle*, const float*, const float*, float*);
+template void ilu_apply<double>(Handle*, const double*, const double*, double*, double*);
+template void ilu_apply<float>(Handle*, const float*, const float*, float*, float*);
 
 }  // namespace fams

@@ -122,6 +122,8 @@ inline unsigned blocks_for(int64_t n, int threads) {
 struct Levels {
   std::vector<int> ptr;  // host: row ranges per level in `rows`
   DBuf<int> rows;        // device: rows grouped by level, ascending within level
+  DBuf<int> chunk;       // device: chunk boundaries (<= 256 rows, inside one level)
+  int nchunks = 0;
   int count() const { return ptr.empty() ? 0 : static_cast<int>(ptr.size()) - 1; }
 };
 
@@ -161,6 +163,9 @@ struct Handle {
   DBuf<double> ilu;
   DBuf<float> ilu32;
   Levels lvl_lo, lvl_up;
+  DBuf<int> ilu_ticket;  // work tickets of the two sweeps
+  DBuf<int> sweep_err;   // set when a bounded wait in a sweep gives up
+  unsigned long long wait_ticks = 0;  // bound of one wait, device wall-clock ticks
 
   // finite-volume stage (built lazily by fams_reconstruct_flux)
   bool fv_ready = false;
@@ -196,7 +201,7 @@ void coarse_apply(Handle* h, const double* inv, int nc, const double* x, double*
 // ilu.hip
 void build_ilu(Handle* h);
 template <class T>
-void ilu_apply(Handle* h, const T* lu, const T* b, T* x);
+void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y);
 // solve.hip
 fams_status_t solve_one(Handle* h, const double* q, double* p, const fams_solve_opts_t* o,
                         fams_info_t* info);

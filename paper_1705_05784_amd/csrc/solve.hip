@@ -205,8 +205,8 @@ __global__ void k_backsolve(GmresState s, int m, int k) {
 // ---- helpers ------------------------------------------------------------------
 struct Work {
   double *r, *w, *d1, *z, *rc, *xc, *part, *V, *Z;
-  float *r32, *d1_32, *rh32, *x32;
-  double *rh, *x;
+  float *r32, *d1_32, *rh32, *x32, *y32;
+  double *rh, *x, *y;
   GmresState gs;
   int m;
 };
@@ -214,7 +214,7 @@ struct Work {
 Work work_of(Handle* h) {
   Work k{};
   int64_t n = h->n;
-  int m = static_cast<int>((h->wk_vectors - 6) / 2);
+  int m = static_cast<int>((h->wk_vectors - 7) / 2);
   double* b = h->wk.get();
   k.m = m;
   k.r = b;
@@ -223,7 +223,8 @@ Work work_of(Handle* h) {
   k.z = b + 3 * n;
   k.rh = b + 4 * n;
   k.x = b + 5 * n;
-  k.V = b + 6 * n;
+  k.y = b + 6 * n;
+  k.V = b + 7 * n;
   k.Z = k.V + static_cast<int64_t>(m + 1) * n;
   double* s = h->red.get();
   k.part = s;
@@ -250,6 +251,7 @@ Work work_of(Handle* h) {
     k.d1_32 = f + n;
     k.rh32 = f + 2 * n;
     k.x32 = f + 3 * n;
+    k.y32 = f + 4 * n;
   }
   return k;
 }
@@ -288,7 +290,7 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
   const T* av;
   const T* lu;
   const T* rT;
-  T *d1, *rh, *x;
+  T *d1, *rh, *x, *ysc;
   if constexpr (std::is_same<T, double>::value) {
     pv = h->p_val.get();
     rv = h->r_val.get();
@@ -298,6 +300,7 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
     d1 = k.d1;
     rh = k.rh;
     x = k.x;
+    ysc = k.y;
   } else {
     pv = h->p_val32.get();
     rv = h->r_val32.get();
@@ -309,6 +312,7 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
     d1 = k.d1_32;
     rh = k.rh32;
     x = k.x32;
+    ysc = k.y32;
   }
   LAUNCH(h, "restrict", (k_spmv_wave<T, T>), blocks_for(nc, 4), 256, 0, nc, h->r_rp.get(),
          h->r_ci.get(), rv, rT, k.rc);
@@ -317,7 +321,7 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
          h->p_ci.get(), pv, k.xc, d1);
   if (h->smoother) {
     resid<T, T, T, T>(h, av, d1, rT, rh);
-    ilu_apply<T>(h, lu, rh, x);
+    ilu_apply<T>(h, lu, rh, x, ysc);
     LAUNCH(h, "add", (k_add<T, T, double>), blocks_for(n, kT), kT, 0, (int64_t)n, d1, x, z);
   } else {
     LAUNCH(h, "cast", (k_cast<T, double>), blocks_for(n, kT), kT, 0, (int64_t)n, d1, z);
@@ -425,18 +429,27 @@ fams_status_t gmres(Handle* h, const Work& k, const double* q, double* p,
   return st;
 }
 
+// a bounded wait that gave up means the sweep's dependency order was broken
+void check_sweeps(Handle* h) {
+  if (!h->sweep_err.get()) return;
+  int e = 0;
+  HIPX(hipMemcpyAsync(&e, h->sweep_err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "ILU(0) sweep: a dependency wait exceeded its bound");
+}
+
 }  // namespace
 
 void ensure_workspace(Handle* h, int restart) {
   int m = std::max(restart, 1);
-  size_t need = static_cast<size_t>(6 + 2 * m + 1);
+  size_t need = static_cast<size_t>(7 + 2 * m + 1);
   if (h->wk_vectors >= need) return;
   h->wk.reset(&h->alloc, need * static_cast<size_t>(h->n));
   h->wk_vectors = need;
   h->red.reset(&h->alloc, static_cast<size_t>(kRedBlocks) * (m + 2) + 16);
   h->hred.reset(&h->alloc, 2 * static_cast<size_t>(h->nc) + static_cast<size_t>(m + 1) * m +
                                6 * static_cast<size_t>(m) + 16);
-  if (h->precision == FAMS_PREC_MIXED) h->wk32.reset(&h->alloc, 4 * static_cast<size_t>(h->n));
+  if (h->precision == FAMS_PREC_MIXED) h->wk32.reset(&h->alloc, 5 * static_cast<size_t>(h->n));
   const size_t nch = (static_cast<size_t>(h->nc) + 63) / 64;   // coarse GEMV column chunks
   if (h->gpart.size() < nch * h->nc) h->gpart.reset(&h->alloc, nch * h->nc);
 }
@@ -445,11 +458,13 @@ fams_status_t solve_one(Handle* h, const double* q, double* p, const fams_solve_
                         fams_info_t* info) {
   ensure_workspace(h, o->outer == FAMS_GMRES ? o->restart : 1);
   Work k = work_of(h);
+  if (h->sweep_err.get()) HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
   if (!o->use_initial_guess) HIPX(hipMemsetAsync(p, 0, sizeof(double) * h->n, h->stream));
   auto t0 = std::chrono::steady_clock::now();
   fams_status_t st = o->outer == FAMS_GMRES ? gmres(h, k, q, p, o, info)
                                             : richardson(h, k, q, p, o, info);
   HIPX(hipStreamSynchronize(h->stream));
+  check_sweeps(h);
   info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
                  .count();
   info->status = st;
@@ -461,6 +476,7 @@ void apply_stage_fp64(Handle* h, const double* r, double* z) {
   Work k = work_of(h);
   stage_any(h, k, r, z);
   HIPX(hipStreamSynchronize(h->stream));
+  check_sweeps(h);
 }
 
 double dev_dot(Handle* h, const double* a, const double* b, int64_t n) {
