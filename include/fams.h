@@ -24,6 +24,11 @@
  *   - A handle is used by one host thread / stream at a time; distinct handles
  *     are independent and may run concurrently on different streams.
  *
+ * Environment
+ *   - FAMS_LDS_LIMIT=<bytes> lowers the LDS budget of the local block solves
+ *     (read when a handle first sizes them); blocks whose band no longer fits
+ *     move to the global-memory storage modes.  For tests and tuning.
+ *
  * Errors: no exceptions cross the ABI.  Negative status = error (on a setup
  * error *out is NULL and nothing is leaked; on a solve error the handle stays
  * valid); positive status = the iteration stopped without meeting rtol, with

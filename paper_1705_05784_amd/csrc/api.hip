@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 #include <string>
 #include <vector>
@@ -80,6 +81,30 @@ Prof::~Prof() {
     (void)hipEventDestroy(pe.a);
     (void)hipEventDestroy(pe.b);
   }
+}
+
+int64_t lds_budget(Handle* h) {
+  if (!h->lds_bytes) {
+    int dev = 0, v = 0;
+    HIPX(hipGetDevice(&dev));
+    HIPX(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // leave room for the kernels' static LDS
+    h->lds_bytes = std::min<int64_t>(std::max(v, 65536), 160 * 1024) - 4096;
+    // FAMS_LDS_LIMIT (bytes) lowers the budget, which moves local blocks to
+    // the global-memory storage modes (used to exercise those modes on small
+    // problems)
+    if (const char* e = std::getenv("FAMS_LDS_LIMIT")) {
+      const long long lim = std::atoll(e);
+      if (lim > 0) h->lds_bytes = std::min<int64_t>(h->lds_bytes, lim);
+    }
+  }
+  return h->lds_bytes;
+}
+
+void allow_lds(const void* kernel, size_t bytes) {
+  if (bytes > 65536)
+    HIPX(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes)));
 }
 
 namespace {

@@ -26,7 +26,6 @@ namespace {
 
 constexpr int kT = 256;
 constexpr double kSingularRowsum = 1e-10;  // s_i <= this * max A_ii counts as zero
-constexpr int kLdsDoubles = 6144;
 
 __global__ void k_rowsum_diag(int n, const int* rp, const int* ci, const double* av, double* s,
                               double* dmax_part) {
@@ -160,8 +159,9 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
   int K = blockIdx.x;
   int beg = ptr[K], n = ptr[K + 1] - beg;
   int b = band[K], w = b + 1;
-  int64_t bsz = static_cast<int64_t>(n) * w;
-  double* B = bsz <= lds_elems ? lds : band_glob + band_off[K];
+  const int64_t bsz = static_cast<int64_t>(n) * w;
+  const int mode = band_mode(n, b, lds_elems);
+  double* B = mode == 0 ? lds : band_glob + band_off[K];
   double* X = xs + beg;
   const bool pin = singular[K] != 0;
   const int lv = pin ? local[vertex[K]] : -1;
@@ -193,7 +193,7 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
     X[l] = rhs;
   }
   __syncthreads();
-  bool bad = band_ldlt_solve<double>(B, n, b, X, 1);
+  bool bad = band_ldlt_solve<double, double>(mode, B, n, b, X, 1, lds);
   for (int l = threadIdx.x; l < n; l += blockDim.x) p2[cells[beg + l]] = X[l];
   if (bad && threadIdx.x == 0) atomicOr(err, 1);
 }
@@ -295,17 +295,21 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   // ---- Neumann problems per primal block ----
   std::vector<int64_t> off(nc, 0);
   int64_t total = 0, lds_need = 0;
+  const int64_t lds_cap = lds_budget(h) / static_cast<int64_t>(sizeof(double));
   for (int K = 0; K < nc; ++K) {
-    int64_t sz = static_cast<int64_t>(hp[K + 1] - hp[K]) * (hb[K] + 1);
+    const int nk = hp[K + 1] - hp[K];
+    const int mode = band_mode(nk, hb[K], lds_cap);
+    FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "primal block bandwidth too large for LDS");
     off[K] = total;
-    if (sz <= kLdsDoubles) lds_need = std::max(lds_need, sz);
-    else total += sz;
+    if (mode != 0) total += static_cast<int64_t>(nk) * (hb[K] + 1);
+    lds_need = std::max(lds_need, band_lds_elems(mode, nk, hb[K]));
   }
   DBuf<int64_t> d_off(A, nc);
   HIPX(hipMemcpyAsync(d_off, off.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
   DBuf<double> scratch(A, std::max<int64_t>(total, 1));
   DBuf<int> err(A, 1);
   HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+  allow_lds(reinterpret_cast<const void*>(&k_neumann), lds_need * sizeof(double));
   LAUNCH(h, "flux_neumann", k_neumann, nc, kT, lds_need * sizeof(double), h->fv_ptr.get(),
          h->fv_order.get(), h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(),
          h->vertex.get(), band.get(), singular.get(), d_off.get(), scratch.get(),

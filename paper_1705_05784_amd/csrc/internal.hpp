@@ -166,6 +166,7 @@ struct Handle {
   DBuf<int> ilu_ticket;  // work tickets of the two sweeps
   DBuf<int> sweep_err;   // set when a bounded wait in a sweep gives up
   unsigned long long wait_ticks = 0;  // bound of one wait, device wall-clock ticks
+  int64_t lds_bytes = 0;              // dynamic LDS budget per workgroup
 
   // finite-volume stage (built lazily by fams_reconstruct_flux)
   bool fv_ready = false;
@@ -183,6 +184,11 @@ struct Handle {
 
   fams_setup_info_t info{};
 };
+
+// dynamic LDS budget of one workgroup on this device (bytes, <= 160 KiB), and
+// raising a kernel's dynamic LDS limit to `bytes` (api.hip)
+int64_t lds_budget(Handle* h);
+void allow_lds(const void* kernel, size_t bytes);
 
 // ---- launchers implemented in the .hip files --------------------------------
 // prims.hip (rocPRIM)

@@ -21,6 +21,8 @@
 // sums in CSR order), so repeated setups are bitwise identical.
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 #include <type_traits>
 
@@ -34,7 +36,6 @@ enum : int8_t { C_NONE = 0, C_KEPT = 1, C_LUMPED = 2, C_RHS = 3 };
 
 constexpr int kThreads = 256;
 constexpr int kMaxCols = 2048;      // coarse columns per block (RHS count)
-constexpr int kLdsBandDoubles = 6144;  // band kept in LDS up to 48 KiB
 
 enum ErrBits : int {
   E_VERTEX_RANGE = 1, E_VERTEX_CLASS = 2, E_VERTEX_DUP = 4, E_V_NOT_LISTED = 8,
@@ -243,8 +244,8 @@ __device__ void block_bitonic_sort(int* a, int cnt) {
   }
 }
 
-// Local order of a block: breadth-first levels from its lowest cell, cells of
-// one level by ascending natural position.  Irregular blocks (fracture
+// Local order of a block: breadth-first levels from a pseudo-peripheral cell,
+// cells of one level by ascending natural position.  Irregular blocks (fracture
 // regions, merged Coupled-AMS blocks) get a bandwidth tens of times smaller
 // than in ascending-index order; structured dual blocks keep their natural
 // order, which is narrower for them.  The order used is the narrower one.
@@ -254,7 +255,7 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, con
               int* local_idx) {
   __shared__ int lvl[kOrderMax];
   __shared__ int key[8192];
-  __shared__ int s_changed, s_bnat, s_bbfs;
+  __shared__ int s_changed, s_bnat, s_bbfs, s_start;
   int K = blockIdx.x;
   int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
   if (n <= 2 || n > kOrderMax) return;
@@ -268,29 +269,48 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, con
     int i = cells[beg + l];
     for (int p = rp[i]; p < rp[i + 1]; ++p)
       if (ecls[p] == C_KEPT) bnat = max(bnat, abs(local_idx[ci[p]] - l));
-    lvl[l] = l == 0 ? 0 : -1;
   }
   atomicMax(&s_bnat, bnat);
-  __syncthreads();
-  for (int d = 0; d < n; ++d) {
-    if (threadIdx.x == 0) s_changed = 0;
+  // Two breadth-first passes: the second starts from the lowest cell of the
+  // first pass's last level (a pseudo-peripheral cell), which narrows the
+  // levels of elongated blocks.
+  int start = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int l = threadIdx.x; l < n; l += blockDim.x) lvl[l] = l == start ? 0 : -1;
     __syncthreads();
-    for (int l = threadIdx.x; l < n; l += blockDim.x) {
-      if (lvl[l] != d) continue;
-      int i = cells[beg + l];
-      for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        if (ecls[p] != C_KEPT) continue;
-        int lj = local_idx[ci[p]];
-        if (lvl[lj] < 0) {
-          lvl[lj] = d + 1;
-          s_changed = 1;
+    int last = 0;
+    for (int d = 0; d < n; ++d) {
+      if (threadIdx.x == 0) s_changed = 0;
+      __syncthreads();
+      for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        if (lvl[l] != d) continue;
+        int i = cells[beg + l];
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+          if (ecls[p] != C_KEPT) continue;
+          int lj = local_idx[ci[p]];
+          if (lvl[lj] < 0) {
+            lvl[lj] = d + 1;
+            s_changed = 1;
+          }
         }
       }
+      __syncthreads();
+      const int changed = s_changed;
+      __syncthreads();  // every thread has read the flag before it is reset
+      if (!changed) {
+        last = d;
+        break;
+      }
     }
-    __syncthreads();
-    const int changed = s_changed;
-    __syncthreads();  // every thread has read the flag before it is reset
-    if (!changed) break;
+    if (pass == 0) {
+      if (threadIdx.x == 0) s_start = n;
+      __syncthreads();
+      for (int l = threadIdx.x; l < n; l += blockDim.x)
+        if (lvl[l] == last) atomicMin(&s_start, l);
+      __syncthreads();
+      start = s_start;
+      __syncthreads();
+    }
   }
   for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = (lvl[l] << 13) | l;
   __syncthreads();
@@ -464,8 +484,10 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
               const int* coarse_of, const int* comp_of, const int* local_idx,
               const int64_t* col_ptr, const int* cols, const int* ncols, const int* band,
               const int64_t* pval_off, TS* pvals, const int64_t* work_off, TC* band_glob,
-              TC* xwork, int lds_elems, int* err, int* bad_block) {
+              TC* xwork, int lds_elems, int* err, int* bad_block, unsigned long long* timing) {
   extern __shared__ double lds_d[];
+  unsigned long long* tk = timing ? timing + 8 * static_cast<int64_t>(blockIdx.x) : nullptr;
+  if (tk && threadIdx.x == 0) tk[0] = wall_clock64();
   int slot = blockIdx.x;
   int K = list ? list[slot] : c0 + slot;
   int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
@@ -475,48 +497,66 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
   TC* X;
   if constexpr (std::is_same<TS, TC>::value) X = xwork ? xwork + work_off[2 * slot + 1] : pvals + pval_off[K];
   else X = xwork + work_off[2 * slot + 1];
-  int64_t bsz = static_cast<int64_t>(n) * w;
-  TC* B = (bsz <= lds_elems) ? reinterpret_cast<TC*>(lds_d) : band_glob + work_off[2 * slot];
+  const int64_t bsz = static_cast<int64_t>(n) * w;
+  const int mode = band_mode(n, b, lds_elems);
+  TC* lds = reinterpret_cast<TC*>(lds_d);
+  TC* B = mode == 0 ? lds : band_glob + work_off[2 * slot];
 
   for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = TC(0);
   __syncthreads();
-  // assemble: one thread per block row, entries in CSR order
+  for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x) X[t] = TC(0);
+  __syncthreads();
+  // assemble the band: one thread per block row, entries in CSR order
   for (int l = threadIdx.x; l < n; l += blockDim.x) {
     int i = cells[beg + l];
-    TC* xl = X + static_cast<int64_t>(l) * nck;
-    for (int c = 0; c < nck; ++c) xl[c] = TC(0);
     double dg = 0.0;
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
       int j = ci[p];
-      double a = av[p];
       int8_t c = ecls[p];
-      if (j == i) {
-        dg += a;
-      } else if (c == C_LUMPED) {
-        dg += a;
+      if (j == i || c == C_LUMPED) {
+        dg += av[p];
       } else if (c == C_KEPT) {
         int lj = local_idx[j];
-        if (lj < l) B[static_cast<int64_t>(l) * w + b - (l - lj)] = static_cast<TC>(a);
-      } else if (c == C_RHS) {
+        if (lj < l) B[static_cast<int64_t>(l) * w + b - (l - lj)] = static_cast<TC>(av[p]);
+      }
+    }
+    B[static_cast<int64_t>(l) * w + b] = static_cast<TC>(dg);
+  }
+  // right-hand sides (-A_ij P_j for higher-rank j): one wave per block row,
+  // lanes over the columns of P_j
+  {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+    for (int l = wave; l < n; l += nwaves) {
+      int i = cells[beg + l];
+      TC* xl = X + static_cast<int64_t>(l) * nck;
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (ecls[p] != C_RHS) continue;
+        int j = ci[p];
+        TC a = static_cast<TC>(av[p]);
         if (wb[j] == 3) {
-          int pos = bsearch_i32(kcols, nck, coarse_of[j]);
-          xl[pos] -= static_cast<TC>(a);
+          if (lane == 0) xl[bsearch_i32(kcols, nck, coarse_of[j])] -= a;
         } else {
           int cj = comp_of[j];
           int ncj = ncols[cj];
           const TS* src = pvals + pval_off[cj] + static_cast<int64_t>(local_idx[j]) * ncj;
           const int* cc = cols + col_ptr[cj];
-          for (int t = 0; t < ncj; ++t) {
-            int pos = bsearch_i32(kcols, nck, cc[t]);
-            xl[pos] -= static_cast<TC>(a) * static_cast<TC>(src[t]);
-          }
+          for (int t = lane; t < ncj; t += 64)
+            xl[bsearch_i32(kcols, nck, cc[t])] -= a * static_cast<TC>(src[t]);
         }
+        // the next entry may update the same positions from other lanes
+        __threadfence_block();
       }
     }
-    B[static_cast<int64_t>(l) * w + b] = static_cast<TC>(dg);
   }
   __syncthreads();
-  bool bad = band_ldlt_solve<TC>(B, n, b, X, nck);
+  __syncthreads();
+  if (tk && threadIdx.x == 0) {
+    tk[1] = wall_clock64();
+    tk[5] = (static_cast<unsigned long long>(n) << 32) | static_cast<unsigned>(b);
+    tk[6] = (static_cast<unsigned long long>(nck) << 32) |
+            static_cast<unsigned>(mode);
+  }
+  bool bad = band_ldlt_solve<TC, TC>(mode, B, n, b, X, nck, lds, tk ? tk + 2 : nullptr);
   if (!std::is_same<TS, TC>::value || xwork) {
     TS* out = pvals + pval_off[K];
     for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x)
@@ -728,6 +768,31 @@ void coupled_groups(Handle* h, const int8_t* wb, const int* base, int* group) {
   HIPX(hipStreamSynchronize(h->stream));
 }
 
+// FAMS_BLOCK_TIMING=1: per-block phase durations of one launch to stderr
+// (wall-clock ticks of the device's constant-rate counter).
+void print_block_timing(const unsigned long long* dev, int nb, int first) {
+  std::vector<unsigned long long> t(8 * static_cast<size_t>(nb));
+  HIPX(hipMemcpy(t.data(), dev, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  double sum[4] = {0, 0, 0, 0};
+  std::vector<std::pair<double, int>> tot;
+  for (int k = 0; k < nb; ++k) {
+    const unsigned long long* r = &t[8 * static_cast<size_t>(k)];
+    double ph[4] = {double(r[1] - r[0]), double(r[2] - r[1]), double(r[3] - r[2]),
+                    double(r[4] - r[3])};
+    for (int q = 0; q < 4; ++q) sum[q] += ph[q];
+    tot.emplace_back(double(r[4] - r[0]), k);
+  }
+  std::sort(tot.begin(), tot.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  std::fprintf(stderr, "[blocks from %d] %d blocks; sum ticks assemble %.3g factor %.3g normalise %.3g substitute %.3g\n",
+               first, nb, sum[0], sum[1], sum[2], sum[3]);
+  for (int q = 0; q < std::min(nb, 6); ++q) {
+    const unsigned long long* r = &t[8 * static_cast<size_t>(tot[q].second)];
+    std::fprintf(stderr, "   n %llu b %llu nck %llu mode %llu : assemble %llu factor %llu normalise %llu substitute %llu\n",
+                 r[5] >> 32, r[5] & 0xffffffffull, r[6] >> 32, r[6] & 0xffffffffull, r[1] - r[0],
+                 r[2] - r[1], r[3] - r[2], r[4] - r[3]);
+  }
+}
+
 // Launch the local solves of blocks `blocks` (all of one rank level).
 template <class TS, class TC>
 void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, const int* comp_ptr,
@@ -741,14 +806,15 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
   const bool separate_x = !std::is_same<TS, TC>::value;
   std::vector<int64_t> off(2 * nb, 0);
   int64_t band_total = 0, x_total = 0, lds_need = 0;
-  const int lds_cap = kLdsBandDoubles * 8 / static_cast<int>(sizeof(TC));
+  const int64_t lds_cap = lds_budget(h) / static_cast<int64_t>(sizeof(TC));
   for (int k = 0; k < nb; ++k) {
     int K = blocks[k];
     int64_t nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
-    int64_t sz = nk * (h_band[K] + 1);
+    const int mode = band_mode(static_cast<int>(nk), h_band[K], lds_cap);
+    FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "local block bandwidth too large for LDS");
     off[2 * k] = band_total;
-    if (sz <= lds_cap) lds_need = std::max(lds_need, sz);
-    else band_total += sz;
+    if (mode != 0) band_total += nk * (h_band[K] + 1);  // band in global memory
+    lds_need = std::max(lds_need, band_lds_elems(mode, static_cast<int>(nk), h_band[K]));
     off[2 * k + 1] = x_total;
     if (separate_x) x_total += nk * h_ncols[K];
   }
@@ -765,12 +831,17 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
   DBuf<TC> xw;
   if (separate_x) xw.reset(&h->alloc, std::max<int64_t>(x_total, 1));
   int lds_elems = static_cast<int>(lds_need);
+  allow_lds(reinterpret_cast<const void*>(&k_local_solve<TS, TC>), lds_elems * sizeof(TC));
+  static const bool timing_on = std::getenv("FAMS_BLOCK_TIMING") != nullptr;
+  DBuf<unsigned long long> timing;
+  if (timing_on) timing.reset(&h->alloc, 8 * static_cast<size_t>(nb));
   LAUNCH(h, "local_solve", (k_local_solve<TS, TC>), nb, kThreads, lds_elems * sizeof(TC),
          static_cast<const int*>(d_list.get()), blocks[0], comp_ptr, cells, h->rp.get(),
          h->ci.get(), h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols,
          ncols, band, pval_off, pvals, d_off.get(), scratch.get(), xw.get(), lds_elems, err,
-         bad_block);
+         bad_block, timing.get());
   HIPX(hipStreamSynchronize(h->stream));  // scratch is freed on return
+  if (timing_on) print_block_timing(timing.get(), nb, blocks[0]);
 }
 
 }  // namespace

@@ -27,26 +27,35 @@ namespace {
 constexpr int kT = 256;
 constexpr int kRedBlocks = 512;
 
-template <class TV, class TX, class TY>
-__global__ void k_spmv(int n, const int* rp, const int* ci, const TV* val, const TX* x, TY* y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// y = b - A x (b may be null: y = -A x); 8 lanes per row, so a wavefront
+// reads 8 consecutive rows' entries as one contiguous stretch; fixed-order
+// shuffle reduction (deterministic).
+constexpr int kSub = 8;
+template <class TV, class TX, class TB, class TY>
+__global__ void __launch_bounds__(256)
+k_resid(int n, const int* rp, const int* ci, const TV* val, const TX* x, const TB* b, TY* y) {
+  const int i = blockIdx.x * (blockDim.x / kSub) + threadIdx.x / kSub;
+  const int l = threadIdx.x % kSub;
   double s = 0.0;
-  for (int p = rp[i]; p < rp[i + 1]; ++p)
-    s += static_cast<double>(val[p]) * static_cast<double>(x[ci[p]]);
-  y[i] = static_cast<TY>(s);
+  if (i < n)
+    for (int p = rp[i] + l; p < rp[i + 1]; p += kSub)
+      s += static_cast<double>(val[p]) * static_cast<double>(x[ci[p]]);
+  for (int o = kSub / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kSub);
+  if (i < n && l == 0) y[i] = static_cast<TY>((b ? static_cast<double>(b[i]) : 0.0) - s);
 }
 
-// y = b - A x
-template <class TV, class TX, class TB, class TY>
-__global__ void k_resid(int n, const int* rp, const int* ci, const TV* val, const TX* x,
-                        const TB* b, TY* y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = static_cast<double>(b[i]);
-  for (int p = rp[i]; p < rp[i + 1]; ++p)
-    s -= static_cast<double>(val[p]) * static_cast<double>(x[ci[p]]);
-  y[i] = static_cast<TY>(s);
+// y = M x with 8 lanes per row (see k_resid)
+template <class TV, class TX, class TY>
+__global__ void __launch_bounds__(256)
+k_spmv8(int n, const int* rp, const int* ci, const TV* val, const TX* x, TY* y) {
+  const int i = blockIdx.x * (blockDim.x / kSub) + threadIdx.x / kSub;
+  const int l = threadIdx.x % kSub;
+  double s = 0.0;
+  if (i < n)
+    for (int p = rp[i] + l; p < rp[i + 1]; p += kSub)
+      s += static_cast<double>(val[p]) * static_cast<double>(x[ci[p]]);
+  for (int o = kSub / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kSub);
+  if (i < n && l == 0) y[i] = static_cast<TY>(s);
 }
 
 // y[r] = sum_k M[r,k] x[k] for short fat rows (R = P^T has ~N/n_c entries per
@@ -87,14 +96,15 @@ __global__ void k_dot_part(int64_t n, const double* a, const double* b, double* 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// out[k] (+)= sum over blocks of part[b * stride + k], k < nv, fixed order
-__global__ void k_reduce(int nblk, int nv, int stride, const double* part, double* out,
-                         int accumulate) {
-  int k = threadIdx.x;
-  if (k >= nv) return;
+// out[k] (+)= sum over blocks of part[b * stride + k]: one workgroup per k,
+// strided partial sums then a fixed tree -- deterministic
+__global__ void __launch_bounds__(256)
+k_reduce(int nblk, int nv, int stride, const double* part, double* out, int accumulate) {
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[static_cast<int64_t>(b) * stride + k];
-  out[k] = accumulate ? out[k] + s : s;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[static_cast<int64_t>(b) * stride + k];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[k] = accumulate ? out[k] + s : s;
 }
 
 // part[b * stride + k] = sum over this block's rows of V_k . w, k < nv
@@ -260,7 +270,7 @@ Work work_of(Handle* h) {
 void dot_into(Handle* h, const double* a, const double* b, int64_t n, double* part, double* dst) {
   int nb = std::min<int64_t>(kRedBlocks, blocks_for(n, kT));
   LAUNCH(h, "dot", k_dot_part, nb, kT, 0, n, a, b, part);
-  LAUNCH(h, "reduce", k_reduce, 1, 64, 0, nb, 1, 1, part, dst, 0);
+  LAUNCH(h, "reduce", k_reduce, 1, 256, 0, nb, 1, 1, part, dst, 0);
 }
 
 double read_d(Handle* h, const double* d) {
@@ -277,7 +287,7 @@ double norm_host(Handle* h, const double* a, int64_t n, double* part, double* sc
 
 template <class TV, class TX, class TB, class TY>
 void resid(Handle* h, const TV* val, const TX* x, const TB* b, TY* y) {
-  LAUNCH(h, "spmv_resid", (k_resid<TV, TX, TB, TY>), blocks_for(h->n, kT), kT, 0, h->n,
+  LAUNCH(h, "spmv_resid", (k_resid<TV, TX, TB, TY>), blocks_for(h->n, kT / kSub), kT, 0, h->n,
          h->rp.get(), h->ci.get(), val, x, b, y);
 }
 
@@ -317,8 +327,8 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
   LAUNCH(h, "restrict", (k_spmv_wave<T, T>), blocks_for(nc, 4), 256, 0, nc, h->r_rp.get(),
          h->r_ci.get(), rv, rT, k.rc);
   coarse_apply(h, h->Ainv.get(), nc, k.rc, k.xc, h->gpart.get());
-  LAUNCH(h, "prolong", (k_spmv<T, double, T>), blocks_for(n, kT), kT, 0, n, h->p_rp.get(),
-         h->p_ci.get(), pv, k.xc, d1);
+  LAUNCH(h, "prolong", (k_spmv8<T, double, T>), blocks_for(n, kT / kSub), kT, 0, n,
+         h->p_rp.get(), h->p_ci.get(), pv, k.xc, d1);
   if (h->smoother) {
     resid<T, T, T, T>(h, av, d1, rT, rh);
     ilu_apply<T>(h, lu, rh, x, ysc);
@@ -392,15 +402,15 @@ fams_status_t gmres(Handle* h, const Work& k, const double* q, double* p,
       double* vj = k.V + j * n;
       double* zj = k.Z + j * n;
       stage_any(h, k, vj, zj);
-      LAUNCH(h, "spmv", (k_spmv<double, double, double>), blocks_for(n, kT), kT, 0, (int)n,
-             h->rp.get(), h->ci.get(), h->val.get(), zj, k.w);
+      LAUNCH(h, "spmv", (k_spmv8<double, double, double>), blocks_for(n, kT / kSub), kT, 0,
+             (int)n, h->rp.get(), h->ci.get(), h->val.get(), zj, k.w);
       // CGS2 against V_0..V_j: h = V^T w, w -= V h; c = V^T w, w -= V c; h += c
       LAUNCH(h, "mdot", k_mdot_part, nb, kT, 0, n, j + 1, k.V, n, k.w, k.part, m + 2);
-      LAUNCH(h, "reduce", k_reduce, 1, 64, 0, nb, j + 1, m + 2, k.part, k.gs.hcol, 0);
+      LAUNCH(h, "reduce", k_reduce, j + 1, 256, 0, nb, j + 1, m + 2, k.part, k.gs.hcol, 0);
       LAUNCH(h, "maxpy", k_maxpy, blocks_for(n, kT), kT, 0, n, j + 1, k.V, n, k.gs.hcol, -1.0,
              k.w);
       LAUNCH(h, "mdot", k_mdot_part, nb, kT, 0, n, j + 1, k.V, n, k.w, k.part, m + 2);
-      LAUNCH(h, "reduce", k_reduce, 1, 64, 0, nb, j + 1, m + 2, k.part, k.gs.y, 0);
+      LAUNCH(h, "reduce", k_reduce, j + 1, 256, 0, nb, j + 1, m + 2, k.part, k.gs.y, 0);
       LAUNCH(h, "maxpy", k_maxpy, blocks_for(n, kT), kT, 0, n, j + 1, k.V, n, k.gs.y, -1.0,
              k.w);
       LAUNCH(h, "vadd", k_vadd, 1, 64, 0, j + 1, k.gs.y, k.gs.hcol);

@@ -140,3 +140,30 @@ def test_flux_reconstruction(name, variant):
     assert imb <= 1e-10
     assert np.abs(pfv.cpu().numpy() - p1).max() <= 1e-9 * np.abs(p1).max()
     assert np.abs(fl.cpu().numpy() - fr).max() <= 1e-8 * np.abs(fr).max()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("name,lds_limit", [("3d", 24576), ("3d", 49152), ("cfg2s", 65536)])
+def test_global_band_modes(name, lds_limit, variant, monkeypatch):
+    """A lowered LDS budget moves the local blocks (basis and Neumann solves)
+    to the blocked global-memory factorisations; P, the FV pressure and the
+    fluxes still match the oracle."""
+    from paper_1705_05784_amd import fams
+    from oracle import flux as oflux
+    s, gpu0, ora = case(name, variant)
+    spec = small_case(name)[1]
+    wb, pr, vx, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    monkeypatch.setenv("FAMS_LDS_LIMIT", str(lds_limit))
+    say(f"[case] {name} variant {variant} lds_limit {lds_limit}")
+    gpu = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=variant)
+    rp, ci, va = gpu.prolongation()
+    assert np.array_equal(rp, ora.P.indptr)
+    assert np.array_equal(ci, ora.P.indices)
+    assert np.abs(va - ora.P.data).max() <= 1e-10
+    p, _ = gpu.solve(torch.from_numpy(s.q), rtol=1e-6)
+    fl, pfv, imb = gpu.reconstruct_flux(torch.from_numpy(s.q), p)
+    og = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    fr, p1, p2, imr = oflux.reconstruct_flux(ora.A, ora.P, og[1], og[2], s.q, p.cpu().numpy())
+    assert imb <= 1e-10
+    assert np.abs(pfv.cpu().numpy() - p1).max() <= 1e-9 * np.abs(p1).max()
+    assert np.abs(fl.cpu().numpy() - fr).max() <= 1e-8 * np.abs(fr).max()
