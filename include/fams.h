@@ -22,7 +22,9 @@
  *     (NULL = the default stream); calls that return host scalars synchronise
  *     that stream before returning.
  *   - A handle is used by one host thread / stream at a time; distinct handles
- *     are independent and may run concurrently on different streams.
+ *     are independent.  Calls from several host threads of one process at
+ *     once are not supported; concurrent work on one GPU comes from one
+ *     process per concurrent stream of requests (as the serving loop does).
  *
  * Environment
  *   - FAMS_LDS_LIMIT=<bytes> lowers the LDS budget of the local block solves

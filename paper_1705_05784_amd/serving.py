@@ -1,0 +1,360 @@
+"""Serving form: continuous batching of F-AMS setup + solve requests.
+
+Requests arrive over time (each: a fine system with its coarse grids, a basis
+variant and 1..16 right-hand sides).  A dispatcher admits them first come,
+first served, as soon as a slot is free and the HBM reservation of the
+requests in flight plus the new request's footprint (fams_footprint plus its
+input and vector buffers) stays within the budget.  Each slot is a worker
+process with its own HIP context on the same GPU (ProcessRunner): it runs
+fams_setup, reuses that setup for every right-hand side (fams_solve,
+optionally fams_reconstruct_flux), frees it and reports back, and the
+dispatcher releases the reservation.  Kernels of different slots overlap on
+the device; every kernel reduces in a fixed order, so a request's result
+does not depend on what runs beside it.
+
+Several host threads calling the library at once inside one process are not
+used: such a run once ended in a host crash whose cause was not found, so
+the in-process runner (GpuRunner) serves one slot only.
+
+The execution of one request is a replaceable callable (`runner`), so the
+admission logic is testable without a device.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class ServedResult:
+    rid: int
+    status: int = 0
+    error: str = ""
+    iterations: list = field(default_factory=list)
+    rel_residual: list = field(default_factory=list)
+    pressures: np.ndarray | None = None   # [nrhs, n] when kept
+    imbalance: list = field(default_factory=list)
+    footprint: int = 0
+    t_arrival: float = 0.0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    setup_ms: float = 0.0
+    slot: int = -1
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+def prepare(requests, coarse=(10, 10, 10), d_min=8, r_z=8):
+    """Build each distinct system's coarse grids once (host helpers) and keep
+    them, with the coarse size, in the request's meta; grids are inputs of
+    fams_setup, like the matrix."""
+    from . import fams
+    cache = {}
+    for r in requests:
+        key = id(r.system)
+        if key not in cache:
+            wb, pr, vx, _ = fams.full_grid(r.system, coarse, d_min, r_z)
+            cache[key] = (wb, pr, vx)
+        r.meta["grid"] = cache[key]
+        r.meta["n_coarse"] = len(cache[key][2])
+    return requests
+
+
+def request_footprint(req, precision: int, restart: int = 30) -> int:
+    """Device bytes a request may hold: the library's setup + workspace bound,
+    the borrowed inputs and the right-hand-side / pressure buffers."""
+    from . import fams
+    s = req.system
+    nc = int(req.meta["n_coarse"])
+    lib_bytes = fams.footprint(s.n, s.nnz, nc, precision, restart)
+    inputs = 8 * (s.n + 1) + 12 * s.nnz + 13 * s.n + 8 * nc
+    vectors = 2 * 8 * s.n * req.rhs.shape[0] + 2 * 8 * s.nnz
+    return int(lib_bytes + inputs + vectors)
+
+
+def _execute(system, grid, variant, rhs, precision, alpha, rtol, restart, flux, keep) -> dict:
+    """Run one request on the current device and stream: one setup, reused
+    for every right-hand side."""
+    import torch
+
+    from . import fams
+    s = system
+    out = dict(status=0, error="", iterations=[], rel_residual=[], imbalance=[], pressures=None,
+               setup_ms=0.0)
+    t0 = time.perf_counter()
+    solver = fams.Solver(s["row_ptr"], s["col"], s["val"], s["n_matrix"], *grid, variant=variant,
+                         precision=precision, alpha=alpha)
+    try:
+        out["setup_ms"] = (time.perf_counter() - t0) * 1e3
+        q = torch.from_numpy(np.ascontiguousarray(rhs)).to("cuda")
+        ps = []
+        for k in range(q.shape[0]):
+            p, info = solver.solve(q[k], outer=fams.GMRES, restart=restart, rtol=rtol)
+            out["iterations"].append(info[0]["iterations"])
+            out["rel_residual"].append(info[0]["rel_residual"])
+            out["status"] = max(out["status"], info[0]["status"])
+            if flux:
+                _, _, imb = solver.reconstruct_flux(q[k], p)
+                out["imbalance"].append(imb)
+            if keep:
+                ps.append(p)
+        if keep:
+            out["pressures"] = torch.stack(ps).cpu().numpy()
+        torch.cuda.current_stream().synchronize()
+    finally:
+        solver.close()
+    return out
+
+
+def _system_arrays(req):
+    s = req.system
+    return dict(row_ptr=s.row_ptr, col=s.col, val=s.val, n_matrix=s.n_matrix)
+
+
+def _fill(res: ServedResult, out: dict):
+    res.status = out["status"]
+    res.error = out["error"]
+    res.iterations = out["iterations"]
+    res.rel_residual = out["rel_residual"]
+    res.imbalance = out["imbalance"]
+    res.pressures = out["pressures"]
+    res.setup_ms = out["setup_ms"]
+
+
+class GpuRunner:
+    """Executes a request in this process on the current device and stream
+    (one slot only)."""
+
+    in_process = True
+
+    def __init__(self, precision, alpha=1e-2, rtol=1e-6, restart=30, flux=False,
+                 keep_pressures=False):
+        self.args = (precision, alpha, rtol, restart, flux, keep_pressures)
+
+    def __call__(self, req, res: ServedResult):
+        _fill(res, _execute(_system_arrays(req), req.meta["grid"], req.variant, req.rhs, *self.args))
+
+
+def _worker_main(conn, device, args):
+    """Slot process: receives systems once, then runs requests on them."""
+    import torch
+    torch.cuda.set_device(device)
+    from . import fams
+    fams.lib()
+    systems = {}
+    conn.send(("ready", None))
+    while True:
+        msg = conn.recv()
+        if msg[0] == "stop":
+            break
+        if msg[0] == "system":
+            systems[msg[1]] = msg[2]
+            continue
+        _, key, variant, rhs = msg
+        sysd, grid = systems[key]
+        try:
+            out = _execute(sysd, grid, variant, rhs, *args)
+        except Exception as e:  # reported to the dispatcher; the slot goes on
+            out = dict(status=-1, error=f"{type(e).__name__}: {e}", iterations=[],
+                       rel_residual=[], imbalance=[], pressures=None, setup_ms=0.0)
+        conn.send(("done", out))
+    conn.close()
+
+
+class ProcessRunner:
+    """One worker process per slot, all on `device`.  Slot k of the server
+    runs its requests in process k; each process receives a system's arrays
+    the first time one of its requests uses it."""
+
+    def __init__(self, slots, precision, alpha=1e-2, rtol=1e-6, restart=30, flux=False,
+                 keep_pressures=False, device=0, timeout=600.0):
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        self.timeout = timeout
+        self.conns, self.procs, self.sent = [], [], []
+        args = (precision, alpha, rtol, restart, flux, keep_pressures)
+        try:
+            for _ in range(slots):
+                a, b = ctx.Pipe()
+                p = ctx.Process(target=_worker_main, args=(b, device, args), daemon=True)
+                p.start()
+                b.close()
+                self.conns.append(a)
+                self.procs.append(p)
+                self.sent.append(set())
+            for c in self.conns:
+                if not c.poll(timeout):
+                    raise TimeoutError("serving slot process did not start")
+                c.recv()
+        except BaseException:
+            self.close()
+            raise
+
+    @property
+    def slots(self):
+        return len(self.conns)
+
+    def __call__(self, req, res: ServedResult):
+        c = self.conns[res.slot]
+        key = id(req.system)
+        if key not in self.sent[res.slot]:
+            c.send(("system", key, (_system_arrays(req), req.meta["grid"])))
+            self.sent[res.slot].add(key)
+        c.send(("run", key, req.variant, req.rhs))
+        if not c.poll(self.timeout):
+            raise TimeoutError(f"request {req.rid} did not finish in {self.timeout} s")
+        _, out = c.recv()
+        _fill(res, out)
+
+    def close(self):
+        for c in self.conns:
+            try:
+                c.send(("stop",))
+            except Exception:
+                pass
+        for p in self.procs:
+            p.join(timeout=30)
+            if p.is_alive():
+                p.terminate()
+                p.join(timeout=10)
+        self.conns, self.procs = [], []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Continuous-batching request loop.
+
+    slots: requests in flight at most; hbm_budget: bytes the requests in
+    flight may reserve together (default: 90% of the device's free memory
+    when run() starts).
+    """
+
+    def __init__(self, runner, slots: int = 8, hbm_budget: int | None = None,
+                 footprint=None):
+        self.runner = runner
+        self.slots = int(slots)
+        self.hbm_budget = hbm_budget
+        self.footprint = footprint
+        self.peak_inflight = 0
+        self.peak_reserved = 0
+
+    def run(self, requests, realtime: bool = True) -> list[ServedResult]:
+        if getattr(self.runner, "in_process", False) and self.slots > 1:
+            raise ValueError("the in-process runner serves one slot; use ProcessRunner")
+        if hasattr(self.runner, "slots") and self.runner.slots < self.slots:
+            raise ValueError("runner has fewer slot processes than the server has slots")
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        budget = self.hbm_budget
+        if budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            budget = int(0.9 * free)
+        fp = self.footprint or (lambda r: 0)
+        results = {r.rid: ServedResult(r.rid, t_arrival=r.arrival) for r in reqs}
+        cv = threading.Condition()
+        jobs: deque = deque()
+        state = dict(reserved=0, inflight=0, done=0, stop=False)
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        def worker(slot):
+            while True:
+                with cv:
+                    while not jobs and not state["stop"]:
+                        cv.wait()
+                    if not jobs:
+                        return
+                    req, need = jobs.popleft()
+                res = results[req.rid]
+                res.slot = slot
+                try:
+                    self.runner(req, res)
+                except Exception as e:  # a failed request reports, the server goes on
+                    res.status = -1
+                    res.error = f"{type(e).__name__}: {e}"
+                with cv:
+                    res.t_done = now()
+                    state["reserved"] -= need
+                    state["inflight"] -= 1
+                    state["done"] += 1
+                    cv.notify_all()
+
+        threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(self.slots)]
+        for t in threads:
+            t.start()
+        pending: deque = deque()
+        nxt = 0
+        arrive = (lambda r: r.arrival) if realtime else (lambda r: 0.0)
+        try:
+            with cv:
+                while state["done"] < len(reqs):
+                    t = now()
+                    while nxt < len(reqs) and arrive(reqs[nxt]) <= t:
+                        pending.append(reqs[nxt])
+                        if not realtime:
+                            results[reqs[nxt].rid].t_arrival = 0.0
+                        nxt += 1
+                    while pending and state["inflight"] < self.slots:
+                        r = pending[0]
+                        need = int(fp(r))
+                        res = results[r.rid]
+                        res.footprint = need
+                        if need > budget:           # can never fit: reject
+                            pending.popleft()
+                            res.status, res.error = -6, f"footprint {need} B exceeds budget {budget} B"
+                            res.t_admit = res.t_done = t
+                            state["done"] += 1
+                            continue
+                        if state["reserved"] + need > budget:
+                            break                    # first come, first served
+                        pending.popleft()
+                        res.t_admit = t
+                        state["reserved"] += need
+                        state["inflight"] += 1
+                        self.peak_inflight = max(self.peak_inflight, state["inflight"])
+                        self.peak_reserved = max(self.peak_reserved, state["reserved"])
+                        jobs.append((r, need))
+                        cv.notify_all()
+                    if state["done"] >= len(reqs):
+                        break
+                    wait = None
+                    if nxt < len(reqs):
+                        wait = max(0.0, arrive(reqs[nxt]) - now())
+                    cv.wait(wait if wait is None else max(wait, 1e-4))
+        finally:
+            with cv:
+                state["stop"] = True
+                cv.notify_all()
+            for t in threads:
+                t.join()
+        return [results[r.rid] for r in sorted(reqs, key=lambda r: r.rid)]
+
+
+def summarize(results, cells=None) -> dict:
+    """p50/p99 latency (s), solves/s over the makespan, cell-iterations/s."""
+    ok = [r for r in results if r.status >= 0]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    t_first = min(r.t_arrival for r in results) if results else 0.0
+    t_last = max(r.t_done for r in results) if results else 0.0
+    span = max(t_last - t_first, 1e-9)
+    solves = sum(len(r.iterations) for r in ok)
+    out = dict(requests=len(results), failed=len(results) - len(ok), solves=solves,
+               makespan_s=span, solves_per_s=solves / span,
+               p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)))
+    if cells is not None:
+        ci = sum(cells[r.rid] * sum(r.iterations) for r in ok)
+        out["cell_iterations_per_s"] = ci / span
+    return out
