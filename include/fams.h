@@ -144,6 +144,8 @@ typedef struct {
   int64_t ilu_levels_lower, ilu_levels_upper;
   double ms_setup;
   int64_t device_bytes;       /* device memory held by the handle */
+  double local_flops;         /* arithmetic of the banded local solves
+                                 (factorisation + substitution, all levels) */
 } fams_setup_info_t;
 
 /* ---- lifecycle -------------------------------------------------------- */

@@ -247,6 +247,9 @@ fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t p
   b += nnz * (4 + 8 + 8) + (n + 1) * 4 + n * (4 + 4 + 4);       // A, ILU, diag, primal
   b += 2 * zp * (4 + 8) + (n + n_coarse + 2) * 4;                // P and R
   b += 2.0 * 8 * n_coarse * n_coarse;                            // A_c and its inverse
+  b += 2.0 * 8 * n_coarse * n_coarse;                            // FV operator and inverse
+  b += 3.0 * zp * (4 + 8) + 8.0 * (n + 1);                       // A P
+  b += 48.0 * 8 * n;                                             // local solutions (setup)
   b += 8.0 * n * (6 + 2 * std::max(restart, 1) + 1);             // iteration vectors
   if (precision == FAMS_PREC_MIXED) b += nnz * 8.0 + 2 * zp * 4 + 16.0 * n;
   b *= 1.10;

@@ -10,6 +10,7 @@
 //
 // All dense matrices are column-major with leading dimension n.
 #include <algorithm>
+#include <climits>
 #include <vector>
 
 #include "internal.hpp"
@@ -47,6 +48,105 @@ k_rap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int* 
         __syncthreads();
       }
     }
+    for (int t = lane; t < j1 - j0; t += 64) out[static_cast<int64_t>(j0 + t) * nc + I] = acc[t];
+    __syncthreads();
+  }
+}
+
+// ---- A P, then A_c = R (A P) -------------------------------------------------
+// Row i of A P = sum_j A_ij P_j, accumulated in A's column order into an LDS
+// hash table of coarse columns (one wavefront per row, lanes over the
+// entries of P_j, which have distinct columns).  Each row of A P is built once
+// and reused by every coarse row whose restriction row contains i.
+constexpr int kApSlots = 1024;   // hash slots per row (at most half used)
+constexpr int kApWaves = 4;      // rows per 256-thread block
+constexpr int kApEmpty = INT_MIN;
+
+__device__ __forceinline__ int ap_slot(int* tab, int key, bool* full) {
+  unsigned hh = (static_cast<unsigned>(key) * 2654435761u) & (kApSlots - 1);
+  for (int probe = 0; probe < kApSlots; ++probe) {
+    const int prev = atomicCAS(&tab[hh], kApEmpty, key);
+    if (prev == kApEmpty || prev == key) return static_cast<int>(hh);
+    hh = (hh + 1) & (kApSlots - 1);
+  }
+  *full = true;
+  return -1;
+}
+
+// count (fill == false) or write (fill == true) the entries of rows of A P
+template <bool kFill>
+__global__ void __launch_bounds__(64 * kApWaves)
+k_ap(int n, const int* rp, const int* ci, const double* av, const int* p_rp, const int* p_ci,
+     const double* p_val, int64_t* cnt_or_ptr, int* ap_ci, double* ap_val, int* err) {
+  __shared__ int tab[kApWaves][kApSlots];
+  __shared__ double acc[kFill ? kApWaves : 1][kFill ? kApSlots : 1];
+  __shared__ int s_cnt[kApWaves];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = blockIdx.x * kApWaves + wave;
+  int* t = tab[wave];
+  for (int k = lane; k < kApSlots; k += 64) {
+    t[k] = kApEmpty;
+    if constexpr (kFill) acc[wave][k] = 0.0;
+  }
+  if (lane == 0) s_cnt[wave] = 0;
+  __syncthreads();
+  bool full = false;
+  if (i < n) {
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      const int j = ci[p];
+      const double a = av[p];
+      for (int q = p_rp[j] + lane; q < p_rp[j + 1]; q += 64) {
+        const int sl = ap_slot(t, p_ci[q], &full);
+        if constexpr (kFill) {
+          if (sl >= 0) acc[wave][sl] += a * p_val[q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (i < n) {
+    int used = 0;
+    for (int k = lane; k < kApSlots; k += 64) used += t[k] != kApEmpty;
+    for (int off = 32; off > 0; off >>= 1) used += __shfl_xor(used, off);
+    if (full || used > kApSlots / 2) {
+      if (lane == 0) atomicOr(err, 1);
+    } else if constexpr (!kFill) {
+      if (lane == 0) cnt_or_ptr[i] = used;
+    } else {
+      const int64_t base = cnt_or_ptr[i];
+      for (int k = lane; k < kApSlots; k += 64) {
+        if (t[k] != kApEmpty) {
+          const int o = atomicAdd(&s_cnt[wave], 1);
+          ap_ci[base + o] = t[k];
+          ap_val[base + o] = acc[wave][k];
+        }
+      }
+    }
+  }
+}
+
+// A_c rows: one wavefront per coarse row I, acc[J] += w_e (A P)_{i_e, J} over
+// the restriction row's entries e in order (one wavefront: its LDS accesses
+// are ordered, and the columns of one row of A P are distinct)
+__global__ void __launch_bounds__(64)
+k_rap_ap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int64_t* ap_rp,
+         const int* ap_ci, const double* ap_val, double* out, int jt) {
+  extern __shared__ double acc[];
+  const int I = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int j0 = 0; j0 < nc; j0 += jt) {
+    const int j1 = min(nc, j0 + jt);
+    for (int t = lane; t < j1 - j0; t += 64) acc[t] = 0.0;
+    __syncthreads();
+    for (int e = R_rp[I]; e < R_rp[I + 1]; ++e) {
+      const int i = R_ci[e];
+      const double w = R_val ? R_val[e] : 1.0;
+      for (int64_t q = ap_rp[i] + lane; q < ap_rp[i + 1]; q += 64) {
+        const int J = ap_ci[q];
+        if (J >= j0 && J < j1) acc[J - j0] += w * ap_val[q];
+      }
+    }
+    __syncthreads();
     for (int t = lane; t < j1 - j0; t += 64) out[static_cast<int64_t>(j0 + t) * nc + I] = acc[t];
     __syncthreads();
   }
@@ -114,6 +214,116 @@ k_panel(double* a, int n, int k0, int nb, int* ipiv, int* info) {
       cc[r] -= colj[r] * cc[j];
     }
     __syncthreads();
+  }
+}
+
+// Panel of nb <= 16 columns held in registers (rows [k0, n), at most 512*RT
+// of them; thread t owns rows t, t+512, ...).  Row interchanges are logical:
+// pos[] is each row's current position and at_pos[] its inverse, so a step
+// costs two barriers and no memory traffic; the rows are written back to
+// their final positions at the end.  Pivot choice (first maximal |a| in
+// position order) and every update are the same as in k_panel.
+constexpr int kRegNb = 16;
+constexpr int kRegThreads = 512;
+
+template <int RT>
+__global__ void __launch_bounds__(kRegThreads)
+k_panel_reg(double* a, int n, int k0, int nb, int* ipiv, int* info) {
+  __shared__ int at_pos[kRegThreads * RT];
+  __shared__ double s_best[kRegThreads / 64];
+  __shared__ int s_bpos[kRegThreads / 64];
+  __shared__ double s_prow[kRegNb];
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int m = n - k0;
+  double v[RT][kRegNb];
+  int pos[RT];
+#pragma clang loop unroll(full)
+  for (int q = 0; q < RT; ++q) {
+    const int r = tid + q * kRegThreads;
+    pos[q] = r < m ? r : INT_MAX;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kRegNb; ++c)
+      v[q][c] = (r < m && c < nb) ? a[static_cast<int64_t>(k0 + c) * n + k0 + r] : 0.0;
+    if (r < m) at_pos[r] = r;
+  }
+  __syncthreads();
+#pragma clang loop unroll(full)
+  for (int j = 0; j < kRegNb; ++j) {
+    if (j < nb) {
+    double best = -1.0;
+    int bpos = INT_MAX;
+#pragma clang loop unroll(full)
+    for (int q = 0; q < RT; ++q) {
+      if (pos[q] >= j && pos[q] != INT_MAX) {
+        const double x = fabs(v[q][j]);
+        if (x > best || (x == best && pos[q] < bpos)) {
+          best = x;
+          bpos = pos[q];
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int op = __shfl_xor(bpos, off);
+      if (ob > best || (ob == best && op < bpos)) {
+        best = ob;
+        bpos = op;
+      }
+    }
+    if (lane == 0) {
+      s_best[wave] = best;
+      s_bpos[wave] = bpos;
+    }
+    __syncthreads();
+    double pval = s_best[0];
+    int ppos = s_bpos[0];
+    for (int w = 1; w < kRegThreads / 64; ++w) {
+      if (s_best[w] > pval || (s_best[w] == pval && s_bpos[w] < ppos)) {
+        pval = s_best[w];
+        ppos = s_bpos[w];
+      }
+    }
+    const int prow = at_pos[ppos], jrow = at_pos[j];
+#pragma clang loop unroll(full)
+    for (int q = 0; q < RT; ++q) {
+      if (tid + q * kRegThreads == prow) {
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kRegNb; ++c) s_prow[c] = v[q][c];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ipiv[k0 + j] = k0 + ppos;
+      if (!(pval > 0.0) && *info == 0) *info = k0 + j + 1;
+      at_pos[j] = prow;
+      at_pos[ppos] = jrow;
+    }
+#pragma clang loop unroll(full)
+    for (int q = 0; q < RT; ++q) {
+      const int r = tid + q * kRegThreads;
+      if (r == prow) pos[q] = j;
+      else if (r == jrow) pos[q] = ppos;
+    }
+    const double d = s_prow[j];
+    const double rd = d != 0.0 ? 1.0 / d : 0.0;
+#pragma clang loop unroll(full)
+    for (int q = 0; q < RT; ++q) {
+      if (pos[q] > j && pos[q] != INT_MAX) {
+        const double l = v[q][j] * rd;
+        v[q][j] = l;
+#pragma clang loop unroll(full)
+        for (int c = j + 1; c < kRegNb; ++c) v[q][c] -= l * s_prow[c];
+      }
+    }
+  }
+  }
+#pragma clang loop unroll(full)
+  for (int q = 0; q < RT; ++q) {
+    if (pos[q] != INT_MAX) {
+#pragma clang loop unroll(full)
+      for (int c = 0; c < kRegNb; ++c)
+        if (c < nb) a[static_cast<int64_t>(k0 + c) * n + k0 + pos[q]] = v[q][c];
+    }
   }
 }
 
@@ -195,24 +405,24 @@ k_gemm_sub(int m, int p, int k, const double* A, const double* B, double* C, int
       Bs[kb][c] = (gc < p && gk2 < k) ? B[static_cast<int64_t>(gc) * ld + gk2] : 0.0;
     }
     __syncthreads();
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int kk = 0; kk < 16; ++kk) {
       double av[4], bv[4];
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int u = 0; u < 4; ++u) {
         av[u] = As[kk][tx + 16 * u];
         bv[u] = Bs[kk][ty + 16 * u];
       }
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int u = 0; u < 4; ++u)
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
     }
     __syncthreads();
   }
-#pragma unroll
+#pragma clang loop unroll(full)
   for (int u = 0; u < 4; ++u)
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int v = 0; v < 4; ++v) {
       int r = row0 + tx + 16 * u, c = col0 + ty + 16 * v;
       if (r < m && c < p) C[static_cast<int64_t>(c) * ld + r] -= acc[u][v];
@@ -256,21 +466,76 @@ void gemm_sub(Handle* h, int m, int p, int k, const double* A, const double* B, 
 
 }  // namespace
 
+// builds h->ap_* once; leaves ap_state = -1 if some row of A P has more
+// distinct coarse columns than the per-row table holds
+static void build_ap(Handle* h) {
+  if (h->ap_state != 0) return;
+  const int n = h->n;
+  Allocator* al = &h->alloc;
+  DBuf<int> err(al, 1);
+  HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+  DBuf<int64_t> cnt(al, static_cast<size_t>(n) + 1);
+  HIPX(hipMemsetAsync(cnt.get() + n, 0, sizeof(int64_t), h->stream));
+  const unsigned g = static_cast<unsigned>((n + kApWaves - 1) / kApWaves);
+  LAUNCH(h, "ap_count", k_ap<false>, g, 64 * kApWaves, 0, n, h->rp.get(), h->ci.get(),
+         h->val.get(), h->p_rp.get(), h->p_ci.get(), h->p_val.get(), cnt.get(), nullptr, nullptr,
+         err.get());
+  int e = 0;
+  HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  if (e != 0) {
+    h->ap_state = -1;
+    return;
+  }
+  h->ap_rp.reset(al, static_cast<size_t>(n) + 1);
+  exclusive_scan_i64(h, cnt.get(), h->ap_rp.get(), n + 1);
+  int64_t nnz = 0;
+  HIPX(hipMemcpyAsync(&nnz, h->ap_rp.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  h->ap_ci.reset(al, std::max<int64_t>(nnz, 1));
+  h->ap_val.reset(al, std::max<int64_t>(nnz, 1));
+  LAUNCH(h, "ap_fill", k_ap<true>, g, 64 * kApWaves, 0, n, h->rp.get(), h->ci.get(),
+         h->val.get(), h->p_rp.get(), h->p_ci.get(), h->p_val.get(), h->ap_rp.get(),
+         h->ap_ci.get(), h->ap_val.get(), err.get());
+  h->ap_state = 1;
+}
+
 void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const double* R_val,
                            int rows, double* out) {
   const int nc = h->nc;
   const int jt = std::min(nc, 4096);
-  LAUNCH(h, "rap", k_rap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val, h->rp.get(),
-         h->ci.get(), h->val.get(), h->p_rp.get(), h->p_ci.get(), h->p_val.get(), out, jt);
+  build_ap(h);
+  if (h->ap_state == 1) {
+    LAUNCH(h, "rap", k_rap_ap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val,
+           h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, jt);
+  } else {  // rows of A P too wide for the table: the direct triple product
+    LAUNCH(h, "rap", k_rap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val, h->rp.get(),
+           h->ci.get(), h->val.get(), h->p_rp.get(), h->p_ci.get(), h->p_val.get(), out, jt);
+  }
 }
 
 // LU of `a` (n x n, overwritten) and inv = A^{-1}
 void lu_inverse(Handle* h, double* a, double* inv, int n) {
   DBuf<int> ipiv(&h->alloc, n), info(&h->alloc, 1);
   HIPX(hipMemsetAsync(info, 0, sizeof(int), h->stream));
-  for (int k0 = 0; k0 < n; k0 += kNb) {
-    int nb = std::min(kNb, n - k0);
-    LAUNCH(h, "lu_panel", k_panel, 1, 1024, 0, a, n, k0, nb, ipiv.get(), info.get());
+  for (int k0 = 0; k0 < n;) {
+    const int m = n - k0;
+    // panels of at most 4 * 512 rows live in registers (16 columns), larger
+    // ones are factored in place (32 columns)
+    int nb;
+    if (m <= 4 * kRegThreads) {
+      nb = std::min(kRegNb, m);
+      if (m <= kRegThreads)
+        LAUNCH(h, "lu_panel", k_panel_reg<1>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(), info.get());
+      else if (m <= 2 * kRegThreads)
+        LAUNCH(h, "lu_panel", k_panel_reg<2>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(), info.get());
+      else
+        LAUNCH(h, "lu_panel", k_panel_reg<4>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(), info.get());
+    } else {
+      nb = std::min(kNb, m);
+      LAUNCH(h, "lu_panel", k_panel, 1, 1024, 0, a, n, k0, nb, ipiv.get(), info.get());
+    }
     LAUNCH(h, "lu_laswp", k_laswp, blocks_for(n, 256), 256, 0, a, n, k0, nb, ipiv.get());
     int c0 = k0 + nb;
     if (c0 < n) {
@@ -279,6 +544,7 @@ void lu_inverse(Handle* h, double* a, double* inv, int n) {
       gemm_sub(h, n - c0, n - c0, nb, a + static_cast<int64_t>(k0) * n + c0,
                a + static_cast<int64_t>(c0) * n + k0, a + static_cast<int64_t>(c0) * n + c0, n);
     }
+    k0 += nb;
   }
   int hinfo = 0;
   std::vector<int> hp(n);

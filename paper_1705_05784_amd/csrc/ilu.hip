@@ -113,20 +113,28 @@ __device__ __forceinline__ void store_ready(T* p, T v) {
   __hip_atomic_store(reinterpret_cast<U*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until *p is published.  Polls back off up to ~1.7 us; the wait gives
-// up after `limit` wall-clock ticks, or at once when another wait has given
-// up (err != 0), so a broken dependency order ends the kernel quickly.
 template <class T>
-__device__ __forceinline__ T wait_ready(const T* p, int* err, unsigned long long limit) {
+__device__ __forceinline__ typename Sentinel<T>::U load_raw(const T* p) {
+  using U = typename Sentinel<T>::U;
+  return __hip_atomic_load(reinterpret_cast<const U*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *p is published, given a first read u of it.  Polls back off up
+// to ~0.4 us; the wait gives up after `limit` wall-clock ticks, or at once
+// when another wait has given up (err != 0), so a broken dependency order
+// ends the kernel quickly.
+template <class T>
+__device__ __forceinline__ T wait_ready(const T* p, typename Sentinel<T>::U u, int* err,
+                                        unsigned long long limit) {
   using U = typename Sentinel<T>::U;
   const U* q = reinterpret_cast<const U*>(p);
-  U u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (u == Sentinel<T>::bits) {
     const unsigned long long t0 = wall_clock64();
     int backoff = 1;
     while (u == Sentinel<T>::bits) {
       for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
-      backoff = backoff < 64 ? 2 * backoff : 64;
+      backoff = backoff < 16 ? 2 * backoff : 16;
       u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (u != Sentinel<T>::bits) break;
       if (wall_clock64() - t0 > limit ||
@@ -140,6 +148,26 @@ __device__ __forceinline__ T wait_ready(const T* p, int* err, unsigned long long
   T v;
   __builtin_memcpy(&v, &u, sizeof(T));
   return v;
+}
+
+// s -= sum_{p in [p0, p1)} lu[p] x[ci[p]], waiting for each x entry.  The
+// reads of up to kDeps dependencies are issued together, so a row that finds
+// them published pays one memory round trip, not one per dependency.
+constexpr int kDeps = 8;
+
+template <class T>
+__device__ __forceinline__ void dot_ready(T& s, int p0, int p1, const int* ci, const T* lu,
+                                          const T* x, int* err, unsigned long long limit) {
+  using U = typename Sentinel<T>::U;
+  for (int pb = p0; pb < p1; pb += kDeps) {
+    U u[kDeps];
+#pragma unroll
+    for (int k = 0; k < kDeps; ++k)
+      if (pb + k < p1) u[k] = load_raw<T>(x + ci[pb + k]);
+#pragma unroll
+    for (int k = 0; k < kDeps; ++k)
+      if (pb + k < p1) s -= lu[pb + k] * wait_ready<T>(x + ci[pb + k], u[k], err, limit);
+  }
 }
 
 template <class T>
@@ -167,7 +195,7 @@ k_sweep_lower(const int* rows, const int* chunk, int nchunks, const int* rp, con
     if (t < chunk[c + 1]) {
       const int i = rows[t];
       T s = b[i];
-      for (int p = rp[i]; p < diag[i]; ++p) s -= lu[p] * wait_ready<T>(y + ci[p], err, limit);
+      dot_ready<T>(s, rp[i], diag[i], ci, lu, y, err, limit);
       using U = typename Sentinel<T>::U;
       reinterpret_cast<U*>(z)[i] = Sentinel<T>::bits;
       store_ready<T>(y + i, s);
@@ -192,8 +220,7 @@ k_sweep_upper(const int* rows, const int* chunk, int nchunks, const int* rp, con
     if (t < chunk[c + 1]) {
       const int i = rows[t];
       T s = y[i];
-      for (int p = diag[i] + 1; p < rp[i + 1]; ++p)
-        s -= lu[p] * wait_ready<T>(z + ci[p], err, limit);
+      dot_ready<T>(s, diag[i] + 1, rp[i + 1], ci, lu, z, err, limit);
       store_ready<T>(z + i, s / lu[diag[i]]);
     }
   }

@@ -156,8 +156,13 @@ struct Handle {
   DBuf<double> p_val, r_val;
   DBuf<float> p_val32, r_val32;
 
-  // coarse system: dense column-major A_c and its inverse
+  // coarse system: dense column-major A_c and its inverse; A P (CSR, rows in
+  // A's order, columns unsorted), shared by A_c = R (A P) and the FV operator
   DBuf<double> Ac, Ainv;
+  int ap_state = 0;  // 0 not built, 1 built, -1 a row exceeded the hash capacity
+  DBuf<int64_t> ap_rp;
+  DBuf<int> ap_ci;
+  DBuf<double> ap_val;
 
   // ILU(0): factors in A's slots, level schedules of the two sweeps
   DBuf<double> ilu;

@@ -817,6 +817,13 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
     lds_need = std::max(lds_need, band_lds_elems(mode, static_cast<int>(nk), h_band[K]));
     off[2 * k + 1] = x_total;
     if (separate_x) x_total += nk * h_ncols[K];
+    {  // arithmetic of the band LDL^T (step k updates a triangle of
+       // min(b, n-1-k) rows) and of the two sweeps for each column
+      const double b = h_band[K], nn = static_cast<double>(nk), t = std::min(b, nn);
+      const double fac = std::max(0.0, nn - b) * b * (b + 1.0) + (t - 1.0) * t * (t + 1.0) / 3.0;
+      const double S = nn >= b ? nn * b - b * (b + 1.0) / 2.0 : nn * (nn - 1.0) / 2.0;
+      h->info.local_flops += fac + (4.0 * S + nn) * h_ncols[K];
+    }
   }
   DBuf<int64_t> d_off(&h->alloc, 2 * nb);
   HIPX(hipMemcpyAsync(d_off, off.data(), 2 * nb * sizeof(int64_t), hipMemcpyHostToDevice,
