@@ -9,6 +9,10 @@
 // only for its own dependencies (see k_sweep_lower).  The natural ordering --
 // and hence the smoother itself -- is unchanged.
 #include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -226,7 +230,162 @@ k_sweep_upper(const int* rows, const int* chunk, int nchunks, const int* rp, con
   }
 }
 
-void levels(Handle* h, int upper, Levels* out) {
+// Range sweeps.  A workgroup takes ranges in ticket order (ascending for the
+// forward sweep, descending for the backward one) and walks a range level by
+// level with a barrier between levels; values of rows inside the range are
+// read from LDS, values of rows in earlier ranges are waited for in global
+// memory, and every row is published there (value as ready flag) for the
+// ranges after it.  While a level is computed, each thread already loads
+// its row of the next level (ELL dependencies, factor values, and the first
+// read of its dependencies outside the range), so the barrier, LDS reads
+// and arithmetic are all that a level costs on the critical path.  A range
+// depends only on earlier tickets, whose workgroups are already running, so
+// the schedule always progresses; every wait is bounded as above.
+constexpr int kSegCache = 1024;   // level boundaries of a range kept in LDS
+
+template <class T>
+struct SweepRow {
+  using U = typename Sentinel<T>::U;
+  int t, i, cnt;
+  T in, dg;
+  int col[kEll];
+  T val[kEll];
+  U raw[kEll];
+};
+
+template <class T>
+__device__ __forceinline__ void sweep_fetch(SweepRow<T>& w, int t, int lo, int hi,
+                                            const int* rows, const int* ecol, const T* eval,
+                                            const int* ecnt, const T* ediag, const T* in,
+                                            const T* g) {
+  w.t = t;
+  if (t < 0) return;
+  w.i = rows[t];
+  w.cnt = ecnt[t];
+  w.dg = ediag[t];
+#pragma unroll
+  for (int k = 0; k < kEll; ++k) {
+    w.col[k] = ecol[static_cast<int64_t>(t) * kEll + k];
+    w.val[k] = eval[static_cast<int64_t>(t) * kEll + k];
+  }
+  w.in = in[w.i];
+#pragma unroll
+  for (int k = 0; k < kEll; ++k) {
+    const int j = w.col[k];
+    w.raw[k] = (j >= 0 && (j < lo || j >= hi)) ? load_raw<T>(g + j) : typename SweepRow<T>::U(0);
+  }
+}
+
+template <class T, bool kUpper>
+__device__ __forceinline__ void sweep_row(const SweepRow<T>& w, int lo, int hi, T* loc, T* g,
+                                          T* arm, const int* ep0, const int* ci, const T* lu,
+                                          int* err, unsigned long long limit) {
+  using U = typename Sentinel<T>::U;
+  T s = w.in;
+#pragma unroll
+  for (int k = 0; k < kEll; ++k) {
+    const int j = w.col[k];
+    if (j >= 0) {
+      T v;
+      if (j >= lo && j < hi) v = loc[j - lo];
+      else v = wait_ready<T>(g + j, w.raw[k], err, limit);
+      s -= w.val[k] * v;
+    }
+  }
+  if (w.cnt > kEll) {  // dependencies past the ELL width, from the CSR
+    const int p0 = ep0[w.t];
+    for (int p = p0 + kEll; p < p0 + w.cnt; ++p) {
+      const int j = ci[p];
+      T v;
+      if (j >= lo && j < hi) v = loc[j - lo];
+      else v = wait_ready<T>(g + j, load_raw<T>(g + j), err, limit);
+      s -= lu[p] * v;
+    }
+  }
+  if constexpr (kUpper) s = s / w.dg;
+  else reinterpret_cast<U*>(arm)[w.i] = Sentinel<T>::bits;
+  loc[w.i - lo] = s;
+  store_ready<T>(g + w.i, s);
+}
+
+template <class T, bool kUpper>
+__global__ void __launch_bounds__(256)
+k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const int* segbase,
+               const int* ecol, const T* eval, const int* ecnt, const int* ep0, const T* ediag,
+               const int* ci, const T* lu, const T* in, T* out, T* arm, int* ticket, int* err,
+               unsigned long long limit) {
+  extern __shared__ double lds_raw[];
+  T* loc = reinterpret_cast<T*>(lds_raw);
+  __shared__ int s_seg[kSegCache + 1];
+  __shared__ int s_c;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  while (true) {
+    if (tid == 0) s_c = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int c = s_c;
+    if (c >= nranges) break;
+    const int r = kUpper ? nranges - 1 - c : c;
+    const int r0 = r * S, r1 = min(n, r0 + S);
+    const int sb = segbase[r], ns = segbase[r + 1] - sb;
+    const bool cached = ns <= kSegCache;
+    if (cached)
+      for (int k = tid; k <= ns; k += nt) s_seg[k] = seg[sb + k];
+    __syncthreads();
+    auto segat = [&](int k) { return cached ? s_seg[k] : seg[sb + k]; };
+    SweepRow<T> nxt;
+    {
+      const int t = segat(0) + tid;
+      sweep_fetch<T>(nxt, t < segat(1) ? t : -1, r0, r1, rows, ecol, eval, ecnt, ediag, in, out);
+    }
+    for (int k = 0; k < ns; ++k) {
+      const SweepRow<T> cur = nxt;
+      const int a = segat(k), b = segat(k + 1);
+      if (k + 1 < ns) {
+        const int t = segat(k + 1) + tid;
+        sweep_fetch<T>(nxt, t < segat(k + 2) ? t : -1, r0, r1, rows, ecol, eval, ecnt, ediag,
+                       in, out);
+      }
+      if (cur.t >= 0) sweep_row<T, kUpper>(cur, r0, r1, loc, out, arm, ep0, ci, lu, err, limit);
+      for (int t = a + tid + nt; t < b; t += nt) {  // levels wider than the workgroup
+        SweepRow<T> w;
+        sweep_fetch<T>(w, t, r0, r1, rows, ecol, eval, ecnt, ediag, in, out);
+        sweep_row<T, kUpper>(w, r0, r1, loc, out, arm, ep0, ci, lu, err, limit);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ELL form of the dependencies of every position of a range schedule
+__global__ void k_ell_build(int n, int upper, const int* rows, const int* rp, const int* diag,
+                            const int* ci, int* ecol, int* epos, int* ecnt, int* ep0) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = rows[t];
+  const int p0 = upper ? diag[i] + 1 : rp[i];
+  const int p1 = upper ? rp[i + 1] : diag[i];
+  ecnt[t] = p1 - p0;
+  ep0[t] = p0;
+  for (int k = 0; k < kEll; ++k) {
+    const bool in = p0 + k < p1;
+    ecol[static_cast<int64_t>(t) * kEll + k] = in ? ci[p0 + k] : -1;
+    epos[static_cast<int64_t>(t) * kEll + k] = in ? p0 + k : -1;
+  }
+}
+
+template <class T>
+__global__ void k_ell_vals(int n, const int* rows, const int* diag, const int* epos,
+                           const T* lu, T* eval, T* ediag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  for (int k = 0; k < kEll; ++k) {
+    const int p = epos[static_cast<int64_t>(t) * kEll + k];
+    eval[static_cast<int64_t>(t) * kEll + k] = p >= 0 ? lu[p] : T(0);
+  }
+  ediag[t] = lu[diag[rows[t]]];
+}
+
+void levels(Handle* h, int upper, Levels* out, std::vector<int>* host_lev) {
   const int n = h->n;
   unsigned g = blocks_for(n, kT);
   DBuf<int> lev(&h->alloc, n), changed(&h->alloc, 1);
@@ -247,7 +406,8 @@ void levels(Handle* h, int upper, Levels* out) {
   LAUNCH(h, "iota", k_iota, g, kT, 0, n, iota.get());
   int maxlev = 0;
   {
-    std::vector<int> hl(n);
+    std::vector<int>& hl = *host_lev;
+    hl.resize(n);
     HIPX(hipMemcpyAsync(hl.data(), lev.get(), n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPX(hipStreamSynchronize(h->stream));
     for (int v : hl) maxlev = std::max(maxlev, v);
@@ -266,6 +426,74 @@ void levels(Handle* h, int upper, Levels* out) {
 __global__ void k_d2f_ilu(int64_t n, const double* a, float* b) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = static_cast<float>(a[i]);
+}
+
+// rows per range of the range sweeps: FAMS_ILU_RANGE (0 selects the
+// level-chunk sweeps), default 8192
+int sweep_range_rows(Handle* h) {
+  (void)h;
+  int S = 8192;
+  if (const char* e = std::getenv("FAMS_ILU_RANGE")) S = std::atoi(e);
+  if (S < 0) S = 0;
+  return std::min(S, 16384);
+}
+
+// range schedule of one sweep from the rows' global dependency levels: inside
+// a range, rows of equal level are independent and every dependency inside
+// the range has a lower level, so a workgroup can take the range level by
+// level with a barrier between levels (counting sort per range, host side)
+void range_table(Handle* h, const std::vector<int>& lev, int S, int upper, Ranges* R) {
+  const int n = h->n;
+  const int nr = (n + S - 1) / S;
+  std::vector<int> rows(n), seg, segbase(nr + 1);
+  std::vector<int> cnt;
+  for (int r = 0; r < nr; ++r) {
+    const int r0 = r * S, r1 = std::min(n, r0 + S);
+    int lo = INT32_MAX, hi = 0;
+    for (int i = r0; i < r1; ++i) {
+      lo = std::min(lo, lev[i]);
+      hi = std::max(hi, lev[i]);
+    }
+    cnt.assign(hi - lo + 2, 0);
+    for (int i = r0; i < r1; ++i) ++cnt[lev[i] - lo + 1];
+    for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
+    segbase[r] = static_cast<int>(seg.size());
+    for (int L = 0; L <= hi - lo; ++L)
+      if (cnt[L + 1] > cnt[L]) seg.push_back(r0 + cnt[L]);
+    for (int i = r0; i < r1; ++i) rows[r0 + cnt[lev[i] - lo]++] = i;
+  }
+  segbase[nr] = static_cast<int>(seg.size());
+  seg.push_back(n);
+  R->S = S;
+  R->nranges = nr;
+  R->rows.reset(&h->alloc, n);
+  R->seg.reset(&h->alloc, seg.size());
+  R->segbase.reset(&h->alloc, nr + 1);
+  HIPX(hipMemcpyAsync(R->rows, rows.data(), n * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPX(hipMemcpyAsync(R->seg, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice,
+                      h->stream));
+  HIPX(hipMemcpyAsync(R->segbase, segbase.data(), (nr + 1) * sizeof(int), hipMemcpyHostToDevice,
+                      h->stream));
+  const size_t ne = static_cast<size_t>(n) * kEll;
+  R->ecol.reset(&h->alloc, ne);
+  R->epos.reset(&h->alloc, ne);
+  R->ecnt.reset(&h->alloc, n);
+  R->ep0.reset(&h->alloc, n);
+  LAUNCH(h, "ilu_ell", k_ell_build, blocks_for(n, kT), kT, 0, n, upper, R->rows.get(),
+         h->rp.get(), h->diag.get(), h->ci.get(), R->ecol.get(), R->epos.get(), R->ecnt.get(),
+         R->ep0.get());
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
+// factor values of a range schedule in precision T (gathered once)
+template <class T>
+void ell_values(Handle* h, Ranges* R, const T* lu, DBuf<T>& ev, DBuf<T>& ed) {
+  if (ev.get()) return;
+  const int n = h->n;
+  ev.reset(&h->alloc, static_cast<size_t>(n) * kEll);
+  ed.reset(&h->alloc, n);
+  LAUNCH(h, "ilu_ell", k_ell_vals<T>, blocks_for(n, kT), kT, 0, n, R->rows.get(),
+         h->diag.get(), R->epos.get(), lu, ev.get(), ed.get());
 }
 
 // chunks of at most 256 rows inside one level
@@ -295,10 +523,15 @@ void build_ilu(Handle* h) {
   HIPX(hipStreamSynchronize(h->stream));
   FAMS_REQUIRE(e == 0, FAMS_ERR_INVALID_ARG, "a row of A has no stored diagonal");
   if (!h->smoother) return;
-  levels(h, 0, &h->lvl_lo);
-  levels(h, 1, &h->lvl_up);
+  std::vector<int> lev_lo, lev_up;
+  levels(h, 0, &h->lvl_lo, &lev_lo);
+  levels(h, 1, &h->lvl_up, &lev_up);
   chunk_table(h, &h->lvl_lo);
   chunk_table(h, &h->lvl_up);
+  if (const int S = sweep_range_rows(h)) {
+    range_table(h, lev_lo, S, 0, &h->rng_lo);
+    range_table(h, lev_up, S, 1, &h->rng_up);
+  }
   h->info.ilu_levels_lower = h->lvl_lo.count();
   h->info.ilu_levels_upper = h->lvl_up.count();
   h->ilu.reset(&h->alloc, h->nnz);
@@ -335,6 +568,32 @@ void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
     HIPX(hipGetDevice(&dev));
     HIPX(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     h->wait_ticks = 2000ull * static_cast<unsigned long long>(khz > 0 ? khz : 100000);
+  }
+  if (h->rng_lo.nranges > 0) {
+    Ranges& L = h->rng_lo;
+    Ranges& U = h->rng_up;
+    const T *lv, *ld, *uv, *ud;
+    if constexpr (std::is_same<T, double>::value) {
+      ell_values<double>(h, &L, lu, L.eval64, L.ediag64);
+      ell_values<double>(h, &U, lu, U.eval64, U.ediag64);
+      lv = L.eval64.get(); ld = L.ediag64.get(); uv = U.eval64.get(); ud = U.ediag64.get();
+    } else {
+      ell_values<float>(h, &L, lu, L.eval32, L.ediag32);
+      ell_values<float>(h, &U, lu, U.eval32, U.ediag32);
+      lv = L.eval32.get(); ld = L.ediag32.get(); uv = U.eval32.get(); ud = U.ediag32.get();
+    }
+    const size_t lds = static_cast<size_t>(L.S) * sizeof(T);
+    allow_lds(reinterpret_cast<const void*>(&k_sweep_ranges<T, false>), lds);
+    allow_lds(reinterpret_cast<const void*>(&k_sweep_ranges<T, true>), lds);
+    LAUNCH(h, "ilu_lower", (k_sweep_ranges<T, false>), std::min(L.nranges, 2048), 256, lds, n,
+           L.S, L.nranges, L.rows.get(), L.seg.get(), L.segbase.get(), L.ecol.get(), lv,
+           L.ecnt.get(), L.ep0.get(), ld, h->ci.get(), lu, b, y, x, h->ilu_ticket.get(),
+           h->sweep_err.get(), h->wait_ticks);
+    LAUNCH(h, "ilu_upper", (k_sweep_ranges<T, true>), std::min(U.nranges, 2048), 256, lds, n,
+           U.S, U.nranges, U.rows.get(), U.seg.get(), U.segbase.get(), U.ecol.get(), uv,
+           U.ecnt.get(), U.ep0.get(), ud, h->ci.get(), lu, y, x, nullptr,
+           h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks);
+    return;
   }
   // a window of ~kSweepGroups chunks in flight: enough to overlap tens of
   // levels, few enough that waiting rows do not flood the memory system

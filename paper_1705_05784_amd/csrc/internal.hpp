@@ -127,6 +127,24 @@ struct Levels {
   int count() const { return ptr.empty() ? 0 : static_cast<int>(ptr.size()) - 1; }
 };
 
+// Schedule of one triangular sweep by row ranges: rows [r*S, (r+1)*S) form
+// range r; `rows` lists each range's rows grouped by dependency level
+// (ascending level, then row); segment s = rows[seg[s] .. seg[s+1]) is one
+// level of one range, and range r owns segments [segbase[r], segbase[r+1]).
+// For the sweep kernels every position t of `rows` also carries its row's
+// dependencies in sweep order: the first kEll in ELL form (ecol[t*kEll+k],
+// -1 past the end, with the factor entry's CSR position epos), the count
+// ecnt[t] and the first CSR position ep0[t] for the rest; the factor values
+// are gathered per precision (evalN, ediagN) when the factors are known.
+constexpr int kEll = 8;
+struct Ranges {
+  int S = 0, nranges = 0, max_segs = 0;
+  DBuf<int> rows, seg, segbase;
+  DBuf<int> ecol, epos, ecnt, ep0;
+  DBuf<double> eval64, ediag64;
+  DBuf<float> eval32, ediag32;
+};
+
 // ---- the handle ------------------------------------------------------------
 struct Handle {
   Allocator alloc;
@@ -168,6 +186,7 @@ struct Handle {
   DBuf<double> ilu;
   DBuf<float> ilu32;
   Levels lvl_lo, lvl_up;
+  Ranges rng_lo, rng_up;
   DBuf<int> ilu_ticket;  // work tickets of the two sweeps
   DBuf<int> sweep_err;   // set when a bounded wait in a sweep gives up
   unsigned long long wait_ticks = 0;  // bound of one wait, device wall-clock ticks
