@@ -200,6 +200,17 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or
  * disable (0); then read total milliseconds and launch counts per kernel
  * name (host strings valid until the handle is destroyed). */
+/* The dense kernels of the coarse system on an n x n column-major FP64
+ * matrix a (device), result in out (device, n x n), on the default stream:
+ *   op 0: out = a a          (the FP64 MFMA product used by the inverses)
+ *   op 1: out = a^{-1} by blocked Gauss-Jordan without pivoting (A_c, SPD);
+ *         FAMS_ERR_SINGULAR_COARSE if a pivot is not positive
+ *   op 2: out = a^{-1} by LU with partial pivoting and triangular solves
+ *   op 3: out = a^{-1} column by column with the one-workgroup LU solve
+ *         (the FV stage's solver; n <= 12288)
+ * For tests of those kernels; blocking. */
+fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out);
+
 fams_status_t fams_set_profiling(fams_handle_t h, int32_t on);
 fams_status_t fams_get_kernel_stats(fams_handle_t h, int32_t max_entries, int32_t* n_entries,
                                     const char** names, double* total_ms, int64_t* launches);

@@ -190,11 +190,15 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   h->Ac.reset(al, static_cast<size_t>(nc) * nc);
   build_coarse_operator(h, h->r_rp, h->r_ci, h->r_val, nc, h->Ac);
   {
-    DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
-    HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
-                        h->stream));
+    // A_c = P^T A P is SPD for SPD A: Gauss-Jordan without pivoting; if a
+    // pivot is not positive, LU with partial pivoting
     h->Ainv.reset(al, static_cast<size_t>(nc) * nc);
-    lu_inverse(h, lu, h->Ainv, nc);
+    if (!spd_inverse(h, h->Ac, h->Ainv, nc)) {
+      DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
+      HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
+                          h->stream));
+      lu_inverse(h, lu, h->Ainv, nc);
+    }
     HIPX(hipStreamSynchronize(h->stream));
   }
   if (h->precision == FAMS_PREC_MIXED) {
@@ -395,6 +399,43 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z) {
   if (!h || !r || !z) return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     fams::apply_stage_fp64(h, r, z);
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out) {
+  if (op < 0 || op > 3 || n <= 0 || n > 65536 || !a || !out) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    std::unique_ptr<fams_handle_s> h(new fams_handle_s());
+    fams::Handle* H = h.get();
+    H->stream = nullptr;
+    H->alloc.stream = nullptr;
+    const size_t nn = static_cast<size_t>(n) * n;
+    if (op == 0) {
+      HIPX(hipMemsetAsync(out, 0, nn * sizeof(double), nullptr));
+      fams::dense_gemm_add(H, n, n, n, 1.0, a, n, a, n, out, n);
+    } else if (op == 1) {
+      FAMS_REQUIRE(fams::spd_inverse(H, a, out, n), FAMS_ERR_SINGULAR_COARSE,
+                   "not positive definite");
+    } else if (op == 2) {
+      fams::DBuf<double> lu(&H->alloc, nn);
+      HIPX(hipMemcpyAsync(lu, a, nn * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
+      fams::lu_inverse(H, lu, out, n);
+    } else {
+      fams::DBuf<double> lu(&H->alloc, nn), e(&H->alloc, n);
+      fams::DBuf<int> perm(&H->alloc, n);
+      HIPX(hipMemcpyAsync(lu, a, nn * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
+      fams::lu_factor(H, lu, n, perm);
+      std::vector<double> unit(n, 0.0);
+      for (int j = 0; j < n; ++j) {
+        unit[j] = 1.0;
+        HIPX(hipMemcpyAsync(e, unit.data(), n * sizeof(double), hipMemcpyHostToDevice, nullptr));
+        fams::lu_solve(H, lu, perm, n, e, out + static_cast<size_t>(j) * n);
+        HIPX(hipStreamSynchronize(nullptr));
+        unit[j] = 0.0;
+      }
+    }
+    HIPX(hipStreamSynchronize(nullptr));
     return FAMS_OK;
   });
 }

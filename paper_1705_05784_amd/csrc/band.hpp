@@ -25,6 +25,7 @@
 namespace fams {
 
 constexpr int kPanel = 16;   // columns per panel of the blocked factorisation
+constexpr int kPanelRowsPerThread = 2;  // panel rows b + kPanel <= 2 * 256 threads
 constexpr int kSubRows = 8;  // rows per block of the substitution
 
 __host__ __device__ inline int64_t band_panel_elems(int b) {  // P and Q of a panel
@@ -43,6 +44,7 @@ __host__ __device__ inline int band_mode(int n, int b, int64_t lds) {
   const int64_t sub = band_subst_elems(b);
   if (static_cast<int64_t>(n) * (b + 1) + sub <= lds) return 0;
   const int64_t pan = band_panel_elems(b);
+  if (b + kPanel > kPanelRowsPerThread * 256) return -1;  // panel rows held in registers
   if (band_ring_elems(b) + pan <= lds) return 1;
   if (pan <= lds && sub <= lds) return 2;
   return -1;
@@ -102,6 +104,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
   TC* P = lds;
   TC* Q = P + static_cast<int64_t>(mrow) * PS;
   TC* ring = Q + static_cast<int64_t>(kPanel) * mrow;
+  __shared__ TC colbuf[2 * kPanel];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
   auto rowp = [&](int r) -> TC* {
     if constexpr (kRing) return ring + static_cast<int64_t>(r % mrow) * w;
@@ -123,22 +126,50 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
       }
       __syncthreads();
     }
-    for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
-      const int ii = e / kPanel, c = e % kPanel, t = ii - c;
-      P[ii * PS + c] = (c < nb && t >= 0 && t <= b) ? rowp(k + ii)[b - t] : TC(0);
+    // eliminate the panel's columns with its rows in registers (thread t
+    // owns rows t and t + blockDim.x); at step c the owners of rows c..nb-1
+    // publish their column-c entries (double-buffered, one barrier a step)
+    TC pr[kPanelRowsPerThread][kPanel];
+#pragma clang loop unroll(full)
+    for (int h2 = 0; h2 < kPanelRowsPerThread; ++h2) {
+      const int ii = threadIdx.x + h2 * blockDim.x;
+#pragma clang loop unroll(full)
+      for (int c = 0; c < kPanel; ++c) {
+        const int t = ii - c;
+        pr[h2][c] = (ii < np && c < nb && t >= 0 && t <= b) ? rowp(k + ii)[b - t] : TC(0);
+      }
+    }
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kPanel; ++c) {
+      if (c < nb) {
+        TC* cb = colbuf + (c & 1) * kPanel;
+        if (static_cast<int>(threadIdx.x) >= c && static_cast<int>(threadIdx.x) < nb)
+          cb[threadIdx.x] = pr[0][c];
+        __syncthreads();
+        const TC d = cb[c];
+        if (!(d > TC(0))) bad = true;
+        const TC rd = TC(1) / d;
+#pragma clang loop unroll(full)
+        for (int h2 = 0; h2 < kPanelRowsPerThread; ++h2) {
+          const int ii = threadIdx.x + h2 * blockDim.x;
+          if (ii > c && ii < np) {
+            const TC l = pr[h2][c] * rd;
+#pragma clang loop unroll(full)
+            for (int c2 = c + 1; c2 < kPanel; ++c2)
+              if (c2 < nb && c2 <= ii) pr[h2][c2] -= l * cb[c2];
+          }
+        }
+      }
+    }
+#pragma clang loop unroll(full)
+    for (int h2 = 0; h2 < kPanelRowsPerThread; ++h2) {
+      const int ii = threadIdx.x + h2 * blockDim.x;
+      if (ii < np) {
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kPanel; ++c) P[ii * PS + c] = pr[h2][c];
+      }
     }
     __syncthreads();
-    for (int c = 0; c < nb; ++c) {  // eliminate the panel's columns
-      const TC d = P[c * PS + c];
-      if (!(d > TC(0))) bad = true;
-      const TC rd = TC(1) / d;
-      for (int ii = c + 1 + threadIdx.x; ii < np; ii += blockDim.x) {
-        const TC l = P[ii * PS + c] * rd;
-        const int cend = min(nb, ii + 1);
-        for (int c2 = c + 1; c2 < cend; ++c2) P[ii * PS + c2] -= l * P[c2 * PS + c];
-      }
-      __syncthreads();
-    }
     // D and unit-lower L of the panel's columns; Q for the trailing update
     for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
       const int ii = e / kPanel, c = e % kPanel, t = ii - c;
@@ -150,9 +181,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
     __syncthreads();
     // trailing update: A(k+ii, k+jj) -= sum_c P[ii][c] Q[c][jj], nb <= jj <= ii < np
     for (int ii = nb + wave; ii < np; ii += nwaves) {
-      TC p[kPanel];
-#pragma unroll
-      for (int c = 0; c < kPanel; ++c) p[c] = P[ii * PS + c];
+      const TC* p = P + ii * PS;        // the same LDS address in every lane
       TC* row = rowp(k + ii) + b - ii;  // row[jj] = A(k+ii, k+jj)
       for (int j0 = nb; j0 <= ii; j0 += 256) {
         TC a[4];

@@ -464,6 +464,207 @@ void gemm_sub(Handle* h, int m, int p, int k, const double* A, const double* B, 
   LAUNCH(h, "gemm_f64", k_gemm_sub, grid, 256, 0, m, p, k, A, B, C, ld);
 }
 
+// ---- FP64 MFMA GEMM ----------------------------------------------------------
+// C[r, c] += alpha * sum_q A[r, q] B[q, c] for r < m, c < p, except rows and
+// columns in [skip0, skip1); column-major operands.  A workgroup forms a
+// 64 x 64 tile, each wavefront a 32 x 32 quarter of 2 x 2 blocks of
+// v_mfma_f64_16x16x4 (per instruction lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and holds D[4*q + l/16][l%16] in accumulator element q).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kGT = 64, kGK = 16;
+
+__global__ void __launch_bounds__(256)
+k_gemm_mfma(int m, int p, int k, double alpha, const double* A, int lda, const double* B,
+            int ldb, double* C, int ldc, int skip0, int skip1) {
+  __shared__ double As[kGK][kGT + 1];
+  __shared__ double Bs[kGK][kGT + 1];
+  const int r0 = blockIdx.x * kGT, c0 = blockIdx.y * kGT;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wr = (wave % 2) * 32, wc = (wave / 2) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < k; k0 += kGK) {
+    for (int e = tid; e < kGK * kGT; e += 256) {
+      const int i = e % kGT, qa = e / kGT;
+      As[qa][i] = (r0 + i < m && k0 + qa < k) ? A[static_cast<int64_t>(k0 + qa) * lda + r0 + i] : 0.0;
+      const int qb = e % kGK, j = e / kGK;
+      Bs[qb][j] = (c0 + j < p && k0 + qb < k) ? B[static_cast<int64_t>(c0 + j) * ldb + k0 + qb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      double fa[2], fb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        fa[t] = As[kk + lane / 16][wr + t * 16 + lane % 16];
+        fb[t] = Bs[kk + lane / 16][wc + t * 16 + lane % 16];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + wr + a * 16 + 4 * q + lane / 16;
+        const int c = c0 + wc + b * 16 + lane % 16;
+        if (r < m && c < p && (r < skip0 || r >= skip1) && (c < skip0 || c >= skip1))
+          C[static_cast<int64_t>(c) * ldc + r] += alpha * acc[a][b][q];
+      }
+}
+
+void gemm_mfma(Handle* h, int m, int p, int k, double alpha, const double* A, int lda,
+               const double* B, int ldb, double* C, int ldc, int skip0 = 0, int skip1 = 0) {
+  if (m <= 0 || p <= 0 || k <= 0) return;
+  dim3 grid(blocks_for(m, kGT), blocks_for(p, kGT));
+  LAUNCH(h, "gemm_mfma", k_gemm_mfma, grid, 256, 0, m, p, k, alpha, A, lda, B, ldb, C, ldc,
+         skip0, skip1);
+}
+
+// ---- in-place Gauss-Jordan inverse by blocks (no pivoting; SPD A_c) ---------
+// Step k with B = block k: B B <- inv(B B); column block <- -(column block)
+// inv(B B); every other entry += (new column block)(old row block); row block
+// <- inv(B B)(row block).  2 n^3 flops, the rank-kNb updates on MFMA.
+__global__ void __launch_bounds__(1024) k_gje_block(double* a, int n, int k0, int nb, int* info) {
+  __shared__ double T[kNb][kNb + 1];
+  const int i = threadIdx.x % kNb, c = threadIdx.x / kNb;
+  const bool in = i < nb && c < nb;
+  if (in) T[i][c] = a[static_cast<int64_t>(k0 + c) * n + k0 + i];
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = T[j][j];
+    if (threadIdx.x == 0 && !(d > 0.0)) atomicCAS(info, 0, k0 + j + 1);
+    const double rd = 1.0 / d;
+    const double f = in ? T[i][j] : 0.0, rj = in ? T[j][c] : 0.0;
+    __syncthreads();
+    if (in) {
+      double v;
+      if (i == j && c == j) v = rd;
+      else if (i == j) v = rj * rd;
+      else if (c == j) v = -f * rd;
+      else v = T[i][c] - f * (rj * rd);
+      T[i][c] = v;
+    }
+    __syncthreads();
+  }
+  if (in) a[static_cast<int64_t>(k0 + c) * n + k0 + i] = T[i][c];
+}
+
+// column block rows r outside the block: a[r, blk] <- -a[r, blk] inv(B B)
+__global__ void __launch_bounds__(256) k_gje_col(double* a, int n, int k0, int nb) {
+  __shared__ double T[kNb][kNb + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
+    T[e % nb][e / nb] = a[static_cast<int64_t>(k0 + e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n || (r >= k0 && r < k0 + nb)) return;
+  double x[kNb];
+#pragma unroll
+  for (int q = 0; q < kNb; ++q) x[q] = q < nb ? a[static_cast<int64_t>(k0 + q) * n + r] : 0.0;
+  for (int c = 0; c < nb; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNb; ++q)
+      if (q < nb) s += x[q] * T[q][c];
+    a[static_cast<int64_t>(k0 + c) * n + r] = -s;
+  }
+}
+
+// row block columns c outside the block: a[blk, c] <- inv(B B) a[blk, c]
+__global__ void __launch_bounds__(256) k_gje_row(double* a, int n, int k0, int nb) {
+  __shared__ double T[kNb][kNb + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
+    T[e % nb][e / nb] = a[static_cast<int64_t>(k0 + e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || (c >= k0 && c < k0 + nb)) return;
+  double y[kNb];
+  double* col = a + static_cast<int64_t>(c) * n + k0;
+#pragma unroll
+  for (int q = 0; q < kNb; ++q) y[q] = q < nb ? col[q] : 0.0;
+  for (int i = 0; i < nb; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNb; ++q)
+      if (q < nb) s += T[i][q] * y[q];
+    col[i] = s;
+  }
+}
+
+// ---- solves with LU factors (one workgroup) ---------------------------------
+// x = A^{-1} b from P A = L U: x <- P b, then L (unit) and U by blocks of 64
+// rows: the block's 64 x 64 diagonal part is staged in LDS, one wavefront
+// solves it with register shuffles, then all threads subtract the block's
+// contribution from the rows after (before) it.  x lives in LDS.
+constexpr int kLuSolveMax = 12288;
+constexpr int kLuB = 64;
+
+__global__ void __launch_bounds__(1024)
+k_lu_solve(int n, const double* lu, const int* perm, const double* b, double* x) {
+  extern __shared__ double xs[];
+  __shared__ double D[kLuB][kLuB + 1];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid % 64;
+  for (int i = tid; i < n; i += nt) xs[i] = b[perm[i]];
+  for (int b0 = 0; b0 < n; b0 += kLuB) {  // forward, unit lower
+    const int nbk = min(kLuB, n - b0);
+    for (int e = tid; e < kLuB * kLuB; e += nt) {
+      const int r = e % kLuB, q = e / kLuB;
+      D[r][q] = (r < nbk && q < nbk) ? lu[static_cast<int64_t>(b0 + q) * n + b0 + r] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double v = lane < nbk ? xs[b0 + lane] : 0.0;
+      for (int q = 0; q < nbk; ++q) {
+        const double xq = __shfl(v, q);
+        if (lane > q) v -= D[lane][q] * xq;
+      }
+      if (lane < nbk) xs[b0 + lane] = v;
+    }
+    __syncthreads();
+    for (int i = b0 + nbk + tid; i < n; i += nt) {
+      double s = xs[i];
+      for (int q = 0; q < nbk; ++q) s -= lu[static_cast<int64_t>(b0 + q) * n + i] * xs[b0 + q];
+      xs[i] = s;
+    }
+    __syncthreads();
+  }
+  for (int b0 = ((n - 1) / kLuB) * kLuB; b0 >= 0; b0 -= kLuB) {  // backward, upper
+    const int nbk = min(kLuB, n - b0);
+    for (int e = tid; e < kLuB * kLuB; e += nt) {
+      const int r = e % kLuB, q = e / kLuB;
+      D[r][q] = (r < nbk && q < nbk) ? lu[static_cast<int64_t>(b0 + q) * n + b0 + r] : 1.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double v = lane < nbk ? xs[b0 + lane] : 0.0;
+      for (int q = nbk - 1; q >= 0; --q) {
+        if (lane == q) v = v / D[q][q];
+        const double xq = __shfl(v, q);
+        if (lane < q) v -= D[lane][q] * xq;
+      }
+      if (lane < nbk) xs[b0 + lane] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < b0; i += nt) {
+      double s = xs[i];
+      for (int q = 0; q < nbk; ++q) s -= lu[static_cast<int64_t>(b0 + q) * n + i] * xs[b0 + q];
+      xs[i] = s;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nt) x[i] = xs[i];
+}
+
 }  // namespace
 
 // builds h->ap_* once; leaves ap_state = -1 if some row of A P has more
@@ -515,8 +716,9 @@ void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const do
   }
 }
 
-// LU of `a` (n x n, overwritten) and inv = A^{-1}
-void lu_inverse(Handle* h, double* a, double* inv, int n) {
+// LU with partial pivoting of `a` in place (P A = L U); perm (device, n):
+// row i of P A is row perm[i] of A
+void lu_factor(Handle* h, double* a, int n, int* perm_out) {
   DBuf<int> ipiv(&h->alloc, n), info(&h->alloc, 1);
   HIPX(hipMemsetAsync(info, 0, sizeof(int), h->stream));
   for (int k0 = 0; k0 < n;) {
@@ -552,12 +754,17 @@ void lu_inverse(Handle* h, double* a, double* inv, int n) {
   HIPX(hipMemcpyAsync(hp.data(), ipiv.get(), n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
   FAMS_REQUIRE(hinfo == 0, FAMS_ERR_SINGULAR_COARSE, "zero pivot in the coarse LU");
-  // P A = L U  =>  A^{-1} = U^{-1} L^{-1} P
   std::vector<int> perm(n);
   for (int r = 0; r < n; ++r) perm[r] = r;
   for (int j = 0; j < n; ++j) std::swap(perm[j], perm[hp[j]]);
+  HIPX(hipMemcpyAsync(perm_out, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
+// LU of `a` (n x n, overwritten) and inv = A^{-1} = U^{-1} L^{-1} P
+void lu_inverse(Handle* h, double* a, double* inv, int n) {
   DBuf<int> dperm(&h->alloc, n);
-  HIPX(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  lu_factor(h, a, n, dperm.get());
   LAUNCH(h, "perm_identity", k_perm_identity, blocks_for(static_cast<int64_t>(n) * n, 256), 256, 0,
          n, dperm.get(), inv);
   for (int k0 = 0; k0 < n; k0 += kNb) {  // L Y = P
@@ -572,6 +779,41 @@ void lu_inverse(Handle* h, double* a, double* inv, int n) {
     LAUNCH(h, "inv_trsm_u", k_trsm_upper, blocks_for(n, 64), 64, 0, a, n, k0, nb, inv, 0, n);
     if (k0 > 0) gemm_sub(h, k0, n, nb, a + static_cast<int64_t>(k0) * n, inv + k0, inv, n);
   }
+}
+
+// inv = A^{-1} by blocked Gauss-Jordan without pivoting; false (inv
+// undefined) if a pivot is not positive, i.e. A is not SPD
+bool spd_inverse(Handle* h, const double* a, double* inv, int n) {
+  DBuf<int> info(&h->alloc, 1);
+  HIPX(hipMemsetAsync(info, 0, sizeof(int), h->stream));
+  HIPX(hipMemcpyAsync(inv, a, sizeof(double) * n * n, hipMemcpyDeviceToDevice, h->stream));
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    const int nb = std::min(kNb, n - k0);
+    LAUNCH(h, "gje_block", k_gje_block, 1, 1024, 0, inv, n, k0, nb, info.get());
+    LAUNCH(h, "gje_col", k_gje_col, blocks_for(n, 256), 256, 0, inv, n, k0, nb);
+    gemm_mfma(h, n, n, nb, 1.0, inv + static_cast<int64_t>(k0) * n, n, inv + k0, n, inv, n, k0,
+              k0 + nb);
+    LAUNCH(h, "gje_row", k_gje_row, blocks_for(n, 256), 256, 0, inv, n, k0, nb);
+  }
+  int hinfo = 0;
+  HIPX(hipMemcpyAsync(&hinfo, info.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  return hinfo == 0;
+}
+
+int lu_solve_limit() { return kLuSolveMax; }
+
+void dense_gemm_add(Handle* h, int m, int p, int k, double alpha, const double* A, int lda,
+                    const double* B, int ldb, double* C, int ldc) {
+  gemm_mfma(h, m, p, k, alpha, A, lda, B, ldb, C, ldc);
+}
+
+// x = A^{-1} b from lu_factor's output
+void lu_solve(Handle* h, const double* lu, const int* perm, int n, const double* b, double* x) {
+  FAMS_REQUIRE(n <= kLuSolveMax, FAMS_ERR_CAPACITY, "coarse system too large for the LU solve");
+  const size_t lds = static_cast<size_t>(n) * sizeof(double);
+  allow_lds(reinterpret_cast<const void*>(&k_lu_solve), lds);
+  LAUNCH(h, "lu_solve", k_lu_solve, 1, 1024, lds, n, lu, perm, b, x);
 }
 
 // part: [ceil(nc / 64) * nc] partial sums

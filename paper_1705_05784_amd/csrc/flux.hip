@@ -257,12 +257,21 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
     LAUNCH(h, "flux_block_ptr", k_block_ptr, g, kT, 0, n, nc, keys.get(), h->fv_ptr.get());
     h->Afv.reset(A, static_cast<size_t>(nc) * nc);
     build_coarse_operator(h, h->fv_ptr, h->fv_order, nullptr, nc, h->Afv);
-    DBuf<double> lu(A, static_cast<size_t>(nc) * nc);
-    HIPX(hipMemcpyAsync(lu, h->Afv.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
-                        h->stream));
-    h->Afv_inv.reset(A, static_cast<size_t>(nc) * nc);
-    lu_inverse(h, lu, h->Afv_inv, nc);
-    HIPX(hipStreamSynchronize(h->stream));
+    // the FV operator is not symmetric: LU with partial pivoting; its three
+    // solves per call use the factors (an explicit inverse costs more)
+    h->Afv_lu.reset(A, static_cast<size_t>(nc) * nc);
+    HIPX(hipMemcpyAsync(h->Afv_lu, h->Afv.get(), sizeof(double) * nc * nc,
+                        hipMemcpyDeviceToDevice, h->stream));
+    if (nc <= lu_solve_limit()) {
+      h->Afv_perm.reset(A, nc);
+      lu_factor(h, h->Afv_lu, nc, h->Afv_perm);
+    } else {  // too large for the one-workgroup solve: keep the inverse instead
+      DBuf<double> inv(A, static_cast<size_t>(nc) * nc);
+      lu_inverse(h, h->Afv_lu, inv, nc);
+      HIPX(hipMemcpyAsync(h->Afv_lu, inv.get(), sizeof(double) * nc * nc,
+                          hipMemcpyDeviceToDevice, h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+    }
     h->fv_ready = true;
   }
   LAUNCH(h, "flux_block_local", k_block_local, g, kT, 0, n, h->fv_order.get(), h->primal.get(),
@@ -282,11 +291,15 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
          r.get());
   LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
          h->fv_order.get(), r.get(), rc.get());
-  coarse_apply(h, h->Afv_inv, nc, rc, x, h->gpart);
+  auto fv_solve = [&](const double* in, double* out) {
+    if (h->Afv_perm.get()) lu_solve(h, h->Afv_lu, h->Afv_perm, nc, in, out);
+    else coarse_apply(h, h->Afv_lu, nc, in, out, h->gpart);   // holds the inverse
+  };
+  fv_solve(rc, x);
   for (int it = 0; it < 2; ++it) {  // iterative refinement of the coarse solve
     coarse_apply(h, h->Afv, nc, x, t, h->gpart);
     LAUNCH(h, "flux_sub", k_sub, blocks_for(nc, kT), kT, 0, nc, rc.get(), t.get(), t.get());
-    coarse_apply(h, h->Afv_inv, nc, t, t2, h->gpart);
+    fv_solve(t, t2);
     LAUNCH(h, "flux_add", k_add_to, blocks_for(nc, kT), kT, 0, nc, t2.get(), x.get());
   }
   LAUNCH(h, "flux_prolong", k_prolong_add, g, kT, 0, n, h->p_rp.get(), h->p_ci.get(),

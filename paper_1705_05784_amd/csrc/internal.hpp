@@ -194,7 +194,8 @@ struct Handle {
 
   // finite-volume stage (built lazily by fams_reconstruct_flux)
   bool fv_ready = false;
-  DBuf<double> Afv, Afv_inv;
+  DBuf<double> Afv, Afv_lu;
+  DBuf<int> Afv_perm;
   DBuf<int> fv_order, fv_ptr;  // cells grouped by primal block
   int fv_max_block = 0;
 
@@ -227,6 +228,12 @@ void build_prolongation(Handle* h, const int8_t* wb);
 void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const double* R_val,
                            int rows, double* out);
 void lu_inverse(Handle* h, double* a, double* inv, int n);
+void lu_factor(Handle* h, double* a, int n, int* perm);
+bool spd_inverse(Handle* h, const double* a, double* inv, int n);
+void lu_solve(Handle* h, const double* lu, const int* perm, int n, const double* b, double* x);
+int lu_solve_limit();
+void dense_gemm_add(Handle* h, int m, int p, int k, double alpha, const double* A, int lda,
+                    const double* B, int ldb, double* C, int ldc);
 void coarse_apply(Handle* h, const double* inv, int nc, const double* x, double* y, double* part);
 // ilu.hip
 void build_ilu(Handle* h);

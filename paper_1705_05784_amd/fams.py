@@ -76,6 +76,7 @@ EXPORTS = {
     "fams_reconstruct_flux": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(C.c_double)], C.c_int),
     "fams_get_setup_info": ([C.c_void_p, C.POINTER(SetupInfo)], C.c_int),
+    "fams_dense_op": ([C.c_int32, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "fams_destroy": ([C.c_void_p], C.c_int),
     "fams_get_prolongation": ([C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p,
                                C.c_void_p], C.c_int),
@@ -310,3 +311,19 @@ def full_grid(sysm, coarse, d_min, r_z):
 def setup(sysm, coarse, d_min, r_z, **kw) -> Solver:
     wb, pr, vx, _ = full_grid(sysm, coarse, d_min, r_z)
     return Solver(sysm.row_ptr, sysm.col, sysm.val, sysm.n_matrix, wb, pr, vx, **kw)
+
+
+def dense_op(op: int, a):
+    """Run one of the coarse system's dense kernels on a (n x n, float64):
+    0 a@a, 1 SPD Gauss-Jordan inverse, 2 pivoted LU inverse, 3 LU-solve
+    inverse.  Returns a torch tensor on the current device."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    a = torch.as_tensor(a).to(device=dev, dtype=torch.float64)
+    n = a.shape[0]
+    ac = a.t().contiguous()            # column-major
+    out = torch.empty_like(ac)
+    torch.cuda.synchronize()
+    _check(lib().fams_dense_op(int(op), int(n), _ptr(ac), _ptr(out)), "fams_dense_op")
+    return out.t().contiguous()
+

@@ -1,0 +1,57 @@
+"""Dense kernels of the coarse system (FP64 MFMA product, Gauss-Jordan and
+LU inverses, the one-workgroup LU solve) against numpy on seeded matrices."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("n", [1, 37, 64, 130, 600])
+def test_mfma_product(n):
+    from paper_1705_05784_amd import fams
+    _say(f"[dense] product n={n}")
+    a = np.random.default_rng(n).standard_normal((n, n))
+    c = fams.dense_op(0, a).cpu().numpy()
+    ref = a @ a
+    assert np.abs(c - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [1, 37, 100, 700, 1855])
+def test_spd_gauss_jordan(n):
+    from paper_1705_05784_amd import fams
+    _say(f"[dense] gauss-jordan n={n}")
+    m = np.random.default_rng(n + 1).standard_normal((n, n))
+    a = m @ m.T / n + np.eye(n)
+    x = fams.dense_op(1, a).cpu().numpy()
+    assert np.abs(x @ a - np.eye(n)).max() <= 1e-10
+
+
+def test_gauss_jordan_rejects_indefinite():
+    from paper_1705_05784_amd import fams
+    a = np.diag([1.0, -1.0, 2.0])
+    with pytest.raises(fams.FamsError):
+        fams.dense_op(1, a)
+
+
+@pytest.mark.parametrize("n", [1, 37, 600, 1500, 2100])
+def test_lu_inverse(n):
+    from paper_1705_05784_amd import fams
+    _say(f"[dense] lu inverse n={n}")
+    a = np.random.default_rng(n + 2).standard_normal((n, n)) + 0.5 * np.eye(n)
+    x = fams.dense_op(2, a).cpu().numpy()
+    ref = np.linalg.inv(a)
+    assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [1, 37, 65, 300])
+def test_lu_solve(n):
+    from paper_1705_05784_amd import fams
+    _say(f"[dense] lu solve n={n}")
+    a = np.random.default_rng(n + 3).standard_normal((n, n)) + 0.5 * np.eye(n)
+    x = fams.dense_op(3, a).cpu().numpy()
+    ref = np.linalg.inv(a)
+    assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
