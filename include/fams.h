@@ -10,8 +10,8 @@
  * strategies, the coarse operator A_c = R A P with R = P^T (Sec. 3, App. A),
  * and iterates the two-stage scheme of Table 1 (multiscale stage + ILU(0)
  * smoothing) either as a Richardson loop or as the preconditioner of GMRES
- * (Sec. 4.4-4.5).  After any iterate a conservative flux field can be
- * reconstructed through a finite-volume stage (Sec. 3.2, Sec. 4.5).
+ * (Sec. 4.4-4.5).  From any iterate, a finite-volume stage yields a
+ * mass-conservative fine-scale flux field (Sec. 3.2, Sec. 4.5).
  *
  * Memory and ownership
  *   - Every array argument marked "device" is caller-owned GPU memory (e.g. a

@@ -16,7 +16,7 @@ formulas (Decoupled, Frac, Rock and Coupled-AMS) in one rule:
       or when it crosses media between same-class blocks that were not
       merged in Coupled-AMS (merge-size limit, Sec. 3.1);
     - "lumped" (removed and added to the diagonal -- the over/underlined
-      blocks of App. A, "removed from the diagonal term") when cut or when
+      diagonal blocks of App. A) when cut or when
       rho(j) < rho(i) (the localisation assumption, Sec. 3.1);
     - a right-hand-side term -A_ij P_j when rho(j) > rho(i) (the higher-rank
       sub-blocks of P act as boundary conditions, App. A.1);
@@ -27,8 +27,8 @@ formulas (Decoupled, Frac, Rock and Coupled-AMS) in one rule:
 * vertex rows are the Kronecker delta of Eq. (kronecker-basis).
 
 Readings where the paper is silent (listed in the design notes):
-  * Coupled-AMS merging (Sec. 3.1 "adjacent dual blocks of the same type are
-    merged", with an optional cap on merged size): first the within-medium
+  * Coupled-AMS merging (Sec. 3.1: neighbouring dual blocks of one type join
+    across media, with an optional cap on merged size): first the within-medium
     blocks; then cross-media couplings between cells of the same class are
     visited in CSR order (i < j) and the two blocks are united unless the
     union would exceed ``merge_cap`` cells -- a rejected coupling is cut;
@@ -37,8 +37,8 @@ Readings where the paper is silent (listed in the design notes):
     before truncation (its partition-of-unity value); if nothing survives the
     largest entry (lowest column on ties) is kept; rows that lose nothing are
     left untouched;
-  * restriction in the iteration: R = P^T (MSFE, "used during all numerical
-    experiments", Sec. 3);
+  * restriction in the iteration: R = P^T (MSFE, the paper's choice for all of
+    its experiments, Sec. 3);
   * GMRES: right preconditioned, restarted, modified Gram-Schmidt, the
     F-AMS two-stage step as preconditioner (Sec. 4.4), stopping on the true
     relative residual ||q - A p|| / ||q|| (p0 = 0).

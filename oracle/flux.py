@@ -4,8 +4,8 @@ Test infrastructure only (see the package docstring).
 
 The paper states (Sec. 1, Sec. 3, Sec. 3.2, Sec. 4.5) that after any stage
 that uses the finite-volume restriction R^FV -- the 0/1 matrix whose row K
-marks the fine cells of primal block K -- a mass-conservative fine-scale flux
-field can be reconstructed, but gives no algorithm.  The reconstruction here
+marks the fine cells of primal block K -- the fine-scale fluxes can be made
+mass conservative, but gives no algorithm.  The reconstruction here
 is the standard multiscale finite-volume one the paper cites:
 
 1. FV stage: A_FV = R^FV A P;  x = A_FV^{-1} R^FV (q - A p) (LU with partial
