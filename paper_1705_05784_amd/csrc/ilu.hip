@@ -33,20 +33,6 @@ __global__ void k_diag_pos(int n, const int* rp, const int* ci, int* diag, int* 
   if (d < 0) atomicOr(err, 1);
 }
 
-__global__ void k_level_relax(int n, const int* rp, const int* ci, const int* diag, int upper,
-                              int* lev, int* changed) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int m = 0;
-  int a = upper ? diag[i] + 1 : rp[i];
-  int b = upper ? rp[i + 1] : diag[i];
-  for (int p = a; p < b; ++p) m = max(m, lev[ci[p]] + 1);
-  if (m > lev[i]) {
-    lev[i] = m;
-    *changed = 1;
-  }
-}
-
 __global__ void k_iota(int n, int* v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = i;
@@ -58,6 +44,62 @@ __global__ void k_level_ptr(int n, const int* key_sorted, int* ptr) {
   int k = key_sorted[t];
   if (t == 0 || key_sorted[t - 1] != k) ptr[k] = t;
   if (t == n - 1) ptr[k + 1] = n;
+}
+
+// ---- dataflow over natural-order chunks ----------------------------------------
+// Dependency levels in one launch per triangle: a workgroup takes the next
+// chunk of 256 consecutive rows (ascending for the lower triangle, descending
+// for the upper one) from a ticket; every dependency of a row lies in the same
+// or an earlier chunk.  A lane never spins on its own: each pass of the loop
+// either finishes its row (all dependencies published) or leaves it for the
+// next pass, so a row that depends on a row of the same wavefront is finished
+// one pass after it.  The loop is bounded by the wall-clock limit and the
+// shared error flag, like the sweeps.
+template <bool kUpper>
+__global__ void __launch_bounds__(256)
+k_levels_df(int n, const int* rp, const int* ci, const int* diag, int* lev, int* ticket,
+            int* err, unsigned long long limit) {
+  __shared__ int s_c;
+  const int nchunks = (n + 255) / 256;
+  while (true) {
+    if (threadIdx.x == 0) s_c = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int c = s_c;
+    __syncthreads();
+    if (c >= nchunks) break;
+    const int i = kUpper ? n - 1 - (c * 256 + static_cast<int>(threadIdx.x))
+                         : c * 256 + static_cast<int>(threadIdx.x);
+    bool done = i < 0 || i >= n;
+    const int p0 = done ? 0 : (kUpper ? diag[i] + 1 : rp[i]);
+    const int p1 = done ? 0 : (kUpper ? rp[i + 1] : diag[i]);
+    const unsigned long long t0 = wall_clock64();
+    // the exit test is a wavefront vote, so a lane that finishes publishes in
+    // the pass where it finishes (no lane leaves the loop on its own, which
+    // would let the compiler move the store past the loop)
+    while (__any(!done)) {
+      if (!done) {
+        int L = 0;
+        bool ready = true;
+        for (int p = p0; p < p1; ++p) {
+          const int v = __hip_atomic_load(lev + ci[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v < 0) {
+            ready = false;
+            break;
+          }
+          L = max(L, v + 1);
+        }
+        if (ready) {
+          __hip_atomic_store(lev + i, L, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          done = true;
+        } else if (wall_clock64() - t0 > limit ||
+                   __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          atomicOr(err, 2);
+          done = true;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
 }
 
 // IKJ elimination of the rows of one level (rows k < i already final)
@@ -385,22 +427,34 @@ __global__ void k_ell_vals(int n, const int* rows, const int* diag, const int* e
   ediag[t] = lu[diag[rows[t]]];
 }
 
+// bound of one dataflow wait: 2 s of the device's constant-rate clock
+unsigned long long wait_limit(Handle* h) {
+  if (!h->wait_ticks) {
+    int dev = 0, khz = 0;
+    HIPX(hipGetDevice(&dev));
+    HIPX(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    h->wait_ticks = 2000ull * static_cast<unsigned long long>(khz > 0 ? khz : 100000);
+  }
+  return h->wait_ticks;
+}
+
 void levels(Handle* h, int upper, Levels* out, std::vector<int>* host_lev) {
   const int n = h->n;
   unsigned g = blocks_for(n, kT);
-  DBuf<int> lev(&h->alloc, n), changed(&h->alloc, 1);
-  HIPX(hipMemsetAsync(lev, 0, n * sizeof(int), h->stream));
-  for (int it = 0;; ++it) {
-    FAMS_REQUIRE(it < 1000000, FAMS_ERR_DEVICE, "ILU level computation did not converge");
-    HIPX(hipMemsetAsync(changed, 0, sizeof(int), h->stream));
-    for (int s = 0; s < 8; ++s)
-      LAUNCH(h, "ilu_levels", k_level_relax, g, kT, 0, n, h->rp.get(), h->ci.get(),
-             h->diag.get(), upper, lev.get(), changed.get());
-    int c = 0;
-    HIPX(hipMemcpyAsync(&c, changed.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPX(hipStreamSynchronize(h->stream));
-    if (!c) break;
-  }
+  DBuf<int> lev(&h->alloc, n), flags(&h->alloc, 2);
+  HIPX(hipMemsetAsync(lev, 0xFF, n * sizeof(int), h->stream));   // -1: not known yet
+  HIPX(hipMemsetAsync(flags, 0, 2 * sizeof(int), h->stream));     // ticket, error
+  const int groups = std::min<int>((n + 255) / 256, 1024);
+  if (upper)
+    LAUNCH(h, "ilu_levels", k_levels_df<true>, groups, 256, 0, n, h->rp.get(), h->ci.get(),
+           h->diag.get(), lev.get(), flags.get(), flags.get() + 1, wait_limit(h));
+  else
+    LAUNCH(h, "ilu_levels", k_levels_df<false>, groups, 256, 0, n, h->rp.get(), h->ci.get(),
+           h->diag.get(), lev.get(), flags.get(), flags.get() + 1, wait_limit(h));
+  int e = 0;
+  HIPX(hipMemcpyAsync(&e, flags.get() + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "ILU level computation did not complete");
   DBuf<int> iota(&h->alloc, n), keys(&h->alloc, n);
   out->rows.reset(&h->alloc, n);
   LAUNCH(h, "iota", k_iota, g, kT, 0, n, iota.get());
@@ -563,12 +617,7 @@ void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
   HIPX(hipMemsetAsync(h->ilu_ticket, 0, 2 * sizeof(int), h->stream));
   const int n = h->n;
   LAUNCH(h, "ilu_arm", k_fill_sentinel<T>, blocks_for(n, kT), kT, 0, n, y);
-  if (!h->wait_ticks) {  // 2 s of the device's constant-rate wall clock
-    int dev = 0, khz = 0;
-    HIPX(hipGetDevice(&dev));
-    HIPX(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    h->wait_ticks = 2000ull * static_cast<unsigned long long>(khz > 0 ? khz : 100000);
-  }
+  wait_limit(h);
   if (h->rng_lo.nranges > 0) {
     Ranges& L = h->rng_lo;
     Ranges& U = h->rng_up;
