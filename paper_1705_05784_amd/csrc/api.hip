@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <memory>
 #include <string>
@@ -81,6 +82,22 @@ Prof::~Prof() {
     (void)hipEventDestroy(pe.a);
     (void)hipEventDestroy(pe.b);
   }
+}
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+PhaseTimer::PhaseTimer(hipStream_t s)
+    : stream(s), on(std::getenv("FAMS_SETUP_TIMING") != nullptr), t_last(now_ms()) {}
+
+void PhaseTimer::mark(const char* what) {
+  if (!on) return;
+  HIPX(hipStreamSynchronize(stream));
+  const double t = now_ms();
+  std::fprintf(stderr, "[setup] %-22s %8.2f ms\n", what, t - t_last);
+  t_last = t;
 }
 
 int64_t lds_budget(Handle* h) {
@@ -184,11 +201,16 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   HIPX(hipStreamSynchronize(h->stream));
   FAMS_REQUIRE(e == 0 && last == A->nnz, FAMS_ERR_INVALID_ARG, "malformed CSR");
 
+  PhaseTimer pt(h->stream);
+  pt.mark("validate");
   build_ilu(h);                 // diagonal positions (+ ILU(0) factors)
+  pt.mark("ilu");
   build_prolongation(h, wb);    // P, R = P^T
+  pt.mark("prolongation");
   const int nc = h->nc;
   h->Ac.reset(al, static_cast<size_t>(nc) * nc);
   build_coarse_operator(h, h->r_rp, h->r_ci, h->r_val, nc, h->Ac);
+  pt.mark("coarse operator");
   {
     // A_c = P^T A P is SPD for SPD A: Gauss-Jordan without pivoting; if a
     // pivot is not positive, LU with partial pivoting
@@ -201,6 +223,7 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
     }
     HIPX(hipStreamSynchronize(h->stream));
   }
+  pt.mark("coarse inverse");
   if (h->precision == FAMS_PREC_MIXED) {
     h->val32.reset(al, h->nnz);
     LAUNCH(h, "d2f", k_d2f_api, blocks_for(h->nnz, 256), 256, 0, h->nnz, h->val.get(),

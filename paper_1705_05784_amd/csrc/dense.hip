@@ -125,29 +125,59 @@ k_ap(int n, const int* rp, const int* ci, const double* av, const int* p_rp, con
   }
 }
 
-// A_c rows: one wavefront per coarse row I, acc[J] += w_e (A P)_{i_e, J} over
-// the restriction row's entries e in order (one wavefront: its LDS accesses
-// are ordered, and the columns of one row of A P are distinct)
-__global__ void __launch_bounds__(64)
+// A_c rows: one workgroup of kRapWaves wavefronts per coarse row I.  Wavefront
+// w takes the w-th quarter of the restriction row's entries e in order and
+// forms acc_w[J] = sum_e w_e (A P)_{i_e, J} in its own LDS copy (one
+// wavefront's LDS accesses are ordered, and the columns of one row of A P are
+// distinct); the copies are then added in wavefront order, so every sum has a
+// fixed order.
+constexpr int kRapWaves = 4;
+
+__global__ void __launch_bounds__(64 * kRapWaves)
 k_rap_ap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int64_t* ap_rp,
          const int* ap_ci, const double* ap_val, double* out, int jt) {
-  extern __shared__ double acc[];
+  extern __shared__ double acc_all[];
   const int I = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  double* acc = acc_all + static_cast<int64_t>(wave) * jt;
+  const int e0 = R_rp[I], e1 = R_rp[I + 1], ne = e1 - e0;
+  const int eb = e0 + static_cast<int>(static_cast<int64_t>(ne) * wave / kRapWaves);
+  const int ee = e0 + static_cast<int>(static_cast<int64_t>(ne) * (wave + 1) / kRapWaves);
   for (int j0 = 0; j0 < nc; j0 += jt) {
     const int j1 = min(nc, j0 + jt);
     for (int t = lane; t < j1 - j0; t += 64) acc[t] = 0.0;
-    __syncthreads();
-    for (int e = R_rp[I]; e < R_rp[I + 1]; ++e) {
-      const int i = R_ci[e];
-      const double w = R_val ? R_val[e] : 1.0;
-      for (int64_t q = ap_rp[i] + lane; q < ap_rp[i + 1]; q += 64) {
+    int64_t q0 = 0, q1 = 0;
+    double w = 0.0;
+    if (eb < ee) {
+      const int i = R_ci[eb];
+      q0 = ap_rp[i];
+      q1 = ap_rp[i + 1];
+      w = R_val ? R_val[eb] : 1.0;
+    }
+    for (int e = eb; e < ee; ++e) {
+      // bounds of the next row while this one is accumulated
+      int64_t n0 = 0, n1 = 0;
+      double nw = 0.0;
+      if (e + 1 < ee) {
+        const int i = R_ci[e + 1];
+        n0 = ap_rp[i];
+        n1 = ap_rp[i + 1];
+        nw = R_val ? R_val[e + 1] : 1.0;
+      }
+      for (int64_t q = q0 + lane; q < q1; q += 64) {
         const int J = ap_ci[q];
         if (J >= j0 && J < j1) acc[J - j0] += w * ap_val[q];
       }
+      q0 = n0;
+      q1 = n1;
+      w = nw;
     }
     __syncthreads();
-    for (int t = lane; t < j1 - j0; t += 64) out[static_cast<int64_t>(j0 + t) * nc + I] = acc[t];
+    for (int t = threadIdx.x; t < j1 - j0; t += blockDim.x) {
+      double v = acc_all[t];
+      for (int k = 1; k < kRapWaves; ++k) v += acc_all[static_cast<int64_t>(k) * jt + t];
+      out[static_cast<int64_t>(j0 + t) * nc + I] = v;
+    }
     __syncthreads();
   }
 }
@@ -560,45 +590,43 @@ __global__ void __launch_bounds__(1024) k_gje_block(double* a, int n, int k0, in
   if (in) a[static_cast<int64_t>(k0 + c) * n + k0 + i] = T[i][c];
 }
 
-// column block rows r outside the block: a[r, blk] <- -a[r, blk] inv(B B)
+// column block rows r outside the block: a[r, blk] <- -a[r, blk] inv(B B).
+// One thread per (row, output column); a workgroup covers 8 rows x 32
+// columns and stages the 8 rows' old values before writing.
 __global__ void __launch_bounds__(256) k_gje_col(double* a, int n, int k0, int nb) {
   __shared__ double T[kNb][kNb + 1];
+  __shared__ double X[8][kNb + 1];
   for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
     T[e % nb][e / nb] = a[static_cast<int64_t>(k0 + e / nb) * n + k0 + e % nb];
+  const int rl = threadIdx.x % 8, c = threadIdx.x / 8;   // 8 rows x 32 columns
+  int r = blockIdx.x * 8 + rl;
+  if (r >= k0) r += nb;                                     // skip the block's rows
+  const bool in = r < n && c < nb;
+  if (in) X[rl][c] = a[static_cast<int64_t>(k0 + c) * n + r];
   __syncthreads();
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n || (r >= k0 && r < k0 + nb)) return;
-  double x[kNb];
-#pragma unroll
-  for (int q = 0; q < kNb; ++q) x[q] = q < nb ? a[static_cast<int64_t>(k0 + q) * n + r] : 0.0;
-  for (int c = 0; c < nb; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < kNb; ++q)
-      if (q < nb) s += x[q] * T[q][c];
-    a[static_cast<int64_t>(k0 + c) * n + r] = -s;
-  }
+  if (!in) return;
+  double s = 0.0;
+  for (int q = 0; q < nb; ++q) s += X[rl][q] * T[q][c];
+  a[static_cast<int64_t>(k0 + c) * n + r] = -s;
 }
 
-// row block columns c outside the block: a[blk, c] <- inv(B B) a[blk, c]
+// row block columns c outside the block: a[blk, c] <- inv(B B) a[blk, c];
+// one thread per (output row, column), 32 x 8 per workgroup
 __global__ void __launch_bounds__(256) k_gje_row(double* a, int n, int k0, int nb) {
   __shared__ double T[kNb][kNb + 1];
+  __shared__ double Y[8][kNb + 1];
   for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
     T[e % nb][e / nb] = a[static_cast<int64_t>(k0 + e / nb) * n + k0 + e % nb];
+  const int i = threadIdx.x % kNb, cl = threadIdx.x / kNb;  // 32 rows x 8 columns
+  int c = blockIdx.x * 8 + cl;
+  if (c >= k0) c += nb;
+  const bool in = c < n && i < nb;
+  if (in) Y[cl][i] = a[static_cast<int64_t>(c) * n + k0 + i];
   __syncthreads();
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n || (c >= k0 && c < k0 + nb)) return;
-  double y[kNb];
-  double* col = a + static_cast<int64_t>(c) * n + k0;
-#pragma unroll
-  for (int q = 0; q < kNb; ++q) y[q] = q < nb ? col[q] : 0.0;
-  for (int i = 0; i < nb; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < kNb; ++q)
-      if (q < nb) s += T[i][q] * y[q];
-    col[i] = s;
-  }
+  if (!in) return;
+  double s = 0.0;
+  for (int q = 0; q < nb; ++q) s += T[i][q] * Y[cl][q];
+  a[static_cast<int64_t>(c) * n + k0 + i] = s;
 }
 
 // ---- solves with LU factors (one workgroup) ---------------------------------
@@ -708,7 +736,9 @@ void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const do
   const int jt = std::min(nc, 4096);
   build_ap(h);
   if (h->ap_state == 1) {
-    LAUNCH(h, "rap", k_rap_ap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val,
+    const size_t lds = static_cast<size_t>(kRapWaves) * jt * sizeof(double);
+    allow_lds(reinterpret_cast<const void*>(&k_rap_ap), lds);
+    LAUNCH(h, "rap", k_rap_ap, rows, 64 * kRapWaves, lds, nc, R_rp, R_ci, R_val,
            h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, jt);
   } else {  // rows of A P too wide for the table: the direct triple product
     LAUNCH(h, "rap", k_rap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val, h->rp.get(),
@@ -790,10 +820,10 @@ bool spd_inverse(Handle* h, const double* a, double* inv, int n) {
   for (int k0 = 0; k0 < n; k0 += kNb) {
     const int nb = std::min(kNb, n - k0);
     LAUNCH(h, "gje_block", k_gje_block, 1, 1024, 0, inv, n, k0, nb, info.get());
-    LAUNCH(h, "gje_col", k_gje_col, blocks_for(n, 256), 256, 0, inv, n, k0, nb);
+    if (n > nb) LAUNCH(h, "gje_col", k_gje_col, blocks_for(n - nb, 8), 256, 0, inv, n, k0, nb);
     gemm_mfma(h, n, n, nb, 1.0, inv + static_cast<int64_t>(k0) * n, n, inv + k0, n, inv, n, k0,
               k0 + nb);
-    LAUNCH(h, "gje_row", k_gje_row, blocks_for(n, 256), 256, 0, inv, n, k0, nb);
+    if (n > nb) LAUNCH(h, "gje_row", k_gje_row, blocks_for(n - nb, 8), 256, 0, inv, n, k0, nb);
   }
   int hinfo = 0;
   HIPX(hipMemcpyAsync(&hinfo, info.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));

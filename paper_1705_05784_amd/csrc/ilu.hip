@@ -577,15 +577,18 @@ void build_ilu(Handle* h) {
   HIPX(hipStreamSynchronize(h->stream));
   FAMS_REQUIRE(e == 0, FAMS_ERR_INVALID_ARG, "a row of A has no stored diagonal");
   if (!h->smoother) return;
+  PhaseTimer pt(h->stream);
   std::vector<int> lev_lo, lev_up;
   levels(h, 0, &h->lvl_lo, &lev_lo);
   levels(h, 1, &h->lvl_up, &lev_up);
+  pt.mark("ilu levels");
   chunk_table(h, &h->lvl_lo);
   chunk_table(h, &h->lvl_up);
   if (const int S = sweep_range_rows(h)) {
     range_table(h, lev_lo, S, 0, &h->rng_lo);
     range_table(h, lev_up, S, 1, &h->rng_up);
   }
+  pt.mark("ilu schedules");
   h->info.ilu_levels_lower = h->lvl_lo.count();
   h->info.ilu_levels_upper = h->lvl_up.count();
   h->ilu.reset(&h->alloc, h->nnz);
@@ -599,6 +602,7 @@ void build_ilu(Handle* h) {
   HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
   FAMS_REQUIRE(e == 0, FAMS_ERR_ZERO_PIVOT_ILU, "non-positive ILU(0) pivot");
+  pt.mark("ilu factor");
   if (h->precision == FAMS_PREC_MIXED) {
     h->ilu32.reset(&h->alloc, h->nnz);
     LAUNCH(h, "d2f", k_d2f_ilu, blocks_for(h->nnz, kT), kT, 0, h->nnz, h->ilu.get(),

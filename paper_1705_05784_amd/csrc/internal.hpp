@@ -145,6 +145,16 @@ struct Ranges {
   DBuf<float> eval32, ediag32;
 };
 
+// Host phase timer: with FAMS_SETUP_TIMING set, mark() synchronises the
+// stream and prints the time since the previous mark (diagnostics only).
+struct PhaseTimer {
+  hipStream_t stream;
+  bool on;
+  double t_last;
+  explicit PhaseTimer(hipStream_t s);
+  void mark(const char* what);
+};
+
 // ---- the handle ------------------------------------------------------------
 struct Handle {
   Allocator alloc;

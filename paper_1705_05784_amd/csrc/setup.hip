@@ -857,6 +857,7 @@ void build_prolongation(Handle* h, const int8_t* wb) {
   const int n = h->n, nm = h->nm, nc = h->nc;
   unsigned g = blocks_for(n, kThreads);
   Allocator* A = &h->alloc;
+  PhaseTimer pt(h->stream);
 
   DBuf<int> coarse_of(A, n), err(A, 1);
   DBuf<int8_t> rho(A, n), ecls(A, h->nnz);
@@ -999,6 +1000,7 @@ void build_prolongation(Handle* h, const int8_t* wb) {
     cols_size = new_size;
   }
 
+  pt.mark("blocks + column sets");
   // numeric: solve the blocks level by level
   std::vector<int64_t> h_pval_off(ncomp + 1, 0);
   for (int K = 0; K < ncomp; ++K)
@@ -1050,6 +1052,7 @@ void build_prolongation(Handle* h, const int8_t* wb) {
       ev = static_cast<int>(read1(h, err.get()));
     }
     FAMS_REQUIRE(!(ev & E_PIVOT), FAMS_ERR_SINGULAR_LOCAL, "non-positive pivot in a local block");
+    pt.mark("local solves (level)");
   }
   h->info.fp32_fallback_blocks = fallbacks;
 
@@ -1104,6 +1107,7 @@ void build_prolongation(Handle* h, const int8_t* wb) {
            h->r_val32.get());
   }
   HIPX(hipStreamSynchronize(h->stream));
+  pt.mark("P and R");
 }
 
 }  // namespace fams
