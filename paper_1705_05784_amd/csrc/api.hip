@@ -107,6 +107,7 @@ int64_t lds_budget(Handle* h) {
     HIPX(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     // leave room for the kernels' static LDS
     h->lds_bytes = std::min<int64_t>(std::max(v, 65536), 160 * 1024) - 4096;
+    h->lds_hw_bytes = h->lds_bytes;
     // FAMS_LDS_LIMIT (bytes) lowers the budget, which moves local blocks to
     // the global-memory storage modes (used to exercise those modes on small
     // problems)
@@ -116,6 +117,11 @@ int64_t lds_budget(Handle* h) {
     }
   }
   return h->lds_bytes;
+}
+
+int64_t lds_hw_budget(Handle* h) {
+  lds_budget(h);
+  return h->lds_hw_bytes;
 }
 
 void allow_lds(const void* kernel, size_t bytes) {

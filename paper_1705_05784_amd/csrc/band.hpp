@@ -24,6 +24,15 @@
 
 namespace fams {
 
+// Workgroup barrier that orders LDS only: waits for the wave's LDS accesses
+// (lgkmcnt) but not for its global loads and stores, which may stay in
+// flight across it.  For barriers that publish LDS data only.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 constexpr int kPanel = 16;   // columns per panel of the blocked factorisation
 constexpr int kPanelRowsPerThread = 2;  // panel rows b + kPanel <= 2 * 256 threads
 constexpr int kSubRows = 8;  // rows per block of the substitution
@@ -76,7 +85,7 @@ __device__ bool band_factor_inplace(TC* B, int n, int b) {
       for (int s = 1 + lane; s <= t; s += 64)
         row[b - (t - s)] -= lt * B[static_cast<int64_t>(k + s) * w + b - s];
     }
-    __syncthreads();
+    lds_barrier();
   }
   return bad;
 }
@@ -89,7 +98,7 @@ __device__ void band_normalise(TC* B, int n, int b) {
     const int r = static_cast<int>(e / w), t = b - static_cast<int>(e % w);
     if (t > 0 && r - t >= 0) B[e] /= B[static_cast<int64_t>(r - t) * w + b];
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Blocked factorisation of the band G in global memory (mode 1 / 2 above).
@@ -124,7 +133,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
         const int r = r0 + static_cast<int>(e / w), c = static_cast<int>(e % w);
         rowp(r)[c] = G[static_cast<int64_t>(r) * w + c];
       }
-      __syncthreads();
+      lds_barrier();
     }
     // eliminate the panel's columns with its rows in registers (thread t
     // owns rows t and t + blockDim.x); at step c the owners of rows c..nb-1
@@ -145,7 +154,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
         TC* cb = colbuf + (c & 1) * kPanel;
         if (static_cast<int>(threadIdx.x) >= c && static_cast<int>(threadIdx.x) < nb)
           cb[threadIdx.x] = pr[0][c];
-        __syncthreads();
+        lds_barrier();
         const TC d = cb[c];
         if (!(d > TC(0))) bad = true;
         const TC rd = TC(1) / d;
@@ -169,7 +178,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
         for (int c = 0; c < kPanel; ++c) P[ii * PS + c] = pr[h2][c];
       }
     }
-    __syncthreads();
+    lds_barrier();
     // D and unit-lower L of the panel's columns; Q for the trailing update
     for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
       const int ii = e / kPanel, c = e % kPanel, t = ii - c;
@@ -178,7 +187,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
       if (in) rowp(k + ii)[b - t] = v;
       if (ii >= nb) Q[c * mrow + ii] = v;
     }
-    __syncthreads();
+    lds_barrier();
     // trailing update: A(k+ii, k+jj) -= sum_c P[ii][c] Q[c][jj], nb <= jj <= ii < np
     for (int ii = nb + wave; ii < np; ii += nwaves) {
       const TC* p = P + ii * PS;        // the same LDS address in every lane
@@ -202,15 +211,16 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
         }
       }
     }
-    __syncthreads();
+    if constexpr (kRing) lds_barrier(); else __syncthreads();  // global trailing rows
     if constexpr (kRing) {  // rows k .. k+nb-1 are final
       for (int64_t e = threadIdx.x; e < static_cast<int64_t>(nb) * w; e += blockDim.x) {
         const int r = k + static_cast<int>(e / w), c = static_cast<int>(e % w);
         G[static_cast<int64_t>(r) * w + c] = rowp(r)[c];
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
+  __syncthreads();  // the factor rows in G are read by other threads next
   return bad;
 }
 
@@ -230,13 +240,13 @@ __device__ void band_substitute(const TC* B, int n, int b, TX* X, int nck, TC* S
   TC* Dg = S + static_cast<int64_t>(nj) * R;
   for (int i0 = 0; i0 < n; i0 += R) {
     const int nr = min(R, n - i0);
-    __syncthreads();
+    lds_barrier();
     for (int e = threadIdx.x; e < nj * R; e += blockDim.x) {
       const int j = e / R, r = e % R;
       const int k = i0 - b + j, t = b + r - j;  // L(i0+r, k)
       T[e] = (r < nr && k >= 0 && t >= 1 && t <= b) ? B[static_cast<int64_t>(i0 + r) * w + b - t] : TC(0);
     }
-    __syncthreads();
+    lds_barrier();
     const int jb = max(0, b - i0);
     for (int c = threadIdx.x; c < nck; c += blockDim.x) {
       TC acc[R];
@@ -266,7 +276,7 @@ __device__ void band_substitute(const TC* B, int n, int b, TX* X, int nck, TC* S
   const int nblk = (n + R - 1) / R;
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int i0 = blk * R, nr = min(R, n - i0);
-    __syncthreads();
+    lds_barrier();
     for (int e = threadIdx.x; e < nj * R; e += blockDim.x) {
       const int j = e / R, r = e % R;
       const int i = i0 + j, t = j - r;  // L(i0+j, i0+r)
@@ -274,7 +284,7 @@ __device__ void band_substitute(const TC* B, int n, int b, TX* X, int nck, TC* S
     }
     if (threadIdx.x < R)
       Dg[threadIdx.x] = static_cast<int>(threadIdx.x) < nr ? B[static_cast<int64_t>(i0 + threadIdx.x) * w + b] : TC(1);
-    __syncthreads();
+    lds_barrier();
     const int je = min(nj, n - i0);
     for (int c = threadIdx.x; c < nck; c += blockDim.x) {
       TC acc[R];

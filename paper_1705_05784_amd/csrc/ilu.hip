@@ -11,10 +11,12 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <type_traits>
 #include <vector>
 
+#include "band.hpp"
 #include "internal.hpp"
 
 namespace fams {
@@ -283,8 +285,6 @@ k_sweep_upper(const int* rows, const int* chunk, int nchunks, const int* rp, con
 // and arithmetic are all that a level costs on the critical path.  A range
 // depends only on earlier tickets, whose workgroups are already running, so
 // the schedule always progresses; every wait is bounded as above.
-constexpr int kSegCache = 1024;   // level boundaries of a range kept in LDS
-
 template <class T>
 struct SweepRow {
   using U = typename Sentinel<T>::U;
@@ -295,27 +295,34 @@ struct SweepRow {
   U raw[kEll];
 };
 
+// the part of a row's data addressed by its sweep position t alone (the
+// input is gathered into sweep order beforehand)
+// (loads are issued unconditionally -- position 0 stands in for "no row" --
+// so every thread issues the same number of loads per level and the
+// compiler's wait counts stay exact instead of draining all loads in flight)
 template <class T>
-__device__ __forceinline__ void sweep_fetch(SweepRow<T>& w, int t, int lo, int hi,
-                                            const int* rows, const int* ecol, const T* eval,
-                                            const int* ecnt, const T* ediag, const T* in,
-                                            const T* g) {
+__device__ __forceinline__ void fetch_static(SweepRow<T>& w, int t, const int* rows,
+                                             const int* ecol, const T* eval, const int* ecnt,
+                                             const T* ediag, const T* inp) {
   w.t = t;
-  if (t < 0) return;
-  w.i = rows[t];
-  w.cnt = ecnt[t];
-  w.dg = ediag[t];
+  const int64_t u = t < 0 ? 0 : t;
+  w.i = rows[u];
+  w.cnt = ecnt[u];
+  w.dg = ediag[u];
+  w.in = inp[u];
 #pragma unroll
   for (int k = 0; k < kEll; ++k) {
-    w.col[k] = ecol[static_cast<int64_t>(t) * kEll + k];
-    w.val[k] = eval[static_cast<int64_t>(t) * kEll + k];
+    w.col[k] = ecol[u * kEll + k];
+    w.val[k] = eval[u * kEll + k];
   }
-  w.in = in[w.i];
+}
+
+// first read of every dependency in global memory (only those outside the
+// range [lo, hi) are used later; the others come from LDS)
+template <class T>
+__device__ __forceinline__ void fetch_raw(SweepRow<T>& w, const T* g) {
 #pragma unroll
-  for (int k = 0; k < kEll; ++k) {
-    const int j = w.col[k];
-    w.raw[k] = (j >= 0 && (j < lo || j >= hi)) ? load_raw<T>(g + j) : typename SweepRow<T>::U(0);
-  }
+  for (int k = 0; k < kEll; ++k) w.raw[k] = load_raw<T>(g + max(w.col[k], 0));
 }
 
 template <class T, bool kUpper>
@@ -350,15 +357,24 @@ __device__ __forceinline__ void sweep_row(const SweepRow<T>& w, int lo, int hi, 
   store_ready<T>(g + w.i, s);
 }
 
+// Range sweep kernel.  Each thread keeps four levels in flight in a register
+// ring: at level k it issues the position-addressed loads of level k+3 and
+// the outside-range reads of level k+2, then computes its row of level k
+// (loads are issued ~3 levels before use, so a level costs about a barrier
+// and its arithmetic).  The level loop is unrolled by four so the ring is
+// indexed at compile time.
 template <class T, bool kUpper>
 __global__ void __launch_bounds__(256)
 k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const int* segbase,
                const int* ecol, const T* eval, const int* ecnt, const int* ep0, const T* ediag,
-               const int* ci, const T* lu, const T* in, T* out, T* arm, int* ticket, int* err,
-               unsigned long long limit) {
+               const int* ci, const T* lu, const T* inp, T* out, T* arm, int* ticket, int* err,
+               unsigned long long limit, unsigned long long* trace) {
+  // dynamic LDS: the range's values (S entries of T), then its level
+  // boundaries (max_segs + 1 ints; always in LDS, so every read of them is
+  // an LDS read and never waits on the global loads in flight)
   extern __shared__ double lds_raw[];
   T* loc = reinterpret_cast<T*>(lds_raw);
-  __shared__ int s_seg[kSegCache + 1];
+  int* s_seg = reinterpret_cast<int*>(loc + S);
   __shared__ int s_c;
   const int tid = threadIdx.x, nt = blockDim.x;
   while (true) {
@@ -367,35 +383,58 @@ k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const
     const int c = s_c;
     if (c >= nranges) break;
     const int r = kUpper ? nranges - 1 - c : c;
+    if (trace && tid == 0) trace[4 * r] = wall_clock64();
     const int r0 = r * S, r1 = min(n, r0 + S);
     const int sb = segbase[r], ns = segbase[r + 1] - sb;
-    const bool cached = ns <= kSegCache;
-    if (cached)
-      for (int k = tid; k <= ns; k += nt) s_seg[k] = seg[sb + k];
+    for (int k = tid; k <= ns; k += nt) s_seg[k] = seg[sb + k];
     __syncthreads();
-    auto segat = [&](int k) { return cached ? s_seg[k] : seg[sb + k]; };
-    SweepRow<T> nxt;
-    {
-      const int t = segat(0) + tid;
-      sweep_fetch<T>(nxt, t < segat(1) ? t : -1, r0, r1, rows, ecol, eval, ecnt, ediag, in, out);
-    }
-    for (int k = 0; k < ns; ++k) {
-      const SweepRow<T> cur = nxt;
-      const int a = segat(k), b = segat(k + 1);
-      if (k + 1 < ns) {
-        const int t = segat(k + 1) + tid;
-        sweep_fetch<T>(nxt, t < segat(k + 2) ? t : -1, r0, r1, rows, ecol, eval, ecnt, ediag,
-                       in, out);
-      }
+    auto segat = [&](int k) { return s_seg[k]; };
+    auto pos = [&](int lvl) {
+      if (lvl >= ns) return -1;
+      const int t = segat(lvl) + tid;
+      return t < segat(lvl + 1) ? t : -1;
+    };
+    auto fst = [&](SweepRow<T>& w, int lvl) {
+      fetch_static<T>(w, pos(lvl), rows, ecol, eval, ecnt, ediag, inp);
+    };
+    auto step = [&](int lvl, SweepRow<T>& cur, SweepRow<T>& n2, SweepRow<T>& n3) {
+      fst(n3, lvl + 3);
+      fetch_raw<T>(n2, out);
       if (cur.t >= 0) sweep_row<T, kUpper>(cur, r0, r1, loc, out, arm, ep0, ci, lu, err, limit);
+      const int a = segat(lvl), b = segat(lvl + 1);
       for (int t = a + tid + nt; t < b; t += nt) {  // levels wider than the workgroup
         SweepRow<T> w;
-        sweep_fetch<T>(w, t, r0, r1, rows, ecol, eval, ecnt, ediag, in, out);
+        fetch_static<T>(w, t, rows, ecol, eval, ecnt, ediag, inp);
+        fetch_raw<T>(w, out);
         sweep_row<T, kUpper>(w, r0, r1, loc, out, arm, ep0, ci, lu, err, limit);
       }
-      __syncthreads();
+      lds_barrier();  // the level's values in loc; global traffic stays in flight
+      if (trace && tid == 0 && lvl == 0) trace[4 * r + 2] = wall_clock64();
+    };
+    SweepRow<T> s0, s1, s2, s3;
+    fst(s0, 0);
+    fst(s1, 1);
+    fst(s2, 2);
+    fetch_raw<T>(s0, out);
+    fetch_raw<T>(s1, out);
+    for (int k = 0; k < ns; k += 4) {
+      step(k, s0, s2, s3);
+      if (k + 1 < ns) step(k + 1, s1, s3, s0);
+      if (k + 2 < ns) step(k + 2, s2, s0, s1);
+      if (k + 3 < ns) step(k + 3, s3, s1, s2);
+    }
+    if (trace && tid == 0) {
+      trace[4 * r + 1] = wall_clock64();
+      trace[4 * r + 3] = static_cast<unsigned long long>(ns) | (static_cast<unsigned long long>(blockIdx.x) << 32);
     }
   }
+}
+
+// x[t] = v[rows[t]]: a sweep's input in sweep order
+template <class T>
+__global__ void k_gather(int n, const int* rows, const T* v, T* x) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v[rows[t]];
 }
 
 // ELL form of the dependencies of every position of a range schedule
@@ -518,6 +557,8 @@ void range_table(Handle* h, const std::vector<int>& lev, int S, int upper, Range
   }
   segbase[nr] = static_cast<int>(seg.size());
   seg.push_back(n);
+  R->max_segs = 0;
+  for (int r = 0; r < nr; ++r) R->max_segs = std::max(R->max_segs, segbase[r + 1] - segbase[r]);
   R->S = S;
   R->nranges = nr;
   R->rows.reset(&h->alloc, n);
@@ -537,6 +578,29 @@ void range_table(Handle* h, const std::vector<int>& lev, int S, int upper, Range
          h->rp.get(), h->diag.get(), h->ci.get(), R->ecol.get(), R->epos.get(), R->ecnt.get(),
          R->ep0.get());
   HIPX(hipStreamSynchronize(h->stream));
+}
+
+void print_sweep_trace(Handle* h, const unsigned long long* d, int nl, int nu) {
+  std::vector<unsigned long long> t(4 * static_cast<size_t>(nl + nu));
+  HIPX(hipMemcpyAsync(t.data(), d, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  for (int part = 0; part < 2; ++part) {
+    const int base = part ? nl : 0, cnt = part ? nu : nl;
+    unsigned long long t0 = ~0ull, t1 = 0;
+    for (int r = 0; r < cnt; ++r) {
+      t0 = std::min(t0, t[4 * (base + r)]);
+      t1 = std::max(t1, t[4 * (base + r) + 1]);
+    }
+    std::fprintf(stderr, "[sweep %s] %d ranges, %.1f us total (ticks of 10 ns)\n",
+                 part ? "upper" : "lower", cnt, (t1 - t0) * 0.01);
+    for (int r = 0; r < cnt; r += std::max(1, cnt / 12)) {
+      const unsigned long long* q = &t[4 * (base + r)];
+      std::fprintf(stderr, "   range %3d: start %8.1f first-level %6.1f end %8.1f us, %4llu levels\n",
+                   r, (q[0] - t0) * 0.01, (q[2] - q[0]) * 0.01, (q[1] - t0) * 0.01,
+                   q[3] & 0xffffffffull);
+    }
+  }
 }
 
 // factor values of a range schedule in precision T (gathered once)
@@ -635,17 +699,37 @@ void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
       ell_values<float>(h, &U, lu, U.eval32, U.ediag32);
       lv = L.eval32.get(); ld = L.ediag32.get(); uv = U.eval32.get(); ud = U.ediag32.get();
     }
-    const size_t lds = static_cast<size_t>(L.S) * sizeof(T);
+    const size_t lds = static_cast<size_t>(L.S) * sizeof(T) +
+                       static_cast<size_t>(std::max(L.max_segs, U.max_segs) + 1) * sizeof(int);
+    FAMS_REQUIRE(lds <= static_cast<size_t>(lds_hw_budget(h)), FAMS_ERR_CAPACITY,
+                 "ILU range schedule does not fit in LDS");
     allow_lds(reinterpret_cast<const void*>(&k_sweep_ranges<T, false>), lds);
     allow_lds(reinterpret_cast<const void*>(&k_sweep_ranges<T, true>), lds);
+    T* inp;
+    if constexpr (std::is_same<T, double>::value) {
+      if (!h->sweep_in64.get()) h->sweep_in64.reset(&h->alloc, n);
+      inp = h->sweep_in64.get();
+    } else {
+      if (!h->sweep_in32.get()) h->sweep_in32.reset(&h->alloc, n);
+      inp = h->sweep_in32.get();
+    }
+    // FAMS_SWEEP_TRACE: per-range start / first level / end stamps of one
+    // application (diagnostics)
+    static const bool trace_on = std::getenv("FAMS_SWEEP_TRACE") != nullptr;
+    DBuf<unsigned long long> tr;
+    if (trace_on) tr.reset(&h->alloc, 4 * static_cast<size_t>(L.nranges + U.nranges));
+    LAUNCH(h, "ilu_gather", k_gather<T>, blocks_for(n, kT), kT, 0, n, L.rows.get(), b, inp);
     LAUNCH(h, "ilu_lower", (k_sweep_ranges<T, false>), std::min(L.nranges, 2048), 256, lds, n,
            L.S, L.nranges, L.rows.get(), L.seg.get(), L.segbase.get(), L.ecol.get(), lv,
-           L.ecnt.get(), L.ep0.get(), ld, h->ci.get(), lu, b, y, x, h->ilu_ticket.get(),
-           h->sweep_err.get(), h->wait_ticks);
+           L.ecnt.get(), L.ep0.get(), ld, h->ci.get(), lu, inp, y, x, h->ilu_ticket.get(),
+           h->sweep_err.get(), h->wait_ticks, tr.get());
+    LAUNCH(h, "ilu_gather", k_gather<T>, blocks_for(n, kT), kT, 0, n, U.rows.get(), y, inp);
     LAUNCH(h, "ilu_upper", (k_sweep_ranges<T, true>), std::min(U.nranges, 2048), 256, lds, n,
            U.S, U.nranges, U.rows.get(), U.seg.get(), U.segbase.get(), U.ecol.get(), uv,
-           U.ecnt.get(), U.ep0.get(), ud, h->ci.get(), lu, y, x, nullptr,
-           h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks);
+           U.ecnt.get(), U.ep0.get(), ud, h->ci.get(), lu, inp, x, nullptr,
+           h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks,
+           tr.get() ? tr.get() + 4 * static_cast<size_t>(L.nranges) : nullptr);
+    if (trace_on) print_sweep_trace(h, tr.get(), L.nranges, U.nranges);
     return;
   }
   // a window of ~kSweepGroups chunks in flight: enough to overlap tens of

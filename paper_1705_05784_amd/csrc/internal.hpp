@@ -197,10 +197,13 @@ struct Handle {
   DBuf<float> ilu32;
   Levels lvl_lo, lvl_up;
   Ranges rng_lo, rng_up;
+  DBuf<double> sweep_in64;  // a sweep's input gathered into sweep order
+  DBuf<float> sweep_in32;
   DBuf<int> ilu_ticket;  // work tickets of the two sweeps
   DBuf<int> sweep_err;   // set when a bounded wait in a sweep gives up
   unsigned long long wait_ticks = 0;  // bound of one wait, device wall-clock ticks
-  int64_t lds_bytes = 0;              // dynamic LDS budget per workgroup
+  int64_t lds_bytes = 0;              // dynamic LDS budget of the local block solves
+  int64_t lds_hw_bytes = 0;           // dynamic LDS per workgroup the device allows
 
   // finite-volume stage (built lazily by fams_reconstruct_flux)
   bool fv_ready = false;
@@ -223,6 +226,7 @@ struct Handle {
 // dynamic LDS budget of one workgroup on this device (bytes, <= 160 KiB), and
 // raising a kernel's dynamic LDS limit to `bytes` (api.hip)
 int64_t lds_budget(Handle* h);
+int64_t lds_hw_budget(Handle* h);
 void allow_lds(const void* kernel, size_t bytes);
 
 // ---- launchers implemented in the .hip files --------------------------------
