@@ -19,12 +19,14 @@
 #include <vector>
 
 #include "band.hpp"
+#include "order.hpp"
 #include "internal.hpp"
 
 namespace fams {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kFvRefine = 2;  // refinement steps of the FV coarse solve
 constexpr double kSingularRowsum = 1e-10;  // s_i <= this * max A_ii counts as zero
 
 __global__ void k_rowsum_diag(int n, const int* rp, const int* ci, const double* av, double* s,
@@ -150,11 +152,29 @@ __global__ void k_prolong_add(int n, const int* prp, const int* pci, const doubl
   y[i] = p[i] + t;
 }
 
+// couplings inside primal block K
+struct PrimalEdge {
+  const int* primal;
+  const int* ci;
+  __device__ bool operator()(int p, int i, int K) const {
+    const int j = ci[p];
+    return j != i && primal[j] == K;
+  }
+};
+
+// Neumann problem of primal block K for the correction d = p'' - p' (p' the
+// FV pressure): (A_KK with diagonal A_ii + sum_{j not in K} A_ij) d = q - A p'
+// on the block, the right-hand side in flux form
+//   q_i - s_i p'_i + sum_{j != i} A_ij (p'_i - p'_j)   (s_i = row sum of A),
+// whose terms are of the size of the fluxes (not of A_ij p'_j, which at a
+// high permeability contrast are many orders larger), then one step of
+// iterative refinement with the resident factors.  A block without a
+// Dirichlet cell is pinned at its coarse node (d = 0 there).
 __global__ void __launch_bounds__(kT)
 k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const double* av,
           const int* primal, const int* local, const int* vertex, const int* band,
           const int* singular, const int64_t* band_off, double* band_glob, int lds_elems,
-          const double* q, const double* p1, double* xs, double* p2, int* err) {
+          const double* q, const double* p1, double* xs, double* rs, double* p2, int* err) {
   extern __shared__ double lds[];
   int K = blockIdx.x;
   int beg = ptr[K], n = ptr[K + 1] - beg;
@@ -163,38 +183,73 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
   const int mode = band_mode(n, b, lds_elems);
   double* B = mode == 0 ? lds : band_glob + band_off[K];
   double* X = xs + beg;
+  double* R = rs + beg;                    // residual / correction
+  double* Rq = rs + ptr[gridDim.x] + beg;  // the right-hand side, kept
   const bool pin = singular[K] != 0;
   const int lv = pin ? local[vertex[K]] : -1;
-  const double pv = pin ? p1[vertex[K]] : 0.0;
   for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = 0.0;
   __syncthreads();
   for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    int i = cells[beg + l];
-    double dg = 0.0, rhs = q[i];
+    const int i = cells[beg + l];
+    const double pi = p1[i];
+    double dg = 0.0, rs_i = 0.0, rhs = q[i];
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
-      int j = ci[p];
-      double a = av[p];
+      const int j = ci[p];
+      const double a = av[p];
+      rs_i += a;
       if (j == i) {
         dg += a;
-      } else if (primal[j] == K) {
-        int lj = local[j];
-        if (pin && lj == lv) rhs -= a * pv;           // pinned value moves to the RHS
-        else if (lj < l && l != lv) B[static_cast<int64_t>(l) * w + b - (l - lj)] = a;
+        continue;
+      }
+      rhs += a * (pi - p1[j]);
+      if (primal[j] == K) {
+        const int lj = local[j];
+        if (lj < l && lj != lv && l != lv) B[static_cast<int64_t>(l) * w + b - (l - lj)] = a;
       } else {
         dg += a;
-        rhs += a * (p1[i] - p1[j]);
       }
     }
+    rhs -= rs_i * pi;
     if (l == lv) {
       dg = 1.0;
-      rhs = pv;
+      rhs = 0.0;
     }
     B[static_cast<int64_t>(l) * w + b] = dg;
     X[l] = rhs;
+    Rq[l] = rhs;
   }
   __syncthreads();
   bool bad = band_ldlt_solve<double, double>(mode, B, n, b, X, 1, lds);
-  for (int l = threadIdx.x; l < n; l += blockDim.x) p2[cells[beg + l]] = X[l];
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {  // residual of the correction
+    const int i = cells[beg + l];
+    double r = Rq[l];
+    if (l == lv) {
+      r -= X[l];
+    } else {
+      double dg = 0.0;
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        const double a = av[p];
+        if (j == i) {
+          dg += a;
+        } else if (primal[j] == K) {
+          const int lj = local[j];
+          if (lj != lv) r -= a * X[lj];
+        } else {
+          dg += a;
+        }
+      }
+      r -= dg * X[l];
+    }
+    R[l] = r;
+  }
+  __syncthreads();
+  band_substitute<double, double>(B, n, b, R, 1,
+                                  mode == 0 ? lds + static_cast<int64_t>(n) * w : lds);
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const int i = cells[beg + l];
+    p2[i] = p1[i] + (X[l] + R[l]);
+  }
   if (bad && threadIdx.x == 0) atomicOr(err, 1);
 }
 
@@ -255,6 +310,15 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
     while ((int64_t(1) << bits) <= nc) ++bits;
     sort_pairs_i32(h, h->primal, keys, iota, h->fv_order, n, bits);
     LAUNCH(h, "flux_block_ptr", k_block_ptr, g, kT, 0, n, nc, keys.get(), h->fv_ptr.get());
+    {  // breadth-first local order inside each primal block where it narrows
+       // the band (fracture blocks whose cells lie on several plates)
+      DBuf<int> loc0(A, n);
+      LAUNCH(h, "flux_block_local", k_block_local, g, kT, 0, n, h->fv_order.get(),
+             h->primal.get(), h->fv_ptr.get(), loc0.get());
+      LAUNCH(h, "flux_order", k_local_order<PrimalEdge>, nc, 256, 0, h->fv_ptr.get(),
+             h->fv_order.get(), h->rp.get(), h->ci.get(), PrimalEdge{h->primal.get(), h->ci.get()},
+             loc0.get());
+    }
     h->Afv.reset(A, static_cast<size_t>(nc) * nc);
     build_coarse_operator(h, h->fv_ptr, h->fv_order, nullptr, nc, h->Afv);
     // the FV operator is not symmetric: LU with partial pivoting; its three
@@ -286,7 +350,8 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   HIPX(hipStreamSynchronize(h->stream));
 
   // ---- FV stage ----
-  DBuf<double> r(A, n), rc(A, nc), x(A, nc), t(A, nc), t2(A, nc), p1(A, n), p2(A, n), xs(A, n);
+  DBuf<double> r(A, n), rc(A, nc), x(A, nc), t(A, nc), t2(A, nc), p1(A, n), p2(A, n), xs(A, n),
+      rs(A, 2 * static_cast<size_t>(n));
   LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(), p, q,
          r.get());
   LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
@@ -296,9 +361,16 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
     else coarse_apply(h, h->Afv_lu, nc, in, out, h->gpart);   // holds the inverse
   };
   fv_solve(rc, x);
-  for (int it = 0; it < 2; ++it) {  // iterative refinement of the coarse solve
-    coarse_apply(h, h->Afv, nc, x, t, h->gpart);
-    LAUNCH(h, "flux_sub", k_sub, blocks_for(nc, kT), kT, 0, nc, rc.get(), t.get(), t.get());
+  // iterative refinement against the fine-scale defect R^FV (q - A p'), with
+  // p' = p + P x: it removes the coarse solve's error and the rounding of the
+  // dense FV operator itself, which bounds the blocks' conservation
+  for (int it = 0; it < kFvRefine; ++it) {
+    LAUNCH(h, "flux_prolong", k_prolong_add, g, kT, 0, n, h->p_rp.get(), h->p_ci.get(),
+           h->p_val.get(), x.get(), p, p1.get());
+    LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(),
+           p1.get(), q, r.get());
+    LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
+           h->fv_order.get(), r.get(), t.get());
     fv_solve(t, t2);
     LAUNCH(h, "flux_add", k_add_to, blocks_for(nc, kT), kT, 0, nc, t2.get(), x.get());
   }
@@ -326,7 +398,7 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   LAUNCH(h, "flux_neumann", k_neumann, nc, kT, lds_need * sizeof(double), h->fv_ptr.get(),
          h->fv_order.get(), h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(),
          h->vertex.get(), band.get(), singular.get(), d_off.get(), scratch.get(),
-         static_cast<int>(lds_need), q, p1.get(), xs.get(), p2.get(), err.get());
+         static_cast<int>(lds_need), q, p1.get(), xs.get(), rs.get(), p2.get(), err.get());
 
   // ---- fluxes and balance ----
   DBuf<double> bpart(A, g), spart(A, g), mx(A, 2);

@@ -1,0 +1,129 @@
+// Block-local helpers shared by the basis blocks and the primal blocks of the
+// flux reconstruction: a workgroup-wide bitonic sort and the breadth-first
+// local ordering that narrows the band of irregular blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fams {
+namespace {
+
+__device__ inline void block_bitonic_sort(int* a, int cnt) {
+  int m = 1;
+  while (m < cnt) m <<= 1;
+  for (int t = cnt + threadIdx.x; t < m; t += blockDim.x) a[t] = INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        int u = t ^ j;
+        if (u > t) {
+          bool up = (t & k) == 0;
+          int x = a[t], y = a[u];
+          if ((x > y) == up) {
+            a[t] = y;
+            a[u] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Local order of a block: breadth-first levels from a pseudo-peripheral cell,
+// cells of one level by ascending natural position.  Irregular blocks (fracture
+// regions, merged Coupled-AMS blocks) get a bandwidth tens of times smaller
+// than in ascending-index order; structured dual blocks keep their natural
+// order, which is narrower for them.  The order used is the narrower one.
+// `edge(p, i, K)` tells whether CSR entry p of row i couples two cells of
+// block K (the block's own couplings).
+constexpr int kOrderMax = 6144;
+template <class Edge>
+__global__ void __launch_bounds__(256)
+k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edge edge,
+              int* local_idx) {
+  __shared__ int lvl[kOrderMax];
+  __shared__ int key[8192];
+  __shared__ int s_changed, s_bnat, s_bbfs, s_start;
+  int K = blockIdx.x;
+  int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
+  if (n <= 2 || n > kOrderMax) return;
+  if (threadIdx.x == 0) {
+    s_bnat = 0;
+    s_bbfs = 0;
+  }
+  __syncthreads();
+  int bnat = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (edge(p, i, K)) bnat = max(bnat, abs(local_idx[ci[p]] - l));
+  }
+  atomicMax(&s_bnat, bnat);
+  // Two breadth-first passes: the second starts from the lowest cell of the
+  // first pass's last level (a pseudo-peripheral cell), which narrows the
+  // levels of elongated blocks.
+  int start = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int l = threadIdx.x; l < n; l += blockDim.x) lvl[l] = l == start ? 0 : -1;
+    __syncthreads();
+    int last = 0;
+    for (int d = 0; d < n; ++d) {
+      if (threadIdx.x == 0) s_changed = 0;
+      __syncthreads();
+      for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        if (lvl[l] != d) continue;
+        int i = cells[beg + l];
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+          if (!edge(p, i, K)) continue;
+          int lj = local_idx[ci[p]];
+          if (lvl[lj] < 0) {
+            lvl[lj] = d + 1;
+            s_changed = 1;
+          }
+        }
+      }
+      __syncthreads();
+      const int changed = s_changed;
+      __syncthreads();  // every thread has read the flag before it is reset
+      if (!changed) {
+        last = d;
+        break;
+      }
+    }
+    if (pass == 0) {
+      if (threadIdx.x == 0) s_start = n;
+      __syncthreads();
+      for (int l = threadIdx.x; l < n; l += blockDim.x)
+        if (lvl[l] == last) atomicMin(&s_start, l);
+      __syncthreads();
+      start = s_start;
+      __syncthreads();
+    }
+  }
+  for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = (lvl[l] << 13) | l;
+  __syncthreads();
+  block_bitonic_sort(key, n);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) lvl[key[t] & 8191] = t;  // lvl := position
+  __syncthreads();
+  int bb = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (edge(p, i, K)) bb = max(bb, abs(lvl[local_idx[ci[p]]] - lvl[l]));
+  }
+  atomicMax(&s_bbfs, bb);
+  __syncthreads();
+  if (s_bbfs >= s_bnat) return;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = cells[beg + l];
+  __syncthreads();
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    cells[beg + lvl[l]] = key[l];
+    local_idx[key[l]] = lvl[l];
+  }
+}
+
+
+}  // namespace
+}  // namespace fams

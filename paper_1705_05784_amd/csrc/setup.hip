@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "band.hpp"
+#include "order.hpp"
 #include "internal.hpp"
 
 namespace fams {
@@ -220,119 +221,11 @@ __global__ void k_local_idx(int m, const int* key_sorted, const int* cells, cons
   if (t < m) local_idx[cells[t]] = t - comp_ptr[key_sorted[t]];
 }
 
-// ---- block-wide helpers (256 threads) ---------------------------------------
-__device__ void block_bitonic_sort(int* a, int cnt) {
-  int m = 1;
-  while (m < cnt) m <<= 1;
-  for (int t = cnt + threadIdx.x; t < m; t += blockDim.x) a[t] = INT_MAX;
-  __syncthreads();
-  for (int k = 2; k <= m; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < m; t += blockDim.x) {
-        int u = t ^ j;
-        if (u > t) {
-          bool up = (t & k) == 0;
-          int x = a[t], y = a[u];
-          if ((x > y) == up) {
-            a[t] = y;
-            a[u] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Local order of a block: breadth-first levels from a pseudo-peripheral cell,
-// cells of one level by ascending natural position.  Irregular blocks (fracture
-// regions, merged Coupled-AMS blocks) get a bandwidth tens of times smaller
-// than in ascending-index order; structured dual blocks keep their natural
-// order, which is narrower for them.  The order used is the narrower one.
-constexpr int kOrderMax = 6144;
-__global__ void __launch_bounds__(kThreads)
-k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, const int8_t* ecls,
-              int* local_idx) {
-  __shared__ int lvl[kOrderMax];
-  __shared__ int key[8192];
-  __shared__ int s_changed, s_bnat, s_bbfs, s_start;
-  int K = blockIdx.x;
-  int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
-  if (n <= 2 || n > kOrderMax) return;
-  if (threadIdx.x == 0) {
-    s_bnat = 0;
-    s_bbfs = 0;
-  }
-  __syncthreads();
-  int bnat = 0;
-  for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    int i = cells[beg + l];
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-      if (ecls[p] == C_KEPT) bnat = max(bnat, abs(local_idx[ci[p]] - l));
-  }
-  atomicMax(&s_bnat, bnat);
-  // Two breadth-first passes: the second starts from the lowest cell of the
-  // first pass's last level (a pseudo-peripheral cell), which narrows the
-  // levels of elongated blocks.
-  int start = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int l = threadIdx.x; l < n; l += blockDim.x) lvl[l] = l == start ? 0 : -1;
-    __syncthreads();
-    int last = 0;
-    for (int d = 0; d < n; ++d) {
-      if (threadIdx.x == 0) s_changed = 0;
-      __syncthreads();
-      for (int l = threadIdx.x; l < n; l += blockDim.x) {
-        if (lvl[l] != d) continue;
-        int i = cells[beg + l];
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-          if (ecls[p] != C_KEPT) continue;
-          int lj = local_idx[ci[p]];
-          if (lvl[lj] < 0) {
-            lvl[lj] = d + 1;
-            s_changed = 1;
-          }
-        }
-      }
-      __syncthreads();
-      const int changed = s_changed;
-      __syncthreads();  // every thread has read the flag before it is reset
-      if (!changed) {
-        last = d;
-        break;
-      }
-    }
-    if (pass == 0) {
-      if (threadIdx.x == 0) s_start = n;
-      __syncthreads();
-      for (int l = threadIdx.x; l < n; l += blockDim.x)
-        if (lvl[l] == last) atomicMin(&s_start, l);
-      __syncthreads();
-      start = s_start;
-      __syncthreads();
-    }
-  }
-  for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = (lvl[l] << 13) | l;
-  __syncthreads();
-  block_bitonic_sort(key, n);
-  for (int t = threadIdx.x; t < n; t += blockDim.x) lvl[key[t] & 8191] = t;  // lvl := position
-  __syncthreads();
-  int bb = 0;
-  for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    int i = cells[beg + l];
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-      if (ecls[p] == C_KEPT) bb = max(bb, abs(lvl[local_idx[ci[p]]] - lvl[l]));
-  }
-  atomicMax(&s_bbfs, bb);
-  __syncthreads();
-  if (s_bbfs >= s_bnat) return;
-  for (int l = threadIdx.x; l < n; l += blockDim.x) key[l] = cells[beg + l];
-  __syncthreads();
-  for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    cells[beg + lvl[l]] = key[l];
-    local_idx[key[l]] = lvl[l];
-  }
-}
+// kept couplings of a basis block
+struct KeptEdge {
+  const int8_t* ecls;
+  __device__ bool operator()(int p, int, int) const { return ecls[p] == C_KEPT; }
+};
 
 __device__ __forceinline__ int bsearch_i32(const int* a, int n, int key) {
   int lo = 0, hi = n;
@@ -929,8 +822,8 @@ void build_prolongation(Handle* h, const int8_t* wb) {
            cells.get(), comp_ptr.get(), local_idx.get());
   }
   if (ncomp)
-    LAUNCH(h, "local_order", k_local_order, ncomp, kThreads, 0, comp_ptr.get(), cells.get(),
-           h->rp.get(), h->ci.get(), ecls.get(), local_idx.get());
+    LAUNCH(h, "local_order", k_local_order<KeptEdge>, ncomp, kThreads, 0, comp_ptr.get(),
+           cells.get(), h->rp.get(), h->ci.get(), KeptEdge{ecls.get()}, local_idx.get());
   std::vector<int> h_cks(ncomp), h_comp_ptr(ncomp + 1, 0);
   if (ncomp) {
     HIPX(hipMemcpyAsync(h_cks.data(), cks.get(), ncomp * sizeof(int), hipMemcpyDeviceToHost,

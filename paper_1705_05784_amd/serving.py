@@ -358,3 +358,42 @@ def summarize(results, cells=None) -> dict:
         ci = sum(cells[r.rid] * sum(r.iterations) for r in ok)
         out["cell_iterations_per_s"] = ci / span
     return out
+
+
+def _main(argv=None):
+    """Run a seeded request stream and print one JSON line of serving figures."""
+    import argparse
+    import json
+    import sys
+
+    from . import fams
+    from workloads.serving import make_stream
+
+    ap = argparse.ArgumentParser(description="F-AMS serving run (continuous batching)")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--pool", type=int, default=8, help="distinct systems in the stream")
+    ap.add_argument("--side", type=int, nargs=2, default=(32, 128))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--fp64", action="store_true", help="plain FP64 form instead of mixed")
+    a = ap.parse_args(argv)
+    prec = fams.FP64 if a.fp64 else fams.MIXED
+    reqs = prepare(make_stream(a.requests, a.rate, pool=a.pool, seed=a.seed, side=tuple(a.side)))
+    cells = {r.rid: r.system.n for r in reqs}
+    print(f"[serving] {len(reqs)} requests ready", file=sys.stderr, flush=True)
+    with ProcessRunner(a.slots, prec, alpha=1e-2, rtol=1e-6) as run:
+        srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec))
+        res = srv.run(reqs, realtime=True)
+    out = summarize(res, cells)
+    out.update(slots=a.slots, rate=a.rate, precision="fp64" if a.fp64 else "mixed",
+               peak_inflight=srv.peak_inflight, peak_reserved_gb=srv.peak_reserved / 2**30,
+               mean_setup_ms=float(np.mean([r.setup_ms for r in res if r.status >= 0])),
+               mean_iterations=float(np.mean([np.mean(r.iterations) for r in res if r.iterations])),
+               cells_range=[min(cells.values()), max(cells.values())])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(_main())
