@@ -34,7 +34,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 constexpr int kPanel = 16;   // columns per panel of the blocked factorisation
-constexpr int kPanelRowsPerThread = 2;  // panel rows b + kPanel <= 2 * 256 threads
+constexpr int kPanelRowsPerThread = 2;  // panels of up to 2 * 256 rows held in registers
 constexpr int kSubRows = 8;  // rows per block of the substitution
 
 __host__ __device__ inline int64_t band_panel_elems(int b) {  // P and Q of a panel
@@ -53,7 +53,6 @@ __host__ __device__ inline int band_mode(int n, int b, int64_t lds) {
   const int64_t sub = band_subst_elems(b);
   if (static_cast<int64_t>(n) * (b + 1) + sub <= lds) return 0;
   const int64_t pan = band_panel_elems(b);
-  if (b + kPanel > kPanelRowsPerThread * 256) return -1;  // panel rows held in registers
   if (band_ring_elems(b) + pan <= lds) return 1;
   if (pan <= lds && sub <= lds) return 2;
   return -1;
@@ -135,6 +134,25 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
       }
       lds_barrier();
     }
+    if (np > kPanelRowsPerThread * static_cast<int>(blockDim.x)) {
+      // wider panels: eliminate in LDS (the rows do not fit the registers)
+      for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
+        const int ii = e / kPanel, c = e % kPanel, t = ii - c;
+        P[ii * PS + c] = (c < nb && t >= 0 && t <= b) ? rowp(k + ii)[b - t] : TC(0);
+      }
+      lds_barrier();
+      for (int c = 0; c < nb; ++c) {
+        const TC d = P[c * PS + c];
+        if (!(d > TC(0))) bad = true;
+        const TC rd = TC(1) / d;
+        for (int ii = c + 1 + threadIdx.x; ii < np; ii += blockDim.x) {
+          const TC l = P[ii * PS + c] * rd;
+          const int cend = min(nb, ii + 1);
+          for (int c2 = c + 1; c2 < cend; ++c2) P[ii * PS + c2] -= l * P[c2 * PS + c];
+        }
+        lds_barrier();
+      }
+    } else {
     // eliminate the panel's columns with its rows in registers (thread t
     // owns rows t and t + blockDim.x); at step c the owners of rows c..nb-1
     // publish their column-c entries (double-buffered, one barrier a step)
@@ -179,6 +197,7 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
       }
     }
     lds_barrier();
+    }
     // D and unit-lower L of the panel's columns; Q for the trailing update
     for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
       const int ii = e / kPanel, c = e % kPanel, t = ii - c;

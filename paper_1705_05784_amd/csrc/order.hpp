@@ -125,5 +125,93 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edg
 }
 
 
+// Blocks above kOrderMax cells (fracture regions that percolate through plate
+// intersections): the same two-pass breadth-first order with its levels in
+// global scratch, one workgroup for the block.  Writes keys[l] = (level << 16)
+// | l and vals[l] = the cell, for a stable radix sort on the host side, and
+// the natural-order bandwidth to info[0].  Blocks of at most 32768 cells.
+template <class Edge>
+__global__ void __launch_bounds__(256)
+k_bfs_levels(int K, int beg, int n, const int* cells, const int* rp, const int* ci, Edge edge,
+             const int* local_idx, int* lvl, int* keys, int* vals, int* info) {
+  __shared__ int s_changed, s_start, s_bnat;
+  if (threadIdx.x == 0) s_bnat = 0;
+  __syncthreads();
+  int bnat = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (edge(p, i, K)) bnat = max(bnat, abs(local_idx[ci[p]] - l));
+  }
+  atomicMax(&s_bnat, bnat);
+  int start = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int l = threadIdx.x; l < n; l += blockDim.x) lvl[l] = l == start ? 0 : -1;
+    __syncthreads();
+    int last = 0;
+    for (int d = 0; d < n; ++d) {
+      if (threadIdx.x == 0) s_changed = 0;
+      __syncthreads();
+      for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        if (lvl[l] != d) continue;
+        const int i = cells[beg + l];
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+          if (!edge(p, i, K)) continue;
+          const int lj = local_idx[ci[p]];
+          if (lvl[lj] < 0) {
+            lvl[lj] = d + 1;
+            s_changed = 1;
+          }
+        }
+      }
+      __syncthreads();
+      const int changed = s_changed;
+      __syncthreads();
+      if (!changed) {
+        last = d;
+        break;
+      }
+    }
+    if (pass == 0) {
+      if (threadIdx.x == 0) s_start = n;
+      __syncthreads();
+      for (int l = threadIdx.x; l < n; l += blockDim.x)
+        if (lvl[l] == last) atomicMin(&s_start, l);
+      __syncthreads();
+      start = s_start;
+      __syncthreads();
+    }
+  }
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    keys[l] = (max(lvl[l], 0) << 16) | l;   // unreached cells (none in a component) first
+    vals[l] = cells[beg + l];
+  }
+  if (threadIdx.x == 0) info[0] = s_bnat;
+}
+
+// apply the sorted order if it is narrower than the natural one
+template <class Edge>
+__global__ void __launch_bounds__(256)
+k_apply_order(int K, int beg, int n, int* cells, const int* rp, const int* ci, Edge edge,
+              int* local_idx, const int* keys_s, const int* vals_s, int* pos, const int* info) {
+  __shared__ int s_bb;
+  if (threadIdx.x == 0) s_bb = 0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) pos[keys_s[t] & 0xFFFF] = t;
+  __syncthreads();
+  int bb = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const int i = cells[beg + l];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (edge(p, i, K)) bb = max(bb, abs(pos[local_idx[ci[p]]] - pos[l]));
+  }
+  atomicMax(&s_bb, bb);
+  __syncthreads();
+  if (s_bb >= info[0]) return;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    cells[beg + t] = vals_s[t];
+    local_idx[vals_s[t]] = t;
+  }
+}
+
 }  // namespace
 }  // namespace fams

@@ -832,6 +832,29 @@ void build_prolongation(Handle* h, const int8_t* wb) {
                         hipMemcpyDeviceToHost, h->stream));
   }
   HIPX(hipStreamSynchronize(h->stream));
+  {  // blocks too large for the LDS ordering (kOrderMax < n <= 32768)
+    int big = 0;
+    for (int K = 0; K < ncomp; ++K) {
+      const int nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
+      if (nk > kOrderMax && nk <= 32768) big = std::max(big, nk);
+    }
+    if (big) {
+      DBuf<int> lvl(A, big), keys(A, big), vals(A, big), keys_s(A, big), vals_s(A, big),
+          info(A, 1);
+      for (int K = 0; K < ncomp; ++K) {
+        const int nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
+        if (nk <= kOrderMax || nk > 32768) continue;
+        LAUNCH(h, "local_order", k_bfs_levels<KeptEdge>, 1, kThreads, 0, K, h_comp_ptr[K], nk,
+               cells.get(), h->rp.get(), h->ci.get(), KeptEdge{ecls.get()}, local_idx.get(),
+               lvl.get(), keys.get(), vals.get(), info.get());
+        sort_pairs_i32(h, keys, keys_s, vals, vals_s, nk, 31);
+        LAUNCH(h, "local_order", k_apply_order<KeptEdge>, 1, kThreads, 0, K, h_comp_ptr[K], nk,
+               cells.get(), h->rp.get(), h->ci.get(), KeptEdge{ecls.get()}, local_idx.get(),
+               keys_s.get(), vals_s.get(), lvl.get(), info.get());
+      }
+      HIPX(hipStreamSynchronize(h->stream));
+    }
+  }
   // level ranges (key = 7 - rank)
   std::vector<std::pair<int, int>> levels;
   for (int k = 0; k < ncomp;) {

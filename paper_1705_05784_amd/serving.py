@@ -386,6 +386,12 @@ def _main(argv=None):
         srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec))
         res = srv.run(reqs, realtime=True)
     out = summarize(res, cells)
+    errs = {}
+    for r in res:
+        if r.status < 0:
+            key = r.error.split(":")[0] + ": " + r.error.split(":")[-1].strip()[:120]
+            errs.setdefault(key, []).append((r.rid, cells[r.rid]))
+    out["errors"] = {k: v for k, v in errs.items()}
     out.update(slots=a.slots, rate=a.rate, precision="fp64" if a.fp64 else "mixed",
                peak_inflight=srv.peak_inflight, peak_reserved_gb=srv.peak_reserved / 2**30,
                mean_setup_ms=float(np.mean([r.setup_ms for r in res if r.status >= 0])),

@@ -1,7 +1,7 @@
 """Precision form across fracture/matrix contrasts (the 2M-cell workload's
 shapes at reduced size): mixed FP32/FP64 and plain FP64, iterated to 1e-10,
 both against a sparse direct solve of the same system, and the per-cell mass
-balance of the reconstructed flux.  Iterations stop at 1e-10 or after 3000."""
+balance of the reconstructed flux.  Iterations stop at 1e-10 or after 1500."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -25,7 +25,7 @@ def test_contrast_sweep(contrast):
         S = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=fams.COUPLED,
                         precision=prec, alpha=1e-2)
         q = torch.from_numpy(s.q)
-        p, info = S.solve(q, rtol=1e-10, max_iter=3000)
+        p, info = S.solve(q, rtol=1e-10, max_iter=1500)
         _, _, imb = S.reconstruct_flux(q, p)
         err = np.linalg.norm(p.cpu().numpy() - p_ref) / np.linalg.norm(p_ref)
         out[prec] = (info[0], err, imb)
