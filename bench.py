@@ -245,9 +245,10 @@ def main():
         # a profiled replica of the timed mixed steps: HIP events around every
         # launch, recorded on the stream the kernel runs on
         _, r_prof = run_steps(fams.MIXED, args.steps, profile=True)
-        flops = 0.0
+        flops = {"local_solve": 0.0, "local_subst": 0.0}
         for r in r_prof:
-            flops += r["setup_info"]["local_flops"]
+            flops["local_solve"] += r["setup_info"]["local_flops"]
+            flops["local_subst"] += r["setup_info"]["local_subst_flops"]
             for name, (ms, cnt) in r["stats"].items():
                 a = kernels.setdefault(name, [0.0, 0])
                 a[0] += ms
@@ -265,13 +266,13 @@ def main():
                     "launches": cnt}
 
         dom = max(kernels, key=lambda k: kernels[k][0])
-        if dom == "local_solve":
+        if dom in flops:
             tot_ms, cnt = kernels[dom]
-            ach = flops / (tot_ms * 1e-3) / 1e12
+            ach = flops[dom] / (tot_ms * 1e-3) / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": ach,
                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(dom),
-                        "algorithmic_flops_per_launch": flops / cnt,
+                        "algorithmic_flops_per_launch": flops[dom] / cnt,
                         "avg_launch_us": tot_ms / cnt * 1e3, "launches": cnt}
         elif algorithmic_bytes(dom, sizes, 4) is not None:
             roofline = hbm_entry(dom)

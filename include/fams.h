@@ -144,8 +144,11 @@ typedef struct {
   int64_t ilu_levels_lower, ilu_levels_upper;
   double ms_setup;
   int64_t device_bytes;       /* device memory held by the handle */
-  double local_flops;         /* arithmetic of the banded local solves
-                                 (factorisation + substitution, all levels) */
+  double local_flops;         /* arithmetic of the banded local factorisations,
+                                 all levels (with the substitutions of blocks
+                                 too wide for the wavefront solver) */
+  double local_subst_flops;   /* arithmetic of the local substitutions done by
+                                 the wavefront solver, all levels */
 } fams_setup_info_t;
 
 /* ---- lifecycle -------------------------------------------------------- */

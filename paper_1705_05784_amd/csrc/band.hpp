@@ -14,7 +14,9 @@
 // Blocked steps, for the columns [k, k+nb): copy the panel (rows k..k+nb+b-1)
 // to LDS, eliminate its nb columns there, write D and L back, then subtract
 // the panel's rank-nb product from the trailing triangle of b rows.
-// Substitution: see band_substitute.
+// Blocked modes also write the factor's columns contiguously (Lt, the lower
+// band column by column) for the forward substitution.
+// Substitution: band_solve_waves (band_substitute for bandwidths beyond it).
 // Functions return true if a pivot was not positive (matrix not SPD).
 #pragma once
 
@@ -105,7 +107,7 @@ __device__ void band_normalise(TC* B, int n, int b) {
 // Q [kPanel][kPanel + b] (Q[c][i] = P[i][c] / d_c) and, in mode 1, the ring
 // of b + kPanel band rows (row r in slot r mod (b + kPanel)).
 template <class TC, bool kRing>
-__device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
+__device__ bool band_factor_blocked(TC* G, TC* Lt, int n, int b, TC* lds) {
   const int w = b + 1;
   constexpr int PS = kPanel + 1;
   const int mrow = kPanel + b;
@@ -198,12 +200,14 @@ __device__ bool band_factor_blocked(TC* G, int n, int b, TC* lds) {
     }
     lds_barrier();
     }
-    // D and unit-lower L of the panel's columns; Q for the trailing update
+    // D and unit-lower L of the panel's columns (also column by column
+    // into Lt: Lt[j*(b+1) + t] = L(j+t, j)); Q for the trailing update
     for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
-      const int ii = e / kPanel, c = e % kPanel, t = ii - c;
+      const int c = e / np, ii = e % np, t = ii - c;
       const bool in = c < nb && t >= 0 && t <= b;
       const TC v = in ? (t == 0 ? P[c * PS + c] : P[ii * PS + c] / P[c * PS + c]) : TC(0);
       if (in) rowp(k + ii)[b - t] = v;
+      if (in && t > 0) Lt[static_cast<int64_t>(k + c) * w + t] = v;
       if (ii >= nb) Q[c * mrow + ii] = v;
     }
     lds_barrier();
@@ -333,29 +337,231 @@ __device__ void band_substitute(const TC* B, int n, int b, TX* X, int nck, TC* S
   __syncthreads();
 }
 
-// Factorise and solve.  mode: band_mode(); B: the band, in LDS for mode 0,
-// else in global memory; lds: LDS scratch of band_lds_elems(mode, n, b)
-// entries (for mode 0 the band itself is its first n*(b+1) entries).
-// `ticks` (optional): wall-clock stamps after factorisation, normalisation
-// and substitution.
-template <class TC, class TX>
-__device__ bool band_ldlt_solve(int mode, TC* B, int n, int b, TX* X, int nck, TC* lds,
-                                unsigned long long* ticks = nullptr) {
-  bool bad;
-  TC* S = lds;
-  if (mode == 0) {
-    bad = band_factor_inplace<TC>(B, n, b);
-    if (ticks && threadIdx.x == 0) ticks[0] = wall_clock64();
-    band_normalise<TC>(B, n, b);
-    S = lds + static_cast<int64_t>(n) * (b + 1);
+// ---- substitution by wavefronts --------------------------------------------
+// One wavefront solves a group of NC columns of X with A = L D L^T, right-
+// looking: lane l holds, in acc[.][s], the partial result of row
+// 64 (c + s) + l (c the current chunk of 64 rows, s < M), so the window of M
+// chunks covers every row one step can reach when 64 (M - 1) >= b.  Step k
+// broadcasts the finished entry k (a readlane from chunk slot 0) and subtracts
+// its multiple from the rows of the window it couples to; when a chunk is
+// done its rows are stored and the window moves by one chunk.  Forward
+// (z = L^-1 x) reads column k of L, backward (x = D^-1 z - L^T x) row k; the
+// next 8 steps' entries are loaded while the current 8 are applied.  No
+// barriers: columns are independent and B is read-only here.
+//   column k of L: Fw[k*(b+1) + t*fstride + fbase], t = 1..b (row k + t)
+//   row k of L:    Bw[k*(b+1) + b - t], t = 1..b (column k - t); D_k at t = 0
+template <class TC>
+__device__ __forceinline__ TC wave_bcast(TC v, int src) {
+  if constexpr (sizeof(TC) == 4) {
+    return __builtin_bit_cast(TC, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
   } else {
-    bad = mode == 1 ? band_factor_blocked<TC, true>(B, n, b, lds) : band_factor_blocked<TC, false>(B, n, b, lds);
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), src));
+    const unsigned hi = static_cast<unsigned>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), src));
+    return __builtin_bit_cast(TC, (static_cast<unsigned long long>(hi) << 32) | lo);
+  }
+}
+
+template <class TC, class TX, class TO, int M, int NC, int J>
+__device__ __forceinline__ void band_wave_columns(const TC* Bw, const TC* Fw, int fstride,
+                                                  int fbase, int n, int b, TX* X, int nck,
+                                                  int col, TO* Y) {
+  static_assert(64 % J == 0 && (64 / J) % 2 == 0, "J steps per prefetch group");
+  constexpr int GPC = 64 / J;  // prefetch groups per chunk
+  const int lane = threadIdx.x & 63;
+  const int w = b + 1;
+  const int nch = (n + 63) >> 6;
+  const int ng = nch * GPC;  // even
+  TC acc[NC][M];
+  TC bufA[J][M], bufB[J][M];
+  auto xload = [&](int r, int j) -> TC {
+    return (r >= 0 && r < n) ? static_cast<TC>(X[static_cast<int64_t>(r) * nck + col + j]) : TC(0);
+  };
+  auto step = [&](const TC (&buf)[J][M], int g, bool down) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int kk = down ? 63 - ((g % GPC) * J + j) : (g % GPC) * J + j;
+      TC z[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) z[q] = wave_bcast(acc[q][0], kk);
+#pragma unroll
+      for (int s2 = 0; s2 < M; ++s2)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q][s2] -= buf[j][s2] * z[q];
+    }
+  };
+
+  // forward: chunk c = g / GPC, step k = J g + j, slot rows 64 (c + s) + lane
+  auto fload = [&](TC (&buf)[J][M], int g) {
+    const int c = g / GPC;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int k = g * J + j;
+#pragma unroll
+      for (int s2 = 0; s2 < M; ++s2) {
+        const int r = 64 * (c + s2) + lane, t = r - k;
+        const bool ok = t >= 1 && t <= b && r < n;
+        const int idx = ok ? k * w + t * fstride + fbase : 0;
+        const TC v = Fw[idx];
+        buf[j][s2] = ok ? v : TC(0);
+      }
+    }
+  };
+#pragma unroll
+  for (int s2 = 0; s2 < M; ++s2)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q][s2] = xload(64 * s2 + lane, q);
+  fload(bufA, 0);
+  for (int g = 0; g < ng; g += 2) {
+    fload(bufB, g + 1);
+    step(bufA, g, false);
+    fload(bufA, g + 2 < ng ? g + 2 : g);
+    step(bufB, g + 1, false);
+    if ((g + 1) % GPC == GPC - 1) {  // chunk (g+1)/GPC done
+      const int c = (g + 1) / GPC, r = 64 * c + lane;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (r < n) X[static_cast<int64_t>(r) * nck + col + q] = static_cast<TX>(acc[q][0]);
+#pragma unroll
+        for (int s2 = 0; s2 + 1 < M; ++s2) acc[q][s2] = acc[q][s2 + 1];
+        acc[q][M - 1] = xload(64 * (c + M) + lane, q);
+      }
+    }
+  }
+
+  // backward: chunk c = nch-1 - g/GPC, steps k = 64 c + 63 - (J (g%GPC) + j),
+  // slot rows 64 (c - s) + lane; rows enter scaled by 1/D; results go to Y
+  auto entry = [&](int r, int q) -> TC {
+    const TC d = (r >= 0 && r < n) ? Bw[r * w + b] : TC(1);
+    return xload(r, q) / d;
+  };
+  auto bload = [&](TC (&buf)[J][M], int g) {
+    const int c = nch - 1 - g / GPC;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int k = 64 * c + 63 - ((g % GPC) * J + j);
+#pragma unroll
+      for (int s2 = 0; s2 < M; ++s2) {
+        const int r = 64 * (c - s2) + lane, t = k - r;
+        const bool ok = t >= 1 && t <= b && r >= 0 && k < n;
+        const int idx = ok ? k * w + b - t : 0;
+        const TC v = Bw[idx];
+        buf[j][s2] = ok ? v : TC(0);
+      }
+    }
+  };
+#pragma unroll
+  for (int s2 = 0; s2 < M; ++s2)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q][s2] = entry(64 * (nch - 1 - s2) + lane, q);
+  bload(bufA, 0);
+  for (int g = 0; g < ng; g += 2) {
+    bload(bufB, g + 1);
+    step(bufA, g, true);
+    bload(bufA, g + 2 < ng ? g + 2 : g);
+    step(bufB, g + 1, true);
+    if ((g + 1) % GPC == GPC - 1) {
+      const int c = nch - 1 - (g + 1) / GPC, r = 64 * c + lane;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (r < n) Y[static_cast<int64_t>(r) * nck + col + q] = static_cast<TO>(acc[q][0]);
+#pragma unroll
+        for (int s2 = 0; s2 + 1 < M; ++s2) acc[q][s2] = acc[q][s2 + 1];
+        acc[q][M - 1] = entry(64 * (c - M) + lane, q);
+      }
+    }
+  }
+}
+
+// chunk slots for bandwidth b (64 (M - 1) >= b), 0 if beyond kWaveMaxBand
+constexpr int kWaveMaxBand = 512;
+__host__ __device__ inline int band_wave_slots(int b) {
+  const int m = (b + 63) / 64 + 1;
+  return b > kWaveMaxBand ? 0 : (m < 2 ? 2 : m);
+}
+// the instantiated slot counts: band_wave_slots rounded up to one of them
+__host__ __device__ inline int band_wave_class(int b) {
+  const int m = band_wave_slots(b);
+  return m == 0 ? 0 : m <= 7 ? m : 9;
+}
+
+// single columns round-robin over the workgroup's waves (in-kernel use)
+template <class TC, class TX, int M, int J>
+__device__ void band_waves_single(const TC* Bw, const TC* Fw, int fstride, int fbase, int n,
+                                  int b, TX* X, int nck) {
+  const int wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
+  for (int q = wave; q < nck; q += nwaves)
+    band_wave_columns<TC, TX, TX, M, 1, J>(Bw, Fw, fstride, fbase, n, b, X, nck, q, X);
+}
+
+// X <- A^{-1} X, one column per wavefront; false (nothing done) if b is
+// beyond kWaveMaxBand.  Ends with a workgroup barrier.
+template <class TC, class TX>
+__device__ bool band_solve_waves(const TC* Bw, const TC* Fw, int fstride, int fbase, int n,
+                                 int b, TX* X, int nck) {
+  constexpr int J = sizeof(TC) == 4 ? 8 : 4;
+  switch (band_wave_class(b)) {
+    case 2: band_waves_single<TC, TX, 2, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    case 3: band_waves_single<TC, TX, 3, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    case 4: band_waves_single<TC, TX, 4, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    case 5: band_waves_single<TC, TX, 5, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    case 6: band_waves_single<TC, TX, 6, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    case 7: band_waves_single<TC, TX, 7, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    case 9: band_waves_single<TC, TX, 9, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
+    default: return false;
+  }
+  __syncthreads();
+  return true;
+}
+
+// copy a factored band from LDS (mode 0) to global memory: the band as is
+// into G and its columns into Lt (Lt[k*(b+1) + t] = L(k+t, k))
+template <class TC>
+__device__ void band_export(const TC* lds, TC* G, TC* Lt, int n, int b) {
+  const int w = b + 1;
+  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * w; e += blockDim.x) {
+    G[e] = lds[e];
+    const int k = static_cast<int>(e / w), t = static_cast<int>(e % w);
+    Lt[e] = (t >= 1 && k + t < n) ? lds[static_cast<int64_t>(k + t) * w + b - t] : TC(0);
+  }
+}
+
+// Factorise.  mode: band_mode(); mode 0: the band is the first n*(b+1)
+// entries of lds; modes 1/2: the band is G (global memory) and Lt (n*(b+1)
+// entries of global memory) receives L column by column; lds: LDS scratch of
+// band_lds_elems(mode, n, b) entries.  `ticks` (optional): wall-clock stamps
+// after factorisation and normalisation.
+template <class TC>
+__device__ bool band_factor(int mode, TC* G, TC* Lt, int n, int b, TC* lds,
+                            unsigned long long* ticks = nullptr) {
+  bool bad;
+  if (mode == 0) {
+    bad = band_factor_inplace<TC>(lds, n, b);
+    if (ticks && threadIdx.x == 0) ticks[0] = wall_clock64();
+    band_normalise<TC>(lds, n, b);
+  } else {
+    bad = mode == 1 ? band_factor_blocked<TC, true>(G, Lt, n, b, lds)
+                    : band_factor_blocked<TC, false>(G, Lt, n, b, lds);
     if (ticks && threadIdx.x == 0) ticks[0] = wall_clock64();
   }
   if (ticks && threadIdx.x == 0) ticks[1] = wall_clock64();
-  band_substitute<TC, TX>(B, n, b, X, nck, S);
-  if (ticks && threadIdx.x == 0) ticks[2] = wall_clock64();
   return bad;
+}
+
+// X <- A^{-1} X with the factor of band_factor (same mode, G, Lt, lds).
+// Ends with a workgroup barrier.
+template <class TC, class TX>
+__device__ void band_solve(int mode, const TC* G, const TC* Lt, int n, int b, TX* X, int nck,
+                           TC* lds) {
+  if (mode == 0) {
+    if (!band_solve_waves<TC, TX>(lds, lds, b, b, n, b, X, nck))
+      band_substitute<TC, TX>(lds, n, b, X, nck, lds + static_cast<int64_t>(n) * (b + 1));
+  } else {
+    if (!band_solve_waves<TC, TX>(G, Lt, 1, 0, n, b, X, nck))
+      band_substitute<TC, TX>(G, n, b, X, nck, lds);
+  }
 }
 
 }  // namespace fams

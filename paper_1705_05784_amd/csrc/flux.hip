@@ -16,6 +16,7 @@
 //     E_i = s_i p''_i - q_i in the diagonal slot; sum_j F_ij + E_i = 0.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "band.hpp"
@@ -170,18 +171,68 @@ struct PrimalEdge {
 // high permeability contrast are many orders larger), then one step of
 // iterative refinement with the resident factors.  A block without a
 // Dirichlet cell is pinned at its coarse node (d = 0 there).
+//
+// k_neumann assembles and factors block K (xs: the right-hand side, rs
+// second half: a copy of it); the solves, the residual of the first solve
+// and the correction p'' = p' + d follow in k_neumann_solve, one wavefront a
+// block.  Blocks beyond the wavefront solver's bandwidth are finished in
+// k_neumann itself.
+
+// R <- Rq - A_KK X (the modified block matrix; the pinned row is the identity)
+__device__ void neumann_residual(int K, int beg, int n, int lv, const int* cells, const int* rp,
+                                 const int* ci, const double* av, const int* primal,
+                                 const int* local, const double* X, const double* Rq, double* R,
+                                 int t0, int dt) {
+  for (int l = t0; l < n; l += dt) {
+    const int i = cells[beg + l];
+    double r = Rq[l];
+    if (l == lv) {
+      r -= X[l];
+    } else {
+      double dg = 0.0;
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        const double a = av[p];
+        if (j == i) {
+          dg += a;
+        } else if (primal[j] == K) {
+          const int lj = local[j];
+          if (lj != lv) r -= a * X[lj];
+        } else {
+          dg += a;
+        }
+      }
+      r -= dg * X[l];
+    }
+    R[l] = r;
+  }
+}
+
+__device__ void neumann_update(int beg, int n, const int* cells, const double* p1,
+                               const double* X, const double* R, double* p2, int t0, int dt) {
+  for (int l = t0; l < n; l += dt) {
+    const int i = cells[beg + l];
+    p2[i] = p1[i] + (X[l] + R[l]);
+  }
+}
+
 __global__ void __launch_bounds__(kT)
 k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const double* av,
           const int* primal, const int* local, const int* vertex, const int* band,
           const int* singular, const int64_t* band_off, double* band_glob, int lds_elems,
-          const double* q, const double* p1, double* xs, double* rs, double* p2, int* err) {
+          const double* q, const double* p1, double* xs, double* rs, double* p2, int* err,
+          unsigned long long* timing) {
   extern __shared__ double lds[];
   int K = blockIdx.x;
+  unsigned long long* tk = timing ? timing + 8 * static_cast<int64_t>(K) : nullptr;
+  if (tk && threadIdx.x == 0) tk[0] = wall_clock64();
   int beg = ptr[K], n = ptr[K + 1] - beg;
   int b = band[K], w = b + 1;
   const int64_t bsz = static_cast<int64_t>(n) * w;
   const int mode = band_mode(n, b, lds_elems);
-  double* B = mode == 0 ? lds : band_glob + band_off[K];
+  double* G = band_glob + band_off[K];  // band, then its columns
+  double* Lt = G + bsz;
+  double* B = mode == 0 ? lds : G;
   double* X = xs + beg;
   double* R = rs + beg;                    // residual / correction
   double* Rq = rs + ptr[gridDim.x] + beg;  // the right-hand side, kept
@@ -219,38 +270,50 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
     Rq[l] = rhs;
   }
   __syncthreads();
-  bool bad = band_ldlt_solve<double, double>(mode, B, n, b, X, 1, lds);
-  for (int l = threadIdx.x; l < n; l += blockDim.x) {  // residual of the correction
-    const int i = cells[beg + l];
-    double r = Rq[l];
-    if (l == lv) {
-      r -= X[l];
-    } else {
-      double dg = 0.0;
-      for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        const int j = ci[p];
-        const double a = av[p];
-        if (j == i) {
-          dg += a;
-        } else if (primal[j] == K) {
-          const int lj = local[j];
-          if (lj != lv) r -= a * X[lj];
-        } else {
-          dg += a;
-        }
-      }
-      r -= dg * X[l];
-    }
-    R[l] = r;
+  if (tk && threadIdx.x == 0) {
+    tk[1] = wall_clock64();
+    tk[5] = (static_cast<unsigned long long>(n) << 32) | static_cast<unsigned>(b);
+    tk[6] = (1ull << 32) | static_cast<unsigned>(mode);
   }
-  __syncthreads();
-  band_substitute<double, double>(B, n, b, R, 1,
-                                  mode == 0 ? lds + static_cast<int64_t>(n) * w : lds);
-  for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    const int i = cells[beg + l];
-    p2[i] = p1[i] + (X[l] + R[l]);
+  bool bad = band_factor<double>(mode, G, Lt, n, b, lds, tk ? tk + 2 : nullptr);
+  if (band_wave_class(b) != 0) {
+    if (mode == 0) band_export<double>(lds, G, Lt, n, b);
+  } else {
+    band_substitute<double, double>(B, n, b, X, 1, mode == 0 ? lds + bsz : lds);
+    neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x,
+                     blockDim.x);
+    __syncthreads();
+    band_substitute<double, double>(B, n, b, R, 1, mode == 0 ? lds + bsz : lds);
+    neumann_update(beg, n, cells, p1, X, R, p2, threadIdx.x, blockDim.x);
   }
   if (bad && threadIdx.x == 0) atomicOr(err, 1);
+  if (tk && threadIdx.x == 0) tk[4] = wall_clock64();
+}
+
+// solves of the Neumann problems of the blocks list[.] (chunk-slot class M)
+// with the factors k_neumann left in global memory, one wavefront a block
+template <int M>
+__global__ void __launch_bounds__(64)
+k_neumann_solve(const int* list, int nc, const int* ptr, const int* cells, const int* rp,
+                const int* ci, const double* av, const int* primal, const int* local,
+                const int* vertex, const int* band, const int* singular,
+                const int64_t* band_off, const double* band_glob, const double* p1, double* xs,
+                double* rs, double* p2) {
+  const int K = list[blockIdx.x];
+  const int beg = ptr[K], n = ptr[K + 1] - beg, b = band[K];
+  const double* G = band_glob + band_off[K];
+  const double* Lt = G + static_cast<int64_t>(n) * (b + 1);
+  double* X = xs + beg;
+  double* R = rs + beg;
+  const double* Rq = rs + ptr[nc] + beg;
+  const int lv = singular[K] != 0 ? local[vertex[K]] : -1;
+  band_wave_columns<double, double, double, M, 1, 4>(G, Lt, 1, 0, n, b, X, 1, 0, X);
+  __syncthreads();
+  neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x, 64);
+  __syncthreads();
+  band_wave_columns<double, double, double, M, 1, 4>(G, Lt, 1, 0, n, b, R, 1, 0, R);
+  __syncthreads();
+  neumann_update(beg, n, cells, p1, X, R, p2, threadIdx.x, 64);
 }
 
 __global__ void k_flux(int n, const int* rp, const int* ci, const double* av, const int* primal,
@@ -386,7 +449,8 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
     const int mode = band_mode(nk, hb[K], lds_cap);
     FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "primal block bandwidth too large for LDS");
     off[K] = total;
-    if (mode != 0) total += static_cast<int64_t>(nk) * (hb[K] + 1);
+    if (mode != 0 || band_wave_class(hb[K]) != 0)
+      total += 2 * static_cast<int64_t>(nk) * (hb[K] + 1);  // factor band and Lt
     lds_need = std::max(lds_need, band_lds_elems(mode, nk, hb[K]));
   }
   DBuf<int64_t> d_off(A, nc);
@@ -395,10 +459,53 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   DBuf<int> err(A, 1);
   HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
   allow_lds(reinterpret_cast<const void*>(&k_neumann), lds_need * sizeof(double));
+  static const bool timing_on = std::getenv("FAMS_BLOCK_TIMING") != nullptr;
+  DBuf<unsigned long long> timing;
+  if (timing_on) timing.reset(A, 8 * static_cast<size_t>(nc));
   LAUNCH(h, "flux_neumann", k_neumann, nc, kT, lds_need * sizeof(double), h->fv_ptr.get(),
          h->fv_order.get(), h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(),
          h->vertex.get(), band.get(), singular.get(), d_off.get(), scratch.get(),
-         static_cast<int>(lds_need), q, p1.get(), xs.get(), rs.get(), p2.get(), err.get());
+         static_cast<int>(lds_need), q, p1.get(), xs.get(), rs.get(), p2.get(), err.get(),
+         timing.get());
+  if (timing_on) {
+    HIPX(hipStreamSynchronize(h->stream));
+    print_block_timing(timing.get(), nc, 0);
+  }
+  {  // the solves, by chunk-slot class
+    std::vector<int> list;
+    std::vector<std::pair<int, int>> cls;
+    for (int m : {2, 3, 4, 5, 6, 7, 9}) {
+      const size_t l0 = list.size();
+      for (int K = 0; K < nc; ++K)
+        if (band_wave_class(hb[K]) == m) list.push_back(K);
+      if (list.size() > l0) cls.emplace_back(m, static_cast<int>(list.size() - l0));
+    }
+    DBuf<int> d_list(A, std::max<size_t>(list.size(), 1));
+    if (!list.empty())
+      HIPX(hipMemcpyAsync(d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
+    int l0 = 0;
+    for (auto [m, cnt] : cls) {
+#define FAMS_NSOLVE(M)                                                                        \
+  LAUNCH(h, "flux_neumann_solve", k_neumann_solve<M>, cnt, 64, 0,                             \
+         static_cast<const int*>(d_list.get() + l0), nc, h->fv_ptr.get(), h->fv_order.get(),   \
+         h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(), h->vertex.get(), \
+         band.get(), singular.get(), d_off.get(), static_cast<const double*>(scratch.get()),    \
+         p1.get(), xs.get(), rs.get(), p2.get())
+      switch (m) {
+        case 2: FAMS_NSOLVE(2); break;
+        case 3: FAMS_NSOLVE(3); break;
+        case 4: FAMS_NSOLVE(4); break;
+        case 5: FAMS_NSOLVE(5); break;
+        case 6: FAMS_NSOLVE(6); break;
+        case 7: FAMS_NSOLVE(7); break;
+        default: FAMS_NSOLVE(9); break;
+      }
+#undef FAMS_NSOLVE
+      l0 += cnt;
+    }
+    HIPX(hipStreamSynchronize(h->stream));  // d_list is freed on return
+  }
 
   // ---- fluxes and balance ----
   DBuf<double> bpart(A, g), spart(A, g), mx(A, 2);

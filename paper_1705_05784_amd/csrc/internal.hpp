@@ -228,6 +228,8 @@ struct Handle {
 int64_t lds_budget(Handle* h);
 int64_t lds_hw_budget(Handle* h);
 void allow_lds(const void* kernel, size_t bytes);
+// per-block phase ticks of one launch (8 entries a block) to stderr
+void print_block_timing(const unsigned long long* dev, int nb, int first);
 
 // ---- launchers implemented in the .hip files --------------------------------
 // prims.hip (rocPRIM)

@@ -393,7 +393,9 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
   const int64_t bsz = static_cast<int64_t>(n) * w;
   const int mode = band_mode(n, b, lds_elems);
   TC* lds = reinterpret_cast<TC*>(lds_d);
-  TC* B = mode == 0 ? lds : band_glob + work_off[2 * slot];
+  TC* G = band_glob + work_off[2 * slot];  // modes 1/2: band, then its columns
+  TC* Lt = G + bsz;
+  TC* B = mode == 0 ? lds : G;
 
   for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = TC(0);
   __syncthreads();
@@ -449,16 +451,46 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
     tk[6] = (static_cast<unsigned long long>(nck) << 32) |
             static_cast<unsigned>(mode);
   }
-  bool bad = band_ldlt_solve<TC, TC>(mode, B, n, b, X, nck, lds, tk ? tk + 2 : nullptr);
-  if (!std::is_same<TS, TC>::value || xwork) {
-    TS* out = pvals + pval_off[K];
-    for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x)
-      out[t] = static_cast<TS>(X[t]);
+  bool bad = band_factor<TC>(mode, G, Lt, n, b, lds, tk ? tk + 2 : nullptr);
+  if (band_wave_class(b) != 0) {  // the substitution follows in k_local_subst
+    if (mode == 0) band_export<TC>(lds, G, Lt, n, b);
+  } else {
+    band_substitute<TC, TC>(B, n, b, X, nck, mode == 0 ? lds + bsz : lds);
+    if (!std::is_same<TS, TC>::value || xwork) {
+      TS* out = pvals + pval_off[K];
+      for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x)
+        out[t] = static_cast<TS>(X[t]);
+    }
   }
+  if (tk && threadIdx.x == 0) tk[4] = wall_clock64();
   if (bad && threadIdx.x == 0) {
     atomicOr(err, E_PIVOT);
     if (bad_block) bad_block[K] = 1;
   }
+}
+
+// Substitution of one rank level's local solves with the factors (band and
+// Lt) that k_local_solve left in global memory: one wavefront per group of
+// columns of one block, for the blocks of chunk-slot class M.
+// groups[3 g ..] = (slot, first column, columns: 1 or 4).
+template <class TS, class TC, int M>
+__global__ void __launch_bounds__(64)
+k_local_subst(const int* groups, const int* list, int c0, const int* comp_ptr, const int* ncols,
+              const int* band, const int64_t* pval_off, TS* pvals, const int64_t* work_off,
+              const TC* band_glob, TC* xwork) {
+  const int* gq = groups + 3 * static_cast<int64_t>(blockIdx.x);
+  const int slot = gq[0], col = gq[1], nc = gq[2];
+  const int K = list ? list[slot] : c0 + slot;
+  const int n = comp_ptr[K + 1] - comp_ptr[K], b = band[K], nck = ncols[K];
+  const TC* G = band_glob + work_off[2 * slot];
+  const TC* Lt = G + static_cast<int64_t>(n) * (b + 1);
+  TS* out = pvals + pval_off[K];
+  TC* X;
+  if constexpr (std::is_same<TS, TC>::value) X = xwork ? xwork + work_off[2 * slot + 1] : out;
+  else X = xwork + work_off[2 * slot + 1];
+  constexpr int J = sizeof(TC) == 4 ? 8 : 4;
+  if (nc == 4) band_wave_columns<TC, TC, TS, M, 4, J>(G, Lt, 1, 0, n, b, X, nck, col, out);
+  else band_wave_columns<TC, TC, TS, M, 1, J>(G, Lt, 1, 0, n, b, X, nck, col, out);
 }
 
 // ---- P in CSR (with the optional truncation of Sec. 4.3) -------------------
@@ -661,31 +693,6 @@ void coupled_groups(Handle* h, const int8_t* wb, const int* base, int* group) {
   HIPX(hipStreamSynchronize(h->stream));
 }
 
-// FAMS_BLOCK_TIMING=1: per-block phase durations of one launch to stderr
-// (wall-clock ticks of the device's constant-rate counter).
-void print_block_timing(const unsigned long long* dev, int nb, int first) {
-  std::vector<unsigned long long> t(8 * static_cast<size_t>(nb));
-  HIPX(hipMemcpy(t.data(), dev, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-  double sum[4] = {0, 0, 0, 0};
-  std::vector<std::pair<double, int>> tot;
-  for (int k = 0; k < nb; ++k) {
-    const unsigned long long* r = &t[8 * static_cast<size_t>(k)];
-    double ph[4] = {double(r[1] - r[0]), double(r[2] - r[1]), double(r[3] - r[2]),
-                    double(r[4] - r[3])};
-    for (int q = 0; q < 4; ++q) sum[q] += ph[q];
-    tot.emplace_back(double(r[4] - r[0]), k);
-  }
-  std::sort(tot.begin(), tot.end(), [](auto& a, auto& b) { return a.first > b.first; });
-  std::fprintf(stderr, "[blocks from %d] %d blocks; sum ticks assemble %.3g factor %.3g normalise %.3g substitute %.3g\n",
-               first, nb, sum[0], sum[1], sum[2], sum[3]);
-  for (int q = 0; q < std::min(nb, 6); ++q) {
-    const unsigned long long* r = &t[8 * static_cast<size_t>(tot[q].second)];
-    std::fprintf(stderr, "   n %llu b %llu nck %llu mode %llu : assemble %llu factor %llu normalise %llu substitute %llu\n",
-                 r[5] >> 32, r[5] & 0xffffffffull, r[6] >> 32, r[6] & 0xffffffffull, r[1] - r[0],
-                 r[2] - r[1], r[3] - r[2], r[4] - r[3]);
-  }
-}
-
 // Launch the local solves of blocks `blocks` (all of one rank level).
 template <class TS, class TC>
 void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, const int* comp_ptr,
@@ -706,7 +713,8 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
     const int mode = band_mode(static_cast<int>(nk), h_band[K], lds_cap);
     FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "local block bandwidth too large for LDS");
     off[2 * k] = band_total;
-    if (mode != 0) band_total += nk * (h_band[K] + 1);  // band in global memory
+    if (mode != 0 || band_wave_class(h_band[K]) != 0)
+      band_total += 2 * nk * (h_band[K] + 1);  // factor band and Lt in global memory
     lds_need = std::max(lds_need, band_lds_elems(mode, static_cast<int>(nk), h_band[K]));
     off[2 * k + 1] = x_total;
     if (separate_x) x_total += nk * h_ncols[K];
@@ -715,7 +723,10 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
       const double b = h_band[K], nn = static_cast<double>(nk), t = std::min(b, nn);
       const double fac = std::max(0.0, nn - b) * b * (b + 1.0) + (t - 1.0) * t * (t + 1.0) / 3.0;
       const double S = nn >= b ? nn * b - b * (b + 1.0) / 2.0 : nn * (nn - 1.0) / 2.0;
-      h->info.local_flops += fac + (4.0 * S + nn) * h_ncols[K];
+      const double sub = (4.0 * S + nn) * h_ncols[K];
+      h->info.local_flops += fac;
+      if (band_wave_class(h_band[K]) != 0) h->info.local_subst_flops += sub;
+      else h->info.local_flops += sub;
     }
   }
   DBuf<int64_t> d_off(&h->alloc, 2 * nb);
@@ -740,11 +751,90 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
          h->ci.get(), h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols,
          ncols, band, pval_off, pvals, d_off.get(), scratch.get(), xw.get(), lds_elems, err,
          bad_block, timing.get());
+  if (timing_on) {
+    HIPX(hipStreamSynchronize(h->stream));
+    print_block_timing(timing.get(), nb, blocks[0]);
+  }
+  // substitutions: groups of 4 columns, then single columns, per slot class
+  std::vector<int> groups;
+  std::vector<std::pair<int, int>> cls;  // (class, groups in it)
+  for (int m : {2, 3, 4, 5, 6, 7, 9}) {
+    const size_t g0 = groups.size();
+    for (int k = 0; k < nb; ++k) {
+      const int K = blocks[k];
+      if (band_wave_class(h_band[K]) != m) continue;
+      const int nck = h_ncols[K];
+      for (int c = 0; c + 4 <= nck; c += 4) groups.insert(groups.end(), {k, c, 4});
+      for (int c = nck - nck % 4; c < nck; ++c) groups.insert(groups.end(), {k, c, 1});
+    }
+    const int ng = static_cast<int>((groups.size() - g0) / 3);
+    if (ng) cls.emplace_back(m, ng);
+  }
+  DBuf<int> d_groups(&h->alloc, std::max<size_t>(groups.size(), 1));
+  if (!groups.empty())
+    HIPX(hipMemcpyAsync(d_groups, groups.data(), groups.size() * sizeof(int),
+                        hipMemcpyHostToDevice, h->stream));
+  int64_t gofs = 0;
+  for (auto [m, ng] : cls) {
+#define FAMS_SUBST(M)                                                                         \
+  LAUNCH(h, "local_subst", (k_local_subst<TS, TC, M>), ng, 64, 0,                             \
+         static_cast<const int*>(d_groups.get() + 3 * gofs), static_cast<const int*>(d_list.get()), \
+         blocks[0], comp_ptr, ncols, band, pval_off, pvals, static_cast<const int64_t*>(d_off.get()), \
+         static_cast<const TC*>(scratch.get()), xw.get())
+    switch (m) {
+      case 2: FAMS_SUBST(2); break;
+      case 3: FAMS_SUBST(3); break;
+      case 4: FAMS_SUBST(4); break;
+      case 5: FAMS_SUBST(5); break;
+      case 6: FAMS_SUBST(6); break;
+      case 7: FAMS_SUBST(7); break;
+      default: FAMS_SUBST(9); break;
+    }
+#undef FAMS_SUBST
+    gofs += ng;
+  }
   HIPX(hipStreamSynchronize(h->stream));  // scratch is freed on return
-  if (timing_on) print_block_timing(timing.get(), nb, blocks[0]);
 }
 
 }  // namespace
+
+// FAMS_BLOCK_TIMING=1: per-block phase durations of one launch to stderr
+// (wall-clock ticks of the device's constant-rate counter): the launch's
+// span, the summed phases per storage mode and the slowest blocks.
+void print_block_timing(const unsigned long long* dev, int nb, int first) {
+  std::vector<unsigned long long> t(8 * static_cast<size_t>(nb));
+  HIPX(hipMemcpy(t.data(), dev, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  double sum[3][5] = {};
+  int cnt[3] = {0, 0, 0};
+  unsigned long long t_first = ~0ull, t_last = 0;
+  std::vector<std::pair<double, int>> tot;
+  for (int k = 0; k < nb; ++k) {
+    const unsigned long long* r = &t[8 * static_cast<size_t>(k)];
+    const int mode = static_cast<int>(r[6] & 3);
+    double ph[4] = {double(r[1] - r[0]), double(r[2] - r[1]), double(r[3] - r[2]),
+                    double(r[4] - r[3])};
+    for (int q = 0; q < 4; ++q) sum[mode][q] += ph[q];
+    sum[mode][4] = std::max(sum[mode][4], double(r[4] - r[0]));
+    ++cnt[mode];
+    t_first = std::min(t_first, r[0]);
+    t_last = std::max(t_last, r[4]);
+    tot.emplace_back(double(r[4] - r[0]), k);
+  }
+  std::sort(tot.begin(), tot.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  std::fprintf(stderr, "[blocks from %d] %d blocks, span %llu ticks\n", first, nb,
+               t_last - t_first);
+  for (int m = 0; m < 3; ++m)
+    if (cnt[m])
+      std::fprintf(stderr, "   mode %d: %d blocks; sum assemble %.3g factor %.3g normalise %.3g "
+                   "substitute %.3g; slowest %.3g\n", m, cnt[m], sum[m][0], sum[m][1], sum[m][2],
+                   sum[m][3], sum[m][4]);
+  for (int q = 0; q < std::min(nb, 6); ++q) {
+    const unsigned long long* r = &t[8 * static_cast<size_t>(tot[q].second)];
+    std::fprintf(stderr, "   n %llu b %llu nck %llu mode %llu : assemble %llu factor %llu normalise %llu substitute %llu\n",
+                 r[5] >> 32, r[5] & 0xffffffffull, r[6] >> 32, r[6] & 0xffffffffull, r[1] - r[0],
+                 r[2] - r[1], r[3] - r[2], r[4] - r[3]);
+  }
+}
 
 void build_prolongation(Handle* h, const int8_t* wb) {
   const int n = h->n, nm = h->nm, nc = h->nc;

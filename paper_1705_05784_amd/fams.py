@@ -61,7 +61,7 @@ class SetupInfo(C.Structure):
                 ("max_block", C.c_int64), ("fp32_fallback_blocks", C.c_int64),
                 ("ilu_levels_lower", C.c_int64), ("ilu_levels_upper", C.c_int64),
                 ("ms_setup", C.c_double), ("device_bytes", C.c_int64),
-                ("local_flops", C.c_double)]
+                ("local_flops", C.c_double), ("local_subst_flops", C.c_double)]
 
 
 EXPORTS = {
