@@ -1,22 +1,26 @@
-// Banded LDL^T factorisation and solve by one workgroup.
+// Banded LDL^T factorisation and solve.
 //
 // Storage: the lower band of a symmetric matrix of n rows and bandwidth b,
 // row l, column l-t (0 <= t <= b) at B[l*(b+1) + b - t].  X holds nck
 // right-hand sides, row-major [n][nck].  After factorisation the diagonal
-// holds D and the entries below it the unit-lower L.
+// holds D and the entries below it the unit-lower L; Lt holds L column by
+// column (Lt[j*(b+1) + t] = L(j+t, j), t >= 1) for the forward substitution.
 //
-// Three storage modes (band_mode):
-//   0  the whole band in LDS: unblocked right-looking elimination in place;
-//   1  band in global memory, blocked by kPanel columns, with a ring of
-//      b + kPanel band rows in LDS -- each row is read once when a panel first
-//      reaches it and written once when it is final;
-//   2  band in global memory, blocked, trailing updates in global memory.
-// Blocked steps, for the columns [k, k+nb): copy the panel (rows k..k+nb+b-1)
-// to LDS, eliminate its nb columns there, write D and L back, then subtract
-// the panel's rank-nb product from the trailing triangle of b rows.
-// Blocked modes also write the factor's columns contiguously (Lt, the lower
-// band column by column) for the forward substitution.
-// Substitution: band_solve_waves (band_substitute for bandwidths beyond it).
+// The factorisation (one workgroup) is blocked by kPanel columns.  The band
+// lives in one of three places (band_mode):
+//   0  LDS, after the panel scratch;
+//   1  global memory, with a ring of b + kPanel band rows in LDS -- each row
+//      is read once when a panel first reaches it and written once when final;
+//   2  global memory, updated in place.
+// Panel [k, k+nb): wavefront 0 factors the nb x nb diagonal block in
+// registers (readlane broadcasts, no barriers); after one barrier each
+// thread eliminates the panel columns of its own rows below the block
+// against it and writes D, L, Lt and the trailing-update operands P
+// (unscaled columns) and Q (scaled, transposed); the trailing update then
+// subtracts the panel's rank-nb product from the triangle of the next b
+// rows, lanes over columns (their nb entries of Q held in registers) and
+// wavefronts over batches of rows, each batch's loads issued one batch ahead.
+// Substitution: band_wave_columns (band_substitute for bandwidths beyond it).
 // Functions return true if a pivot was not positive (matrix not SPD).
 #pragma once
 
@@ -35,215 +39,231 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int kPanel = 16;   // columns per panel of the blocked factorisation
-constexpr int kPanelRowsPerThread = 2;  // panels of up to 2 * 256 rows held in registers
-constexpr int kSubRows = 8;  // rows per block of the substitution
+// value of lane `src` (uniform) in every lane
+template <class TC>
+__device__ __forceinline__ TC wave_bcast(TC v, int src) {
+  if constexpr (sizeof(TC) == 4) {
+    return __builtin_bit_cast(TC, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), src));
+    const unsigned hi = static_cast<unsigned>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), src));
+    return __builtin_bit_cast(TC, (static_cast<unsigned long long>(hi) << 32) | lo);
+  }
+}
 
-__host__ __device__ inline int64_t band_panel_elems(int b) {  // P and Q of a panel
-  return static_cast<int64_t>(kPanel + b) * (kPanel + 1) + static_cast<int64_t>(kPanel) * (kPanel + b);
+constexpr int kPanel = 16;     // columns per panel of the blocked factorisation
+constexpr int kSubRows = 8;    // rows per block of band_substitute
+constexpr int kTrailRows = 8;  // rows per wavefront batch of the trailing update
+
+// panel scratch: P, Q and the factored diagonal block (entries and 1/D)
+__host__ __device__ inline int64_t band_panel_elems(int b) {
+  return static_cast<int64_t>(kPanel + b) * (kPanel + 1) + static_cast<int64_t>(kPanel) * (kPanel + b) +
+         kPanel * kPanel + kPanel;
 }
 __host__ __device__ inline int64_t band_ring_elems(int b) {
   return static_cast<int64_t>(kPanel + b) * (b + 1);
 }
-__host__ __device__ inline int64_t band_subst_elems(int b) {
+__host__ __device__ inline int64_t band_subst_elems(int b) {  // <= band_panel_elems(b)
   return static_cast<int64_t>(b + kSubRows) * kSubRows + kSubRows;
 }
 
 // storage mode for a band of n rows and bandwidth b with `lds` elements of
 // LDS available; -1 if none fits
 __host__ __device__ inline int band_mode(int n, int b, int64_t lds) {
-  const int64_t sub = band_subst_elems(b);
-  if (static_cast<int64_t>(n) * (b + 1) + sub <= lds) return 0;
   const int64_t pan = band_panel_elems(b);
-  if (band_ring_elems(b) + pan <= lds) return 1;
-  if (pan <= lds && sub <= lds) return 2;
+  if (pan + static_cast<int64_t>(n) * (b + 1) <= lds) return 0;
+  if (pan + band_ring_elems(b) <= lds) return 1;
+  if (pan <= lds) return 2;
   return -1;
 }
-// LDS elements that mode `mode` uses
+// LDS elements that mode `mode` uses: the panel scratch, then (mode 0) the
+// band or (mode 1) the ring
 __host__ __device__ inline int64_t band_lds_elems(int mode, int n, int b) {
-  const int64_t sub = band_subst_elems(b);
-  if (mode == 0) return static_cast<int64_t>(n) * (b + 1) + sub;
   const int64_t pan = band_panel_elems(b);
-  if (mode == 1) return band_ring_elems(b) + pan;
-  return pan > sub ? pan : sub;
+  if (mode == 0) return pan + static_cast<int64_t>(n) * (b + 1);
+  if (mode == 1) return pan + band_ring_elems(b);
+  return pan;
 }
 
-// right-looking factorisation of B in place (B in LDS or global memory).
-// Wavefronts take the rows k+t of the update, lanes the columns k+s (s <= t).
-template <class TC>
-__device__ bool band_factor_inplace(TC* B, int n, int b) {
-  const int w = b + 1;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
-  bool bad = false;
-  for (int k = 0; k < n; ++k) {
-    const TC piv = B[static_cast<int64_t>(k) * w + b];
-    if (!(piv > TC(0))) bad = true;
-    const TC rpiv = TC(1) / piv;
-    const int m = min(b, n - 1 - k);
-    for (int t = 1 + wave; t <= m; t += nwaves) {
-      TC* row = B + static_cast<int64_t>(k + t) * w;
-      const TC lt = row[b - t] * rpiv;
-      for (int s = 1 + lane; s <= t; s += 64)
-        row[b - (t - s)] -= lt * B[static_cast<int64_t>(k + s) * w + b - s];
+// Blocked factorisation (see the top of this file).  kMode: band_mode();
+// G: the band in global memory (modes 1, 2); lds: band_lds_elems() entries,
+// the band itself at lds + band_panel_elems(b) in mode 0.  LDS layout: the
+// panel P [(kPanel + b) rows][kPanel + 1] (unscaled columns), Q [kPanel]
+// [kPanel + b] (Q[c][i] = L(k+i, k+c)), the diagonal block, then the band
+// or the ring (row r in slot r mod (b + kPanel)).
+// ph (optional): summed wall-clock ticks of the phases (ring load, panel,
+// -, trailing update, ring store), by thread 0.
+template <class TC, int kMode>
+__device__ __forceinline__ bool band_factor_blocked(TC* G, TC* Lt, int n, int b, TC* lds,
+                                    unsigned long long* ph = nullptr) {
+  unsigned long long tph = (ph && threadIdx.x == 0) ? wall_clock64() : 0;
+  auto mark = [&](int q) {
+    if (ph && threadIdx.x == 0) {
+      const unsigned long long t2 = wall_clock64();
+      ph[q] += t2 - tph;
+      tph = t2;
     }
-    lds_barrier();
-  }
-  return bad;
-}
-
-// turn the unscaled columns into unit-lower L: B(r, r-t) /= d_{r-t}
-template <class TC>
-__device__ void band_normalise(TC* B, int n, int b) {
-  const int w = b + 1;
-  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * w; e += blockDim.x) {
-    const int r = static_cast<int>(e / w), t = b - static_cast<int>(e % w);
-    if (t > 0 && r - t >= 0) B[e] /= B[static_cast<int64_t>(r - t) * w + b];
-  }
-  lds_barrier();
-}
-
-// Blocked factorisation of the band G in global memory (mode 1 / 2 above).
-// LDS: the panel P [(kPanel + b) rows][kPanel + 1], its scaled transpose
-// Q [kPanel][kPanel + b] (Q[c][i] = P[i][c] / d_c) and, in mode 1, the ring
-// of b + kPanel band rows (row r in slot r mod (b + kPanel)).
-template <class TC, bool kRing>
-__device__ bool band_factor_blocked(TC* G, TC* Lt, int n, int b, TC* lds) {
+  };
   const int w = b + 1;
   constexpr int PS = kPanel + 1;
   const int mrow = kPanel + b;
   TC* P = lds;
   TC* Q = P + static_cast<int64_t>(mrow) * PS;
-  TC* ring = Q + static_cast<int64_t>(kPanel) * mrow;
-  __shared__ TC colbuf[2 * kPanel];
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
-  auto rowp = [&](int r) -> TC* {
-    if constexpr (kRing) return ring + static_cast<int64_t>(r % mrow) * w;
+  TC* dgu = Q + static_cast<int64_t>(kPanel) * mrow;  // diagonal block: u(i, c) at [i * kPanel + c], c < i
+  TC* dgr = dgu + kPanel * kPanel;                     // 1 / d_c
+  TC* band = dgr + kPanel;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, nwaves = blockDim.x / 64;
+  auto rowp = [&](int r) -> TC* {  // band row r
+    if constexpr (kMode == 0) return band + static_cast<int64_t>(r) * w;
+    else if constexpr (kMode == 1) return band + static_cast<int64_t>(r % mrow) * w;
     else return G + static_cast<int64_t>(r) * w;
   };
   bool bad = false;
-  if constexpr (kRing) {  // rows 0..b-1 enter before the first panel
-    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(min(n, b)) * w; e += blockDim.x)
-      ring[e] = G[e];
+  if constexpr (kMode == 1) {  // rows 0..b-1 enter before the first panel
+    for (int64_t e = tid; e < static_cast<int64_t>(min(n, b)) * w; e += blockDim.x)
+      band[e] = G[e];
   }
   for (int k = 0; k < n; k += kPanel) {
     const int nb = min(kPanel, n - k);
     const int np = min(n - k, nb + b);  // panel rows k .. k+np-1
-    if constexpr (kRing) {  // rows k+b .. k+np-1 are new
+    const int s0 = kMode == 1 ? k % mrow : 0;
+    auto prow = [&](int ii) -> TC* {  // band row k + ii, 0 <= ii < np
+      if constexpr (kMode == 1) {
+        int sl = s0 + ii;
+        sl -= sl >= mrow ? mrow : 0;
+        return band + static_cast<int64_t>(sl) * w;
+      } else {
+        return rowp(k + ii);
+      }
+    };
+    if constexpr (kMode == 1) {  // rows k+b .. k+np-1 are new
       const int r0 = k + b, r1 = k + np;
-      for (int64_t e = threadIdx.x; e < static_cast<int64_t>(max(0, r1 - r0)) * w; e += blockDim.x) {
+      for (int64_t e = tid; e < static_cast<int64_t>(max(0, r1 - r0)) * w; e += blockDim.x) {
         const int r = r0 + static_cast<int>(e / w), c = static_cast<int>(e % w);
         rowp(r)[c] = G[static_cast<int64_t>(r) * w + c];
       }
       lds_barrier();
     }
-    if (np > kPanelRowsPerThread * static_cast<int>(blockDim.x)) {
-      // wider panels: eliminate in LDS (the rows do not fit the registers)
-      for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
-        const int ii = e / kPanel, c = e % kPanel, t = ii - c;
-        P[ii * PS + c] = (c < nb && t >= 0 && t <= b) ? rowp(k + ii)[b - t] : TC(0);
-      }
-      lds_barrier();
-      for (int c = 0; c < nb; ++c) {
-        const TC d = P[c * PS + c];
-        if (!(d > TC(0))) bad = true;
-        const TC rd = TC(1) / d;
-        for (int ii = c + 1 + threadIdx.x; ii < np; ii += blockDim.x) {
-          const TC l = P[ii * PS + c] * rd;
-          const int cend = min(nb, ii + 1);
-          for (int c2 = c + 1; c2 < cend; ++c2) P[ii * PS + c2] -= l * P[c2 * PS + c];
-        }
-        lds_barrier();
-      }
-    } else {
-    // eliminate the panel's columns with its rows in registers (thread t
-    // owns rows t and t + blockDim.x); at step c the owners of rows c..nb-1
-    // publish their column-c entries (double-buffered, one barrier a step)
-    TC pr[kPanelRowsPerThread][kPanel];
-#pragma clang loop unroll(full)
-    for (int h2 = 0; h2 < kPanelRowsPerThread; ++h2) {
-      const int ii = threadIdx.x + h2 * blockDim.x;
-#pragma clang loop unroll(full)
+    mark(0);
+    // diagonal block: lane i < nb of wavefront 0 holds row k+i, columns
+    // k..k+i; rows and columns nb..kPanel-1 are padded with the identity
+    // (which the steps keep exact) so that all kPanel steps run without
+    // branches; entries above the diagonal are scratch and never read
+    if (wave == 0) {
+      TC r[kPanel];
+      const bool own = lane < nb;
+      const TC* rw = prow(own ? lane : 0);
+#pragma unroll
       for (int c = 0; c < kPanel; ++c) {
-        const int t = ii - c;
-        pr[h2][c] = (ii < np && c < nb && t >= 0 && t <= b) ? rowp(k + ii)[b - t] : TC(0);
+        const int t = lane - c;
+        r[c] = (own && c < nb && t >= 0 && t <= b) ? rw[b - t] : (lane == c ? TC(1) : TC(0));
       }
-    }
-#pragma clang loop unroll(full)
-    for (int c = 0; c < kPanel; ++c) {
-      if (c < nb) {
-        TC* cb = colbuf + (c & 1) * kPanel;
-        if (static_cast<int>(threadIdx.x) >= c && static_cast<int>(threadIdx.x) < nb)
-          cb[threadIdx.x] = pr[0][c];
-        lds_barrier();
-        const TC d = cb[c];
-        if (!(d > TC(0))) bad = true;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        const TC d = wave_bcast(r[c], c);  // u(c, c) = d_c
+        if (c < nb && !(d > TC(0))) bad = true;
         const TC rd = TC(1) / d;
-#pragma clang loop unroll(full)
-        for (int h2 = 0; h2 < kPanelRowsPerThread; ++h2) {
-          const int ii = threadIdx.x + h2 * blockDim.x;
-          if (ii > c && ii < np) {
-            const TC l = pr[h2][c] * rd;
-#pragma clang loop unroll(full)
-            for (int c2 = c + 1; c2 < kPanel; ++c2)
-              if (c2 < nb && c2 <= ii) pr[h2][c2] -= l * cb[c2];
-          }
-        }
+        const TC l = r[c] * rd;
+        if (lane == c) dgr[c] = rd;
+#pragma unroll
+        for (int c2 = c + 1; c2 < kPanel; ++c2) r[c2] -= l * wave_bcast(r[c], c2);  // u(c2, c)
+        __builtin_amdgcn_sched_barrier(0);
       }
-    }
-#pragma clang loop unroll(full)
-    for (int h2 = 0; h2 < kPanelRowsPerThread; ++h2) {
-      const int ii = threadIdx.x + h2 * blockDim.x;
-      if (ii < np) {
-#pragma clang loop unroll(full)
-        for (int c = 0; c < kPanel; ++c) P[ii * PS + c] = pr[h2][c];
+      if (lane < kPanel) {
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) {
+          if (c < lane) dgu[lane * kPanel + c] = r[c];
+          if (own && c <= lane) P[lane * PS + c] = r[c];
+        }
       }
     }
     lds_barrier();
+    // rows below the diagonal block: eliminate the panel columns against it
+    // (unscaled results to P)
+    for (int ii = nb + tid; ii < np; ii += blockDim.x) {
+      const TC* rw = prow(ii);
+      TC x[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        const int t = ii - c;
+        x[c] = (c < nb && t <= b) ? rw[b - t] : TC(0);
+      }
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        const TC l = x[c] * dgr[c];
+#pragma unroll
+        for (int c2 = c + 1; c2 < kPanel; ++c2) x[c2] -= l * dgu[c2 * kPanel + c];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) P[ii * PS + c] = x[c];
     }
-    // D and unit-lower L of the panel's columns (also column by column
-    // into Lt: Lt[j*(b+1) + t] = L(j+t, j)); Q for the trailing update
-    for (int e = threadIdx.x; e < np * kPanel; e += blockDim.x) {
+    lds_barrier();
+    mark(1);
+    // D and unit-lower L of the panel's columns into the band and (column
+    // by column) Lt; Q for the trailing update
+    for (int e = tid; e < np * kPanel; e += blockDim.x) {
       const int c = e / np, ii = e % np, t = ii - c;
       const bool in = c < nb && t >= 0 && t <= b;
-      const TC v = in ? (t == 0 ? P[c * PS + c] : P[ii * PS + c] / P[c * PS + c]) : TC(0);
-      if (in) rowp(k + ii)[b - t] = v;
-      if (in && t > 0) Lt[static_cast<int64_t>(k + c) * w + t] = v;
+      const TC u = P[ii * PS + c];
+      const TC v = in ? (t == 0 ? u : u * dgr[c]) : TC(0);
+      if (in) {
+        prow(ii)[b - t] = v;
+        if (t > 0) Lt[static_cast<int64_t>(k + c) * w + t] = v;
+      }
       if (ii >= nb) Q[c * mrow + ii] = v;
     }
     lds_barrier();
+    mark(2);
     // trailing update: A(k+ii, k+jj) -= sum_c P[ii][c] Q[c][jj], nb <= jj <= ii < np
-    for (int ii = nb + wave; ii < np; ii += nwaves) {
-      const TC* p = P + ii * PS;        // the same LDS address in every lane
-      TC* row = rowp(k + ii) + b - ii;  // row[jj] = A(k+ii, k+jj)
-      for (int j0 = nb; j0 <= ii; j0 += 256) {
-        TC a[4];
+    for (int j0 = nb; j0 < np; j0 += 64) {
+      const int jj = j0 + lane;
+      TC qv[kPanel];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int jj = j0 + lane + 64 * q;
-          a[q] = jj <= ii ? row[jj] : TC(0);
+      for (int c = 0; c < kPanel; ++c) qv[c] = jj < np ? Q[c * mrow + jj] : TC(0);
+      TC a[kTrailRows], an[kTrailRows];
+      auto load = [&](TC (&dst)[kTrailRows], int i0) {
+#pragma unroll
+        for (int q = 0; q < kTrailRows; ++q) {
+          const int ii = min(i0 + q, np - 1), jc = min(jj, ii);  // clamped, in the band
+          dst[q] = prow(ii)[b - ii + jc];
         }
+      };
+      int i0 = j0 + wave * kTrailRows;
+      load(a, i0);
+      for (; i0 < np; i0 += nwaves * kTrailRows) {
+        load(an, i0 + nwaves * kTrailRows);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int jj = j0 + lane + 64 * q;
-          if (jj <= ii) {
+        for (int q = 0; q < kTrailRows; ++q) {
+          const int ii = i0 + q;
+          if (ii < np) {
+            const TC* p = P + ii * PS;
             TC acc = a[q];
 #pragma unroll
-            for (int c = 0; c < kPanel; ++c) acc -= p[c] * Q[c * mrow + jj];
-            row[jj] = acc;
+            for (int c = 0; c < kPanel; ++c) acc -= p[c] * qv[c];
+            if (jj <= ii) prow(ii)[b - ii + jj] = acc;
           }
+          __builtin_amdgcn_sched_barrier(0);  // one row's P entries live at a time
         }
+#pragma unroll
+        for (int q = 0; q < kTrailRows; ++q) a[q] = an[q];
       }
     }
-    if constexpr (kRing) lds_barrier(); else __syncthreads();  // global trailing rows
-    if constexpr (kRing) {  // rows k .. k+nb-1 are final
-      for (int64_t e = threadIdx.x; e < static_cast<int64_t>(nb) * w; e += blockDim.x) {
+    if constexpr (kMode == 2) __syncthreads(); else lds_barrier();
+    mark(3);
+    if constexpr (kMode == 1) {  // rows k .. k+nb-1 are final
+      for (int64_t e = tid; e < static_cast<int64_t>(nb) * w; e += blockDim.x) {
         const int r = k + static_cast<int>(e / w), c = static_cast<int>(e % w);
         G[static_cast<int64_t>(r) * w + c] = rowp(r)[c];
       }
       lds_barrier();
     }
+    mark(4);
   }
-  __syncthreads();  // the factor rows in G are read by other threads next
+  __syncthreads();  // the factor rows are read by other threads next
   return bad;
 }
 
@@ -350,20 +370,6 @@ __device__ void band_substitute(const TC* B, int n, int b, TX* X, int nck, TC* S
 // barriers: columns are independent and B is read-only here.
 //   column k of L: Fw[k*(b+1) + t*fstride + fbase], t = 1..b (row k + t)
 //   row k of L:    Bw[k*(b+1) + b - t], t = 1..b (column k - t); D_k at t = 0
-template <class TC>
-__device__ __forceinline__ TC wave_bcast(TC v, int src) {
-  if constexpr (sizeof(TC) == 4) {
-    return __builtin_bit_cast(TC, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
-  } else {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = static_cast<unsigned>(
-        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), src));
-    const unsigned hi = static_cast<unsigned>(
-        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), src));
-    return __builtin_bit_cast(TC, (static_cast<unsigned long long>(hi) << 32) | lo);
-  }
-}
-
 template <class TC, class TX, class TO, int M, int NC, int J>
 __device__ __forceinline__ void band_wave_columns(const TC* Bw, const TC* Fw, int fstride,
                                                   int fbase, int n, int b, TX* X, int nck,
@@ -487,81 +493,27 @@ __host__ __device__ inline int band_wave_class(int b) {
   return m == 0 ? 0 : m <= 7 ? m : 9;
 }
 
-// single columns round-robin over the workgroup's waves (in-kernel use)
-template <class TC, class TX, int M, int J>
-__device__ void band_waves_single(const TC* Bw, const TC* Fw, int fstride, int fbase, int n,
-                                  int b, TX* X, int nck) {
-  const int wave = threadIdx.x / 64, nwaves = blockDim.x / 64;
-  for (int q = wave; q < nck; q += nwaves)
-    band_wave_columns<TC, TX, TX, M, 1, J>(Bw, Fw, fstride, fbase, n, b, X, nck, q, X);
-}
-
-// X <- A^{-1} X, one column per wavefront; false (nothing done) if b is
-// beyond kWaveMaxBand.  Ends with a workgroup barrier.
-template <class TC, class TX>
-__device__ bool band_solve_waves(const TC* Bw, const TC* Fw, int fstride, int fbase, int n,
-                                 int b, TX* X, int nck) {
-  constexpr int J = sizeof(TC) == 4 ? 8 : 4;
-  switch (band_wave_class(b)) {
-    case 2: band_waves_single<TC, TX, 2, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    case 3: band_waves_single<TC, TX, 3, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    case 4: band_waves_single<TC, TX, 4, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    case 5: band_waves_single<TC, TX, 5, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    case 6: band_waves_single<TC, TX, 6, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    case 7: band_waves_single<TC, TX, 7, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    case 9: band_waves_single<TC, TX, 9, J>(Bw, Fw, fstride, fbase, n, b, X, nck); break;
-    default: return false;
-  }
-  __syncthreads();
-  return true;
-}
-
-// copy a factored band from LDS (mode 0) to global memory: the band as is
-// into G and its columns into Lt (Lt[k*(b+1) + t] = L(k+t, k))
+// copy a band factored in LDS (mode 0) to global memory
 template <class TC>
-__device__ void band_export(const TC* lds, TC* G, TC* Lt, int n, int b) {
-  const int w = b + 1;
-  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * w; e += blockDim.x) {
-    G[e] = lds[e];
-    const int k = static_cast<int>(e / w), t = static_cast<int>(e % w);
-    Lt[e] = (t >= 1 && k + t < n) ? lds[static_cast<int64_t>(k + t) * w + b - t] : TC(0);
-  }
+__device__ void band_export(const TC* band_lds, TC* G, int n, int b) {
+  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * (b + 1); e += blockDim.x)
+    G[e] = band_lds[e];
 }
 
-// Factorise.  mode: band_mode(); mode 0: the band is the first n*(b+1)
-// entries of lds; modes 1/2: the band is G (global memory) and Lt (n*(b+1)
-// entries of global memory) receives L column by column; lds: LDS scratch of
-// band_lds_elems(mode, n, b) entries.  `ticks` (optional): wall-clock stamps
-// after factorisation and normalisation.
+// Factorise: mode = band_mode(); G, Lt in global memory (G unused in mode
+// 0, whose band is at lds + band_panel_elems(b)); lds: band_lds_elems()
+// entries.  `ticks` (optional): ticks[0], ticks[1] = wall clock when done,
+// ticks[6..10] the phase sums of band_factor_blocked.
 template <class TC>
 __device__ bool band_factor(int mode, TC* G, TC* Lt, int n, int b, TC* lds,
                             unsigned long long* ticks = nullptr) {
+  unsigned long long* ph = ticks ? ticks + 6 : nullptr;
   bool bad;
-  if (mode == 0) {
-    bad = band_factor_inplace<TC>(lds, n, b);
-    if (ticks && threadIdx.x == 0) ticks[0] = wall_clock64();
-    band_normalise<TC>(lds, n, b);
-  } else {
-    bad = mode == 1 ? band_factor_blocked<TC, true>(G, Lt, n, b, lds)
-                    : band_factor_blocked<TC, false>(G, Lt, n, b, lds);
-    if (ticks && threadIdx.x == 0) ticks[0] = wall_clock64();
-  }
-  if (ticks && threadIdx.x == 0) ticks[1] = wall_clock64();
+  if (mode == 0) bad = band_factor_blocked<TC, 0>(G, Lt, n, b, lds, ph);
+  else if (mode == 1) bad = band_factor_blocked<TC, 1>(G, Lt, n, b, lds, ph);
+  else bad = band_factor_blocked<TC, 2>(G, Lt, n, b, lds, ph);
+  if (ticks && threadIdx.x == 0) ticks[0] = ticks[1] = wall_clock64();
   return bad;
-}
-
-// X <- A^{-1} X with the factor of band_factor (same mode, G, Lt, lds).
-// Ends with a workgroup barrier.
-template <class TC, class TX>
-__device__ void band_solve(int mode, const TC* G, const TC* Lt, int n, int b, TX* X, int nck,
-                           TC* lds) {
-  if (mode == 0) {
-    if (!band_solve_waves<TC, TX>(lds, lds, b, b, n, b, X, nck))
-      band_substitute<TC, TX>(lds, n, b, X, nck, lds + static_cast<int64_t>(n) * (b + 1));
-  } else {
-    if (!band_solve_waves<TC, TX>(G, Lt, 1, 0, n, b, X, nck))
-      band_substitute<TC, TX>(G, n, b, X, nck, lds);
-  }
 }
 
 }  // namespace fams

@@ -224,7 +224,7 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
           unsigned long long* timing) {
   extern __shared__ double lds[];
   int K = blockIdx.x;
-  unsigned long long* tk = timing ? timing + 8 * static_cast<int64_t>(K) : nullptr;
+  unsigned long long* tk = timing ? timing + kTickSlots * static_cast<int64_t>(K) : nullptr;
   if (tk && threadIdx.x == 0) tk[0] = wall_clock64();
   int beg = ptr[K], n = ptr[K + 1] - beg;
   int b = band[K], w = b + 1;
@@ -232,7 +232,7 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
   const int mode = band_mode(n, b, lds_elems);
   double* G = band_glob + band_off[K];  // band, then its columns
   double* Lt = G + bsz;
-  double* B = mode == 0 ? lds : G;
+  double* B = mode == 0 ? lds + band_panel_elems(b) : G;
   double* X = xs + beg;
   double* R = rs + beg;                    // residual / correction
   double* Rq = rs + ptr[gridDim.x] + beg;  // the right-hand side, kept
@@ -277,13 +277,13 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
   }
   bool bad = band_factor<double>(mode, G, Lt, n, b, lds, tk ? tk + 2 : nullptr);
   if (band_wave_class(b) != 0) {
-    if (mode == 0) band_export<double>(lds, G, Lt, n, b);
+    if (mode == 0) band_export<double>(lds + band_panel_elems(b), G, n, b);
   } else {
-    band_substitute<double, double>(B, n, b, X, 1, mode == 0 ? lds + bsz : lds);
+    band_substitute<double, double>(B, n, b, X, 1, lds);
     neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x,
                      blockDim.x);
     __syncthreads();
-    band_substitute<double, double>(B, n, b, R, 1, mode == 0 ? lds + bsz : lds);
+    band_substitute<double, double>(B, n, b, R, 1, lds);
     neumann_update(beg, n, cells, p1, X, R, p2, threadIdx.x, blockDim.x);
   }
   if (bad && threadIdx.x == 0) atomicOr(err, 1);
@@ -449,8 +449,7 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
     const int mode = band_mode(nk, hb[K], lds_cap);
     FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "primal block bandwidth too large for LDS");
     off[K] = total;
-    if (mode != 0 || band_wave_class(hb[K]) != 0)
-      total += 2 * static_cast<int64_t>(nk) * (hb[K] + 1);  // factor band and Lt
+    total += 2 * static_cast<int64_t>(nk) * (hb[K] + 1);  // factor band and Lt
     lds_need = std::max(lds_need, band_lds_elems(mode, nk, hb[K]));
   }
   DBuf<int64_t> d_off(A, nc);
@@ -461,7 +460,10 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   allow_lds(reinterpret_cast<const void*>(&k_neumann), lds_need * sizeof(double));
   static const bool timing_on = std::getenv("FAMS_BLOCK_TIMING") != nullptr;
   DBuf<unsigned long long> timing;
-  if (timing_on) timing.reset(A, 8 * static_cast<size_t>(nc));
+  if (timing_on) {
+    timing.reset(A, kTickSlots * static_cast<size_t>(nc));
+    HIPX(hipMemsetAsync(timing, 0, kTickSlots * nc * sizeof(unsigned long long), h->stream));
+  }
   LAUNCH(h, "flux_neumann", k_neumann, nc, kT, lds_need * sizeof(double), h->fv_ptr.get(),
          h->fv_order.get(), h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(),
          h->vertex.get(), band.get(), singular.get(), d_off.get(), scratch.get(),

@@ -228,7 +228,10 @@ struct Handle {
 int64_t lds_budget(Handle* h);
 int64_t lds_hw_budget(Handle* h);
 void allow_lds(const void* kernel, size_t bytes);
-// per-block phase ticks of one launch (8 entries a block) to stderr
+// per-block phase ticks of one launch (kTickSlots entries a block) to stderr:
+// [0] start, [1] assembled, [2] factored, [3] normalised, [4] end,
+// [5] n << 32 | b, [6] columns << 32 | mode, [8..12] blocked-factor phases
+constexpr int kTickSlots = 16;
 void print_block_timing(const unsigned long long* dev, int nb, int first);
 
 // ---- launchers implemented in the .hip files --------------------------------

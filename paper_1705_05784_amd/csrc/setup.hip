@@ -379,7 +379,7 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
               const int64_t* pval_off, TS* pvals, const int64_t* work_off, TC* band_glob,
               TC* xwork, int lds_elems, int* err, int* bad_block, unsigned long long* timing) {
   extern __shared__ double lds_d[];
-  unsigned long long* tk = timing ? timing + 8 * static_cast<int64_t>(blockIdx.x) : nullptr;
+  unsigned long long* tk = timing ? timing + kTickSlots * static_cast<int64_t>(blockIdx.x) : nullptr;
   if (tk && threadIdx.x == 0) tk[0] = wall_clock64();
   int slot = blockIdx.x;
   int K = list ? list[slot] : c0 + slot;
@@ -395,7 +395,7 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
   TC* lds = reinterpret_cast<TC*>(lds_d);
   TC* G = band_glob + work_off[2 * slot];  // modes 1/2: band, then its columns
   TC* Lt = G + bsz;
-  TC* B = mode == 0 ? lds : G;
+  TC* B = mode == 0 ? lds + band_panel_elems(b) : G;
 
   for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = TC(0);
   __syncthreads();
@@ -453,9 +453,9 @@ k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, co
   }
   bool bad = band_factor<TC>(mode, G, Lt, n, b, lds, tk ? tk + 2 : nullptr);
   if (band_wave_class(b) != 0) {  // the substitution follows in k_local_subst
-    if (mode == 0) band_export<TC>(lds, G, Lt, n, b);
+    if (mode == 0) band_export<TC>(lds + band_panel_elems(b), G, n, b);
   } else {
-    band_substitute<TC, TC>(B, n, b, X, nck, mode == 0 ? lds + bsz : lds);
+    band_substitute<TC, TC>(B, n, b, X, nck, lds);
     if (!std::is_same<TS, TC>::value || xwork) {
       TS* out = pvals + pval_off[K];
       for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x)
@@ -713,8 +713,7 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
     const int mode = band_mode(static_cast<int>(nk), h_band[K], lds_cap);
     FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "local block bandwidth too large for LDS");
     off[2 * k] = band_total;
-    if (mode != 0 || band_wave_class(h_band[K]) != 0)
-      band_total += 2 * nk * (h_band[K] + 1);  // factor band and Lt in global memory
+    band_total += 2 * nk * (h_band[K] + 1);  // factor band and Lt in global memory
     lds_need = std::max(lds_need, band_lds_elems(mode, static_cast<int>(nk), h_band[K]));
     off[2 * k + 1] = x_total;
     if (separate_x) x_total += nk * h_ncols[K];
@@ -745,7 +744,10 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
   allow_lds(reinterpret_cast<const void*>(&k_local_solve<TS, TC>), lds_elems * sizeof(TC));
   static const bool timing_on = std::getenv("FAMS_BLOCK_TIMING") != nullptr;
   DBuf<unsigned long long> timing;
-  if (timing_on) timing.reset(&h->alloc, 8 * static_cast<size_t>(nb));
+  if (timing_on) {
+    timing.reset(&h->alloc, kTickSlots * static_cast<size_t>(nb));
+    HIPX(hipMemsetAsync(timing, 0, kTickSlots * nb * sizeof(unsigned long long), h->stream));
+  }
   LAUNCH(h, "local_solve", (k_local_solve<TS, TC>), nb, kThreads, lds_elems * sizeof(TC),
          static_cast<const int*>(d_list.get()), blocks[0], comp_ptr, cells, h->rp.get(),
          h->ci.get(), h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols,
@@ -802,14 +804,14 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
 // (wall-clock ticks of the device's constant-rate counter): the launch's
 // span, the summed phases per storage mode and the slowest blocks.
 void print_block_timing(const unsigned long long* dev, int nb, int first) {
-  std::vector<unsigned long long> t(8 * static_cast<size_t>(nb));
+  std::vector<unsigned long long> t(kTickSlots * static_cast<size_t>(nb));
   HIPX(hipMemcpy(t.data(), dev, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
   double sum[3][5] = {};
   int cnt[3] = {0, 0, 0};
   unsigned long long t_first = ~0ull, t_last = 0;
   std::vector<std::pair<double, int>> tot;
   for (int k = 0; k < nb; ++k) {
-    const unsigned long long* r = &t[8 * static_cast<size_t>(k)];
+    const unsigned long long* r = &t[kTickSlots * static_cast<size_t>(k)];
     const int mode = static_cast<int>(r[6] & 3);
     double ph[4] = {double(r[1] - r[0]), double(r[2] - r[1]), double(r[3] - r[2]),
                     double(r[4] - r[3])};
@@ -829,10 +831,13 @@ void print_block_timing(const unsigned long long* dev, int nb, int first) {
                    "substitute %.3g; slowest %.3g\n", m, cnt[m], sum[m][0], sum[m][1], sum[m][2],
                    sum[m][3], sum[m][4]);
   for (int q = 0; q < std::min(nb, 6); ++q) {
-    const unsigned long long* r = &t[8 * static_cast<size_t>(tot[q].second)];
+    const unsigned long long* r = &t[kTickSlots * static_cast<size_t>(tot[q].second)];
     std::fprintf(stderr, "   n %llu b %llu nck %llu mode %llu : assemble %llu factor %llu normalise %llu substitute %llu\n",
                  r[5] >> 32, r[5] & 0xffffffffull, r[6] >> 32, r[6] & 0xffffffffull, r[1] - r[0],
                  r[2] - r[1], r[3] - r[2], r[4] - r[3]);
+    if (r[8] | r[9] | r[10] | r[11] | r[12])
+      std::fprintf(stderr, "      blocked factor: ring load %llu panel %llu D/L %llu trailing %llu ring store %llu\n",
+                   r[8], r[9], r[10], r[11], r[12]);
   }
 }
 
