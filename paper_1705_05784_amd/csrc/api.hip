@@ -45,21 +45,22 @@ void Allocator::release(void* p, size_t bytes) {
   live_bytes -= static_cast<int64_t>(bytes);
 }
 
-int Prof::begin(const char* name) {
+int Prof::begin(const char* name, hipStream_t s) {
   if (!on) return -1;
   Pending pe;
   pe.name = name;
+  pe.s = s ? s : stream;
   HIPX(hipEventCreate(&pe.a));
   HIPX(hipEventCreate(&pe.b));
-  HIPX(hipEventRecord(pe.a, stream));
+  HIPX(hipEventRecord(pe.a, pe.s));
   pending.push_back(pe);
   return static_cast<int>(pending.size()) - 1;
 }
 
 void Prof::end(int token) {
   if (token < 0) return;
-  HIPX(hipEventRecord(pending[token].b, stream));
-  if (pending.size() > 20000) collect();
+  HIPX(hipEventRecord(pending[token].b, pending[token].s));
+  if (pending.size() > 20000 && pending[token].s == stream) collect();
 }
 
 void Prof::collect() {
@@ -81,6 +82,59 @@ Prof::~Prof() {
   for (auto& pe : pending) {
     (void)hipEventDestroy(pe.a);
     (void)hipEventDestroy(pe.b);
+  }
+}
+
+AuxStreams::~AuxStreams() {
+  for (int i = 0; i < kAuxStreams; ++i) {
+    if (s[i]) {
+      (void)hipStreamSynchronize(s[i]);
+      (void)hipStreamDestroy(s[i]);
+    }
+    if (join[i]) (void)hipEventDestroy(join[i]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+}
+
+Fork::Fork(Handle* h) : h_(h) {
+  AuxStreams& a = h->aux;
+  if (!a.fork) {
+    HIPX(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+    for (int i = 0; i < kAuxStreams; ++i) {
+      HIPX(hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking));
+      HIPX(hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming));
+    }
+  }
+  HIPX(hipEventRecord(a.fork, h->stream));
+}
+
+hipStream_t Fork::next() {
+  const int i = k_++ % (kAuxStreams + 1);
+  if (i == 0) return h_->stream;
+  if (!used_[i - 1]) {
+    HIPX(hipStreamWaitEvent(h_->aux.s[i - 1], h_->aux.fork, 0));
+    used_[i - 1] = true;
+  }
+  return h_->aux.s[i - 1];
+}
+
+void Fork::join() {
+  if (joined_) return;
+  joined_ = true;
+  for (int i = 0; i < kAuxStreams; ++i) {
+    if (!used_[i]) continue;
+    HIPX(hipEventRecord(h_->aux.join[i], h_->aux.s[i]));
+    HIPX(hipStreamWaitEvent(h_->stream, h_->aux.join[i], 0));
+  }
+}
+
+Fork::~Fork() {
+  if (joined_) return;
+  joined_ = true;
+  for (int i = 0; i < kAuxStreams; ++i) {
+    if (!used_[i]) continue;
+    (void)hipEventRecord(h_->aux.join[i], h_->aux.s[i]);
+    (void)hipStreamWaitEvent(h_->stream, h_->aux.join[i], 0);
   }
 }
 

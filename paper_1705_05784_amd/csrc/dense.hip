@@ -629,68 +629,89 @@ __global__ void __launch_bounds__(256) k_gje_row(double* a, int n, int k0, int n
   a[static_cast<int64_t>(c) * n + k0 + i] = s;
 }
 
-// ---- solves with LU factors (one workgroup) ---------------------------------
-// x = A^{-1} b from P A = L U: x <- P b, then L (unit) and U by blocks of 64
-// rows: the block's 64 x 64 diagonal part is staged in LDS, one wavefront
-// solves it with register shuffles, then all threads subtract the block's
-// contribution from the rows after (before) it.  x lives in LDS.
-constexpr int kLuSolveMax = 12288;
+// ---- solves with LU factors ---------------------------------------------------
+// x = A^{-1} b from P A = L U (factors column-major): x <- P b, then L (unit)
+// and U, each in one launch of one wavefront per chunk of 64 rows.  The
+// wavefront of chunk i subtracts the contributions of the chunks before it
+// (after it, for U) in chunk order, each as soon as that chunk's solution is
+// published, then solves its 64 x 64 diagonal block with register shuffles,
+// publishes its own solution and raises its flag.  Chunks wait only on
+// chunks dispatched before them.  A wait is bounded (`limit` ticks): on
+// timeout err is set, the remaining waits end at once and the result is void.
+constexpr int kLuSolveMax = 1 << 20;
 constexpr int kLuB = 64;
 
-__global__ void __launch_bounds__(1024)
-k_lu_solve(int n, const double* lu, const int* perm, const double* b, double* x) {
-  extern __shared__ double xs[];
-  __shared__ double D[kLuB][kLuB + 1];
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid % 64;
-  for (int i = tid; i < n; i += nt) xs[i] = b[perm[i]];
-  for (int b0 = 0; b0 < n; b0 += kLuB) {  // forward, unit lower
-    const int nbk = min(kLuB, n - b0);
-    for (int e = tid; e < kLuB * kLuB; e += nt) {
-      const int r = e % kLuB, q = e / kLuB;
-      D[r][q] = (r < nbk && q < nbk) ? lu[static_cast<int64_t>(b0 + q) * n + b0 + r] : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double v = lane < nbk ? xs[b0 + lane] : 0.0;
-      for (int q = 0; q < nbk; ++q) {
-        const double xq = __shfl(v, q);
-        if (lane > q) v -= D[lane][q] * xq;
+__global__ void k_gather_perm(int n, const int* perm, const double* b, double* w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = b[perm[i]];
+}
+
+template <bool kUpper>
+__global__ void __launch_bounds__(64)
+k_lu_df(int n, const double* lu, const double* w, double* x, int* flag, int epoch, int* err,
+        unsigned long long limit) {
+  const int lane = threadIdx.x;
+  const int nch = (n + kLuB - 1) / kLuB;
+  const int ci = kUpper ? nch - 1 - static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x);
+  const int r0 = ci * kLuB, nbk = min(kLuB, n - r0), r = r0 + lane;
+  const bool own = lane < nbk;
+  double v = own ? w[r] : 0.0;
+  auto wait = [&](int j) {
+    const unsigned long long t0 = wall_clock64();
+    while (true) {
+      int f = __hip_atomic_load(flag + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      f = __builtin_amdgcn_readfirstlane(f);
+      if (f == epoch) break;
+      int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      e = __builtin_amdgcn_readfirstlane(e);
+      if (e != 0) break;
+      if (wall_clock64() - t0 > limit) {
+        if (lane == 0) atomicOr(err, 1);
+        break;
       }
-      if (lane < nbk) xs[b0 + lane] = v;
+      __builtin_amdgcn_s_sleep(2);
     }
-    __syncthreads();
-    for (int i = b0 + nbk + tid; i < n; i += nt) {
-      double s = xs[i];
-      for (int q = 0; q < nbk; ++q) s -= lu[static_cast<int64_t>(b0 + q) * n + i] * xs[b0 + q];
-      xs[i] = s;
+  };
+  // contributions of the other chunks, in the order the chunks finish
+  for (int s = 0; s < (kUpper ? nch - 1 - ci : ci); ++s) {
+    const int j = kUpper ? nch - 1 - s : s;
+    const int c0 = j * kLuB, nbj = min(kLuB, n - c0);
+    double a[kLuB];
+#pragma unroll
+    for (int q = 0; q < kLuB; ++q)
+      a[q] = (own && q < nbj) ? lu[static_cast<int64_t>(c0 + q) * n + r] : 0.0;
+    wait(j);
+    const double xj = lane < nbj ? x[c0 + lane] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kLuB; ++q) {
+      const double xq = __shfl(xj, q);
+      if (q < nbj) v -= a[q] * xq;
     }
-    __syncthreads();
   }
-  for (int b0 = ((n - 1) / kLuB) * kLuB; b0 >= 0; b0 -= kLuB) {  // backward, upper
-    const int nbk = min(kLuB, n - b0);
-    for (int e = tid; e < kLuB * kLuB; e += nt) {
-      const int r = e % kLuB, q = e / kLuB;
-      D[r][q] = (r < nbk && q < nbk) ? lu[static_cast<int64_t>(b0 + q) * n + b0 + r] : 1.0;
+  // the diagonal block: A(r0 + lane, r0 + q)
+  double d[kLuB];
+#pragma unroll
+  for (int q = 0; q < kLuB; ++q)
+    d[q] = (own && q < nbk) ? lu[static_cast<int64_t>(r0 + q) * n + r] : 0.0;
+  if constexpr (!kUpper) {
+#pragma unroll
+    for (int q = 0; q < kLuB; ++q) {
+      const double xq = __shfl(v, q);
+      if (q < nbk && lane > q) v -= d[q] * xq;
     }
-    __syncthreads();
-    if (tid < 64) {
-      double v = lane < nbk ? xs[b0 + lane] : 0.0;
-      for (int q = nbk - 1; q >= 0; --q) {
-        if (lane == q) v = v / D[q][q];
+  } else {
+#pragma unroll
+    for (int q = kLuB - 1; q >= 0; --q) {
+      if (q < nbk) {
+        if (lane == q) v = v / d[q];
         const double xq = __shfl(v, q);
-        if (lane < q) v -= D[lane][q] * xq;
+        if (lane < q) v -= d[q] * xq;
       }
-      if (lane < nbk) xs[b0 + lane] = v;
     }
-    __syncthreads();
-    for (int i = tid; i < b0; i += nt) {
-      double s = xs[i];
-      for (int q = 0; q < nbk; ++q) s -= lu[static_cast<int64_t>(b0 + q) * n + i] * xs[b0 + q];
-      xs[i] = s;
-    }
-    __syncthreads();
   }
-  for (int i = tid; i < n; i += nt) x[i] = xs[i];
+  if (own) x[r] = v;
+  __threadfence();
+  if (lane == 0) __hip_atomic_store(flag + ci, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace
@@ -838,12 +859,30 @@ void dense_gemm_add(Handle* h, int m, int p, int k, double alpha, const double* 
   gemm_mfma(h, m, p, k, alpha, A, lda, B, ldb, C, ldc);
 }
 
-// x = A^{-1} b from lu_factor's output
+// x = A^{-1} b from lu_factor's output (x and b may alias)
 void lu_solve(Handle* h, const double* lu, const int* perm, int n, const double* b, double* x) {
   FAMS_REQUIRE(n <= kLuSolveMax, FAMS_ERR_CAPACITY, "coarse system too large for the LU solve");
-  const size_t lds = static_cast<size_t>(n) * sizeof(double);
-  allow_lds(reinterpret_cast<const void*>(&k_lu_solve), lds);
-  LAUNCH(h, "lu_solve", k_lu_solve, 1, 1024, lds, n, lu, perm, b, x);
+  const int nch = (n + kLuB - 1) / kLuB;
+  if (h->lu_flag_n < 2 * nch) {
+    h->lu_flags.reset(&h->alloc, 2 * nch);
+    HIPX(hipMemsetAsync(h->lu_flags, 0, 2 * nch * sizeof(int), h->stream));
+    h->lu_flag_n = 2 * nch;
+    h->lu_epoch = 0;
+  }
+  if (!h->lu_err.get()) h->lu_err.reset(&h->alloc, 1);
+  HIPX(hipMemsetAsync(h->lu_err, 0, sizeof(int), h->stream));
+  const int epoch = ++h->lu_epoch;
+  const unsigned long long limit = wait_limit(h);
+  DBuf<double> w1(&h->alloc, n), w2(&h->alloc, n);
+  LAUNCH(h, "lu_solve", k_gather_perm, blocks_for(n, 256), 256, 0, n, perm, b, w1.get());
+  LAUNCH(h, "lu_solve", k_lu_df<false>, nch, 64, 0, n, lu, static_cast<const double*>(w1.get()),
+         w2.get(), h->lu_flags.get(), epoch, h->lu_err.get(), limit);
+  LAUNCH(h, "lu_solve", k_lu_df<true>, nch, 64, 0, n, lu, static_cast<const double*>(w2.get()), x,
+         h->lu_flags.get() + nch, epoch, h->lu_err.get(), limit);
+  int e = 0;
+  HIPX(hipMemcpyAsync(&e, h->lu_err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "LU solve: a dependency wait exceeded its bound");
 }
 
 // part: [ceil(nc / 64) * nc] partial sums

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <numeric>
 #include <vector>
 
 #include "band.hpp"
@@ -476,9 +477,13 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   {  // the solves, by chunk-slot class
     std::vector<int> list;
     std::vector<std::pair<int, int>> cls;
+    std::vector<int> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return hp[a + 1] - hp[a] > hp[b + 1] - hp[b]; });
     for (int m : {2, 3, 4, 5, 6, 7, 9}) {
       const size_t l0 = list.size();
-      for (int K = 0; K < nc; ++K)
+      for (int K : order)
         if (band_wave_class(hb[K]) == m) list.push_back(K);
       if (list.size() > l0) cls.emplace_back(m, static_cast<int>(list.size() - l0));
     }
@@ -487,9 +492,11 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
       HIPX(hipMemcpyAsync(d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
                           h->stream));
     int l0 = 0;
+    Fork fork(h);
     for (auto [m, cnt] : cls) {
+      hipStream_t st = fork.next();
 #define FAMS_NSOLVE(M)                                                                        \
-  LAUNCH(h, "flux_neumann_solve", k_neumann_solve<M>, cnt, 64, 0,                             \
+  LAUNCH_ON(h, st, "flux_neumann_solve", k_neumann_solve<M>, cnt, 64, 0,                      \
          static_cast<const int*>(d_list.get() + l0), nc, h->fv_ptr.get(), h->fv_order.get(),   \
          h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(), h->vertex.get(), \
          band.get(), singular.get(), d_off.get(), static_cast<const double*>(scratch.get()),    \
@@ -506,6 +513,7 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
 #undef FAMS_NSOLVE
       l0 += cnt;
     }
+    fork.join();
     HIPX(hipStreamSynchronize(h->stream));  // d_list is freed on return
   }
 

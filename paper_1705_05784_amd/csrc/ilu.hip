@@ -466,6 +466,8 @@ __global__ void k_ell_vals(int n, const int* rows, const int* diag, const int* e
   ediag[t] = lu[diag[rows[t]]];
 }
 
+}  // namespace
+
 // bound of one dataflow wait: 2 s of the device's constant-rate clock
 unsigned long long wait_limit(Handle* h) {
   if (!h->wait_ticks) {
@@ -476,6 +478,8 @@ unsigned long long wait_limit(Handle* h) {
   }
   return h->wait_ticks;
 }
+
+namespace {
 
 void levels(Handle* h, int upper, Levels* out, std::vector<int>* host_lev) {
   const int n = h->n;

@@ -94,23 +94,38 @@ struct Prof {
   struct Pending {
     std::string name;
     hipEvent_t a, b;
+    hipStream_t s;
   };
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int64_t>> totals;
   std::vector<std::string> names_cache;
-  int begin(const char* name);
+  // events around one launch on stream s (the handle's stream if null)
+  int begin(const char* name, hipStream_t s = nullptr);
   void end(int token);
   void collect();  // synchronises the stream, folds pending events into totals
   ~Prof();
 };
 
-#define LAUNCH(H, NAME, KERNEL, GRID, BLOCK, SHMEM, ...)                          \
+#define LAUNCH_ON(H, STREAM, NAME, KERNEL, GRID, BLOCK, SHMEM, ...)                \
   do {                                                                            \
-    int tok_ = (H)->prof.begin(NAME);                                             \
-    hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), SHMEM, (H)->stream, __VA_ARGS__); \
+    hipStream_t st_ = (STREAM);                                                   \
+    int tok_ = (H)->prof.begin(NAME, st_);                                        \
+    hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), SHMEM, st_, __VA_ARGS__);  \
     HIPX(hipGetLastError());                                                      \
     (H)->prof.end(tok_);                                                          \
   } while (0)
+#define LAUNCH(H, NAME, KERNEL, GRID, BLOCK, SHMEM, ...) \
+  LAUNCH_ON(H, (H)->stream, NAME, KERNEL, GRID, BLOCK, SHMEM, __VA_ARGS__)
+
+// Auxiliary streams (default priority) for independent launches that may
+// run side by side; see Fork.
+constexpr int kAuxStreams = 3;
+struct AuxStreams {
+  hipStream_t s[kAuxStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kAuxStreams] = {};
+  ~AuxStreams();
+};
 
 inline unsigned blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
@@ -160,6 +175,7 @@ struct Handle {
   Allocator alloc;
   hipStream_t stream = nullptr;
   Prof prof;
+  AuxStreams aux;
 
   // options
   int variant = FAMS_DECOUPLED;
@@ -209,6 +225,10 @@ struct Handle {
   bool fv_ready = false;
   DBuf<double> Afv, Afv_lu;
   DBuf<int> Afv_perm;
+  DBuf<int> lu_flags;  // chunk flags of the dataflow LU solve (2 per 64 rows), and
+  DBuf<int> lu_err;    // its error word
+  int lu_epoch = 0;
+  int lu_flag_n = 0;
   DBuf<int> fv_order, fv_ptr;  // cells grouped by primal block
   int fv_max_block = 0;
 
@@ -221,6 +241,24 @@ struct Handle {
   size_t wk_vectors = 0;
 
   fams_setup_info_t info{};
+};
+
+// Fork-join of independent launches: next() hands out the handle's stream
+// and then the auxiliary streams in turn, each ordered after the work the
+// handle's stream held when the Fork was made; join() (also on destruction,
+// where errors are ignored) makes the handle's stream wait for all of them.
+class Fork {
+ public:
+  explicit Fork(Handle* h);
+  hipStream_t next();
+  void join();
+  ~Fork();
+
+ private:
+  Handle* h_;
+  int k_ = 0;
+  bool used_[kAuxStreams] = {};
+  bool joined_ = false;
 };
 
 // dynamic LDS budget of one workgroup on this device (bytes, <= 160 KiB), and
@@ -251,6 +289,8 @@ void lu_factor(Handle* h, double* a, int n, int* perm);
 bool spd_inverse(Handle* h, const double* a, double* inv, int n);
 void lu_solve(Handle* h, const double* lu, const int* perm, int n, const double* b, double* x);
 int lu_solve_limit();
+// bound of one dataflow wait (device wall-clock ticks)
+unsigned long long wait_limit(Handle* h);
 void dense_gemm_add(Handle* h, int m, int p, int k, double alpha, const double* A, int lda,
                     const double* B, int ldb, double* C, int ldc);
 void coarse_apply(Handle* h, const double* inv, int nc, const double* x, double* y, double* part);

@@ -36,6 +36,7 @@ namespace {
 enum : int8_t { C_NONE = 0, C_KEPT = 1, C_LUMPED = 2, C_RHS = 3 };
 
 constexpr int kThreads = 256;
+constexpr int kBigBlockThreads = 512;  // blocks whose band lives in global memory
 constexpr int kMaxCols = 2048;      // coarse columns per block (RHS count)
 
 enum ErrBits : int {
@@ -371,7 +372,7 @@ __global__ void k_colcopy(int c0, int ncomp_level, const int* tmp_cols, const in
 // is computed in `xwork` and rounded into the pool.  `list` (optional)
 // selects the blocks: block = list[blockIdx.x], else c0 + blockIdx.x.
 template <class TS, class TC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kBigBlockThreads)
 k_local_solve(const int* list, int c0, const int* comp_ptr, const int* cells, const int* rp,
               const int* ci, const double* av, const int8_t* ecls, const int8_t* wb,
               const int* coarse_of, const int* comp_of, const int* local_idx,
@@ -477,7 +478,8 @@ template <class TS, class TC, int M>
 __global__ void __launch_bounds__(64)
 k_local_subst(const int* groups, const int* list, int c0, const int* comp_ptr, const int* ncols,
               const int* band, const int64_t* pval_off, TS* pvals, const int64_t* work_off,
-              const TC* band_glob, TC* xwork) {
+              const TC* band_glob, TC* xwork, unsigned long long* timing) {
+  unsigned long long t0 = timing ? wall_clock64() : 0;
   const int* gq = groups + 3 * static_cast<int64_t>(blockIdx.x);
   const int slot = gq[0], col = gq[1], nc = gq[2];
   const int K = list ? list[slot] : c0 + slot;
@@ -491,6 +493,13 @@ k_local_subst(const int* groups, const int* list, int c0, const int* comp_ptr, c
   constexpr int J = sizeof(TC) == 4 ? 8 : 4;
   if (nc == 4) band_wave_columns<TC, TC, TS, M, 4, J>(G, Lt, 1, 0, n, b, X, nck, col, out);
   else band_wave_columns<TC, TC, TS, M, 1, J>(G, Lt, 1, 0, n, b, X, nck, col, out);
+  if (timing && threadIdx.x == 0) {
+    unsigned long long* tk = timing + 4 * static_cast<int64_t>(blockIdx.x);
+    tk[0] = t0;
+    tk[1] = wall_clock64();
+    tk[2] = (static_cast<unsigned long long>(n) << 32) | static_cast<unsigned>(b);
+    tk[3] = (static_cast<unsigned long long>(M) << 32) | static_cast<unsigned>(nc);
+  }
 }
 
 // ---- P in CSR (with the optional truncation of Sec. 4.3) -------------------
@@ -701,20 +710,35 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
                   const int* cols, const int* ncols, const int* band, const int64_t* pval_off,
                   TS* pvals, const std::vector<int>& h_comp_ptr, const std::vector<int>& h_band,
                   const std::vector<int>& h_ncols, int* err, int* bad_block) {
-  int nb = static_cast<int>(blocks.size());
+  const int nb = static_cast<int>(blocks.size());
   if (nb == 0) return;
+  (void)use_list;
   const bool separate_x = !std::is_same<TS, TC>::value;
-  std::vector<int64_t> off(2 * nb, 0);
-  int64_t band_total = 0, x_total = 0, lds_need = 0;
   const int64_t lds_cap = lds_budget(h) / static_cast<int64_t>(sizeof(TC));
+  // slots: the blocks whose band fits in LDS (in the given order), then the
+  // others, longest first, which get a launch of their own with more waves
+  std::vector<int> blk, big;
+  for (int K : blocks) {
+    const int nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
+    const int mode = band_mode(nk, h_band[K], lds_cap);
+    FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "local block bandwidth too large for LDS");
+    (mode == 0 ? blk : big).push_back(K);
+  }
+  std::stable_sort(big.begin(), big.end(), [&](int a, int b) {
+    return h_comp_ptr[a + 1] - h_comp_ptr[a] > h_comp_ptr[b + 1] - h_comp_ptr[b];
+  });
+  const int n_small = static_cast<int>(blk.size());
+  blk.insert(blk.end(), big.begin(), big.end());
+  std::vector<int64_t> off(2 * nb, 0);
+  int64_t band_total = 0, x_total = 0, lds_small = 0, lds_big = 0;
   for (int k = 0; k < nb; ++k) {
-    int K = blocks[k];
+    int K = blk[k];
     int64_t nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
     const int mode = band_mode(static_cast<int>(nk), h_band[K], lds_cap);
-    FAMS_REQUIRE(mode >= 0, FAMS_ERR_CAPACITY, "local block bandwidth too large for LDS");
     off[2 * k] = band_total;
     band_total += 2 * nk * (h_band[K] + 1);  // factor band and Lt in global memory
-    lds_need = std::max(lds_need, band_lds_elems(mode, static_cast<int>(nk), h_band[K]));
+    int64_t& need = k < n_small ? lds_small : lds_big;
+    need = std::max(need, band_lds_elems(mode, static_cast<int>(nk), h_band[K]));
     off[2 * k + 1] = x_total;
     if (separate_x) x_total += nk * h_ncols[K];
     {  // arithmetic of the band LDL^T (step k updates a triangle of
@@ -731,39 +755,55 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
   DBuf<int64_t> d_off(&h->alloc, 2 * nb);
   HIPX(hipMemcpyAsync(d_off, off.data(), 2 * nb * sizeof(int64_t), hipMemcpyHostToDevice,
                       h->stream));
-  DBuf<int> d_list;
-  if (use_list) {
-    d_list.reset(&h->alloc, nb);
-    HIPX(hipMemcpyAsync(d_list, blocks.data(), nb * sizeof(int), hipMemcpyHostToDevice,
-                        h->stream));
-  }
+  DBuf<int> d_list(&h->alloc, nb);
+  HIPX(hipMemcpyAsync(d_list, blk.data(), nb * sizeof(int), hipMemcpyHostToDevice, h->stream));
   DBuf<TC> scratch(&h->alloc, std::max<int64_t>(band_total, 1));
   DBuf<TC> xw;
   if (separate_x) xw.reset(&h->alloc, std::max<int64_t>(x_total, 1));
-  int lds_elems = static_cast<int>(lds_need);
-  allow_lds(reinterpret_cast<const void*>(&k_local_solve<TS, TC>), lds_elems * sizeof(TC));
+  allow_lds(reinterpret_cast<const void*>(&k_local_solve<TS, TC>),
+            std::max(lds_small, lds_big) * sizeof(TC));
   static const bool timing_on = std::getenv("FAMS_BLOCK_TIMING") != nullptr;
   DBuf<unsigned long long> timing;
   if (timing_on) {
     timing.reset(&h->alloc, kTickSlots * static_cast<size_t>(nb));
     HIPX(hipMemsetAsync(timing, 0, kTickSlots * nb * sizeof(unsigned long long), h->stream));
   }
-  LAUNCH(h, "local_solve", (k_local_solve<TS, TC>), nb, kThreads, lds_elems * sizeof(TC),
-         static_cast<const int*>(d_list.get()), blocks[0], comp_ptr, cells, h->rp.get(),
-         h->ci.get(), h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols,
-         ncols, band, pval_off, pvals, d_off.get(), scratch.get(), xw.get(), lds_elems, err,
-         bad_block, timing.get());
+  {
+    Fork fork(h);
+    for (int part = 0; part < 2; ++part) {  // slots [s0, s1)
+      const int s0 = part ? n_small : 0, s1 = part ? nb : n_small;
+      if (s1 == s0) continue;
+      const int lds_elems = static_cast<int>(part ? lds_big : lds_small);
+      hipStream_t st = fork.next();
+      LAUNCH_ON(h, st, "local_solve", (k_local_solve<TS, TC>), s1 - s0,
+                part ? kBigBlockThreads : kThreads, lds_elems * sizeof(TC),
+                static_cast<const int*>(d_list.get() + s0), 0, comp_ptr, cells, h->rp.get(),
+                h->ci.get(), h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols,
+                ncols, band, pval_off, pvals, d_off.get() + 2 * s0, scratch.get(), xw.get(),
+                lds_elems, err, bad_block, timing_on ? timing.get() + kTickSlots * s0 : nullptr);
+    }
+    fork.join();
+  }
   if (timing_on) {
     HIPX(hipStreamSynchronize(h->stream));
-    print_block_timing(timing.get(), nb, blocks[0]);
+    if (n_small) print_block_timing(timing.get(), n_small, blocks[0]);
+    if (nb > n_small)
+      print_block_timing(timing.get() + kTickSlots * n_small, nb - n_small, blocks[0]);
   }
   // substitutions: groups of 4 columns, then single columns, per slot class
+  // (classes on separate streams; within a class the longest blocks first)
+  std::vector<int> order(nb);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return h_comp_ptr[blk[a] + 1] - h_comp_ptr[blk[a]] >
+           h_comp_ptr[blk[b] + 1] - h_comp_ptr[blk[b]];
+  });
   std::vector<int> groups;
   std::vector<std::pair<int, int>> cls;  // (class, groups in it)
   for (int m : {2, 3, 4, 5, 6, 7, 9}) {
     const size_t g0 = groups.size();
-    for (int k = 0; k < nb; ++k) {
-      const int K = blocks[k];
+    for (int k : order) {
+      const int K = blk[k];
       if (band_wave_class(h_band[K]) != m) continue;
       const int nck = h_ncols[K];
       for (int c = 0; c + 4 <= nck; c += 4) groups.insert(groups.end(), {k, c, 4});
@@ -776,13 +816,18 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
   if (!groups.empty())
     HIPX(hipMemcpyAsync(d_groups, groups.data(), groups.size() * sizeof(int),
                         hipMemcpyHostToDevice, h->stream));
+  DBuf<unsigned long long> sub_timing;
+  if (timing_on) sub_timing.reset(&h->alloc, 4 * std::max<size_t>(groups.size() / 3, 1));
   int64_t gofs = 0;
+  Fork fork(h);
   for (auto [m, ng] : cls) {
+    hipStream_t st = fork.next();
 #define FAMS_SUBST(M)                                                                         \
-  LAUNCH(h, "local_subst", (k_local_subst<TS, TC, M>), ng, 64, 0,                             \
+  LAUNCH_ON(h, st, "local_subst", (k_local_subst<TS, TC, M>), ng, 64, 0,                      \
          static_cast<const int*>(d_groups.get() + 3 * gofs), static_cast<const int*>(d_list.get()), \
          blocks[0], comp_ptr, ncols, band, pval_off, pvals, static_cast<const int64_t*>(d_off.get()), \
-         static_cast<const TC*>(scratch.get()), xw.get())
+         static_cast<const TC*>(scratch.get()), xw.get(),                                      \
+         timing_on ? sub_timing.get() + 4 * gofs : nullptr)
     switch (m) {
       case 2: FAMS_SUBST(2); break;
       case 3: FAMS_SUBST(3); break;
@@ -795,7 +840,29 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
 #undef FAMS_SUBST
     gofs += ng;
   }
+  fork.join();
   HIPX(hipStreamSynchronize(h->stream));  // scratch is freed on return
+  if (timing_on && !groups.empty()) {  // the launch span and its longest wavefronts
+    const size_t ng = groups.size() / 3;
+    std::vector<unsigned long long> t(4 * ng);
+    HIPX(hipMemcpy(t.data(), sub_timing.get(), t.size() * sizeof(unsigned long long),
+                   hipMemcpyDeviceToHost));
+    unsigned long long lo = ~0ull, hi = 0;
+    std::vector<std::pair<unsigned long long, size_t>> d(ng);
+    for (size_t g = 0; g < ng; ++g) {
+      lo = std::min(lo, t[4 * g]);
+      hi = std::max(hi, t[4 * g + 1]);
+      d[g] = {t[4 * g + 1] - t[4 * g], g};
+    }
+    std::sort(d.begin(), d.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    std::fprintf(stderr, "[subst from %d] %zu wavefronts, span %llu ticks\n", blocks[0], ng, hi - lo);
+    for (size_t q = 0; q < std::min<size_t>(ng, 4); ++q) {
+      const unsigned long long* r = &t[4 * d[q].second];
+      std::fprintf(stderr, "   n %llu b %llu M %llu cols %llu : %llu ticks (start +%llu)\n",
+                   r[2] >> 32, r[2] & 0xffffffffull, r[3] >> 32, r[3] & 0xffffffffull, d[q].first,
+                   r[0] - lo);
+    }
+  }
 }
 
 }  // namespace

@@ -109,6 +109,7 @@ def traffic(fetch_db, write_db, copy_bytes, out_json, source_digest, launch_name
 # library kernel symbols -> the launch names used by the library's own timers
 LAUNCH_NAMES = {
     "k_local_solve<float, float>": "local_solve",
+    "k_sweep_ranges<float, false>": "ilu_lower", "k_sweep_ranges<float, true>": "ilu_upper",
     "k_sweep_lower<float>": "ilu_lower", "k_sweep_upper<float>": "ilu_upper",
 }
 

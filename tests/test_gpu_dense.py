@@ -47,7 +47,7 @@ def test_lu_inverse(n):
     assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("n", [1, 37, 65, 300])
+@pytest.mark.parametrize("n", [1, 37, 65, 300, 700])
 def test_lu_solve(n):
     from paper_1705_05784_amd import fams
     _say(f"[dense] lu solve n={n}")
