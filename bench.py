@@ -66,7 +66,7 @@ ITERATION_KERNELS = ("ilu_lower", "ilu_upper", "spmv_resid", "spmv", "prolong", 
                      "coarse_gemv")
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "traffic_config2.json")
+                            "traffic_edfm3d_100x100x50.json")
 
 
 def source_digest():
