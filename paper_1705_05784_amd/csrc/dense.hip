@@ -61,6 +61,7 @@ k_rap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int* 
 constexpr int kApSlots = 1024;   // hash slots per row (at most half used)
 constexpr int kApWaves = 4;      // rows per 256-thread block
 constexpr int kApEmpty = INT_MIN;
+constexpr int kApSrc = 8;        // entries of a row of A whose P rows are loaded together
 
 __device__ __forceinline__ int ap_slot(int* tab, int key, bool* full) {
   unsigned hh = (static_cast<unsigned>(key) * 2654435761u) & (kApSlots - 1);
@@ -92,13 +93,40 @@ k_ap(int n, const int* rp, const int* ci, const double* av, const int* p_rp, con
   __syncthreads();
   bool full = false;
   if (i < n) {
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-      const int j = ci[p];
-      const double a = av[p];
-      for (int q = p_rp[j] + lane; q < p_rp[j + 1]; q += 64) {
-        const int sl = ap_slot(t, p_ci[q], &full);
-        if constexpr (kFill) {
-          if (sl >= 0) acc[wave][sl] += a * p_val[q];
+    // kApSrc entries of A's row at a time: their P rows are loaded together
+    // (lanes over a P row's entries, one register slot per entry of A), then
+    // entered into the row's table in A's column order
+    const int p0 = rp[i], p1 = rp[i + 1];
+    for (int pb = p0; pb < p1; pb += kApSrc) {
+      const int ps = pb + lane;
+      const bool oks = lane < kApSrc && ps < p1;
+      const int js = oks ? ci[ps] : 0;
+      const double as = oks ? av[ps] : 0.0;
+      const int qs = oks ? p_rp[js] : 0, qe = oks ? p_rp[js + 1] : 0;
+      int key[kApSrc];
+      double pv[kApSrc];
+#pragma unroll
+      for (int e = 0; e < kApSrc; ++e) {
+        const int q = __shfl(qs, e) + lane;
+        const bool ok = q < __shfl(qe, e);
+        key[e] = ok ? p_ci[q] : kApEmpty;
+        pv[e] = ok ? p_val[q] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < kApSrc; ++e) {
+        const double a = __shfl(as, e);
+        if (key[e] != kApEmpty) {
+          const int sl = ap_slot(t, key[e], &full);
+          if constexpr (kFill) {
+            if (sl >= 0) acc[wave][sl] += a * pv[e];
+          }
+        }
+        const int qe_e = __shfl(qe, e);
+        for (int q = __shfl(qs, e) + 64 + lane; q < qe_e; q += 64) {  // P rows beyond 64 entries
+          const int sl = ap_slot(t, p_ci[q], &full);
+          if constexpr (kFill) {
+            if (sl >= 0) acc[wave][sl] += a * p_val[q];
+          }
         }
       }
     }
@@ -132,6 +160,7 @@ k_ap(int n, const int* rp, const int* ci, const double* av, const int* p_rp, con
 // distinct); the copies are then added in wavefront order, so every sum has a
 // fixed order.
 constexpr int kRapWaves = 4;
+constexpr int kRapGroup = 8;  // entries of R whose rows of A P are loaded together
 
 __global__ void __launch_bounds__(64 * kRapWaves)
 k_rap_ap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int64_t* ap_rp,
@@ -146,31 +175,34 @@ k_rap_ap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const in
   for (int j0 = 0; j0 < nc; j0 += jt) {
     const int j1 = min(nc, j0 + jt);
     for (int t = lane; t < j1 - j0; t += 64) acc[t] = 0.0;
-    int64_t q0 = 0, q1 = 0;
-    double w = 0.0;
-    if (eb < ee) {
-      const int i = R_ci[eb];
-      q0 = ap_rp[i];
-      q1 = ap_rp[i + 1];
-      w = R_val ? R_val[eb] : 1.0;
-    }
-    for (int e = eb; e < ee; ++e) {
-      // bounds of the next row while this one is accumulated
-      int64_t n0 = 0, n1 = 0;
-      double nw = 0.0;
-      if (e + 1 < ee) {
-        const int i = R_ci[e + 1];
-        n0 = ap_rp[i];
-        n1 = ap_rp[i + 1];
-        nw = R_val ? R_val[e + 1] : 1.0;
+    // kRapGroup entries of R at a time: their bounds (lanes), then the first
+    // 64 entries of each of their rows of A P are loaded together and added
+    // in R's order
+    for (int e0b = eb; e0b < ee; e0b += kRapGroup) {
+      const int el = e0b + lane;
+      const bool okl = lane < kRapGroup && el < ee;
+      const int il = okl ? R_ci[el] : 0;
+      const int64_t ql0 = okl ? ap_rp[il] : 0, ql1 = okl ? ap_rp[il + 1] : 0;
+      const double wl = okl ? (R_val ? R_val[el] : 1.0) : 0.0;
+      int Jv[kRapGroup];
+      double v[kRapGroup];
+#pragma unroll
+      for (int g = 0; g < kRapGroup; ++g) {
+        const int64_t q = __shfl(ql0, g) + lane;
+        const bool ok = q < __shfl(ql1, g);
+        Jv[g] = ok ? ap_ci[q] : -1;
+        v[g] = ok ? ap_val[q] : 0.0;
       }
-      for (int64_t q = q0 + lane; q < q1; q += 64) {
-        const int J = ap_ci[q];
-        if (J >= j0 && J < j1) acc[J - j0] += w * ap_val[q];
+#pragma unroll
+      for (int g = 0; g < kRapGroup; ++g) {
+        const double w = __shfl(wl, g);
+        if (Jv[g] >= j0 && Jv[g] < j1) acc[Jv[g] - j0] += w * v[g];
+        const int64_t q1 = __shfl(ql1, g);
+        for (int64_t q = __shfl(ql0, g) + 64 + lane; q < q1; q += 64) {  // rows beyond 64 entries
+          const int J = ap_ci[q];
+          if (J >= j0 && J < j1) acc[J - j0] += w * ap_val[q];
+        }
       }
-      q0 = n0;
-      q1 = n1;
-      w = nw;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < j1 - j0; t += blockDim.x) {
