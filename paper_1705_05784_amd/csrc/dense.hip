@@ -389,20 +389,6 @@ k_panel_reg(double* a, int n, int k0, int nb, int* ipiv, int* info) {
   }
 }
 
-// apply the panel's row interchanges to the columns outside the panel
-__global__ void k_laswp(double* a, int n, int k0, int nb, const int* ipiv) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n || (c >= k0 && c < k0 + nb)) return;
-  double* cc = a + static_cast<int64_t>(c) * n;
-  for (int j = k0; j < k0 + nb; ++j) {
-    int p = ipiv[j];
-    if (p != j) {
-      double t = cc[j];
-      cc[j] = cc[p];
-      cc[p] = t;
-    }
-  }
-}
 
 // B[k0:k0+nb, c] <- L11^{-1} B[...] (unit lower L11 at (k0, k0) of `l`), for
 // columns c in [c0, c1) of `b`; one thread per column
@@ -418,6 +404,40 @@ __global__ void k_trsm_lower_unit(const double* l, int n, int k0, int nb, double
   if (c >= c1) return;
   double x[kNb];
   double* col = b + static_cast<int64_t>(c) * n + k0;
+  for (int r = 0; r < nb; ++r) x[r] = col[r];
+  for (int r = 0; r < nb; ++r) {
+    double s = x[r];
+    for (int t = 0; t < r; ++t) s -= L[t * nb + r] * x[t];
+    x[r] = s;
+  }
+  for (int r = 0; r < nb; ++r) col[r] = x[r];
+}
+
+// the panel's row interchanges applied to every column outside the panel,
+// then, for the columns after it, B[k0:k0+nb, c] <- L11^{-1} B[...] (unit
+// lower L11 of the factored panel); one thread per column
+__global__ void k_swap_trsm(double* a, int n, int k0, int nb, const int* ipiv) {
+  __shared__ double L[kNb * kNb];
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    int r = t % nb, c = t / nb;
+    L[t] = a[static_cast<int64_t>(k0 + c) * n + k0 + r];
+  }
+  __syncthreads();
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k0) c += nb;  // skip the panel's own columns
+  if (c >= n) return;
+  double* cc = a + static_cast<int64_t>(c) * n;
+  for (int j = k0; j < k0 + nb; ++j) {
+    int p = ipiv[j];
+    if (p != j) {
+      double t = cc[j];
+      cc[j] = cc[p];
+      cc[p] = t;
+    }
+  }
+  if (c < k0 + nb) return;
+  double x[kNb];
+  double* col = cc + k0;
   for (int r = 0; r < nb; ++r) x[r] = col[r];
   for (int r = 0; r < nb; ++r) {
     double s = x[r];
@@ -821,14 +841,12 @@ void lu_factor(Handle* h, double* a, int n, int* perm_out) {
       nb = std::min(kNb, m);
       LAUNCH(h, "lu_panel", k_panel, 1, 1024, 0, a, n, k0, nb, ipiv.get(), info.get());
     }
-    LAUNCH(h, "lu_laswp", k_laswp, blocks_for(n, 256), 256, 0, a, n, k0, nb, ipiv.get());
     int c0 = k0 + nb;
-    if (c0 < n) {
-      LAUNCH(h, "lu_trsm", k_trsm_lower_unit, blocks_for(n - c0, 64), 64, 0, a, n, k0, nb, a, c0,
-             n);
+    if (n - nb > 0)
+      LAUNCH(h, "lu_trsm", k_swap_trsm, blocks_for(n - nb, 64), 64, 0, a, n, k0, nb, ipiv.get());
+    if (c0 < n)
       gemm_sub(h, n - c0, n - c0, nb, a + static_cast<int64_t>(k0) * n + c0,
                a + static_cast<int64_t>(c0) * n + k0, a + static_cast<int64_t>(c0) * n + c0, n);
-    }
     k0 += nb;
   }
   int hinfo = 0;
