@@ -142,8 +142,8 @@ def main():
                     help="one mixed step plus a 1 GiB device copy (for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; run with --gpus 1 "
-              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py: the F-AMS solve here runs on one GPU; run with --gpus 1 "
+              "(sharding across GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
