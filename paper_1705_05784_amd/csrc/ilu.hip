@@ -119,7 +119,7 @@ __global__ void k_ilu_rows(const int* rows, int r0, int r1, const int* rp, const
     while (a < end && b < bend) {
       int ca = ci[a], cb = ci[b];
       if (ca == cb) {
-        lu[a] -= lik * lu[b];
+        lu[a] = __builtin_fma(-lik, lu[b], lu[a]);  // one rounding, as in k_ilu_ranges
         ++a;
         ++b;
       } else if (ca < cb) {
@@ -430,6 +430,81 @@ k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const
   }
 }
 
+// ILU(0) factorisation in one launch on the lower sweep's range schedule
+// (the factorisation of row i needs exactly the rows its lower triangle
+// refers to).  A workgroup takes ranges in ticket order and walks a range
+// level by level with a barrier between levels (rows of earlier levels of
+// the same range are then visible); a pivot row in an earlier range is
+// waited for through its diagonal entry, which holds the sentinel until the
+// row is final and is published last, after a release fence.  The arithmetic
+// per row is the IKJ merge of k_ilu_rows, in the same order.  Waits are
+// bounded as in the sweeps.
+__global__ void k_diag_arm(int n, const int* diag, double* lu) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    using U = Sentinel<double>::U;
+    reinterpret_cast<U*>(lu)[diag[i]] = Sentinel<double>::bits;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_ilu_ranges(int n, int S, int nranges, const int* rows, const int* seg, const int* segbase,
+             const int* rp, const int* ci, const int* diag, const double* a, double* lu,
+             int* ticket, int* err, int* werr, unsigned long long limit) {
+  __shared__ int s_c;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  while (true) {
+    if (tid == 0) s_c = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int c = s_c;
+    __syncthreads();
+    if (c >= nranges) break;
+    const int r0 = c * S, r1 = min(n, r0 + S);
+    const int sb = segbase[c], ns = segbase[c + 1] - sb;
+    for (int lvl = 0; lvl < ns; ++lvl) {
+      const int t0 = seg[sb + lvl], t1 = seg[sb + lvl + 1];
+      for (int t = t0 + tid; t < t1; t += nt) {
+        const int i = rows[t];
+        const int end = rp[i + 1], di = diag[i];
+        double d = a[di];  // the row's own diagonal (its slot holds the sentinel)
+        for (int p = rp[i]; p < di; ++p) {
+          const int k = ci[p];
+          const int dk = diag[k];
+          double dkk;
+          if (k >= r0 && k < r1) {
+            dkk = lu[dk];
+          } else {
+            dkk = wait_ready<double>(lu + dk, load_raw<double>(lu + dk), werr, limit);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // row k's entries after its flag
+          }
+          const double lik = lu[p] / dkk;
+          lu[p] = lik;
+          int q = p + 1, b = dk + 1;
+          const int bend = rp[k + 1];
+          while (q < end && b < bend) {
+            const int cq = ci[q], cb = ci[b];
+            if (cq == cb) {
+              const double u = lu[b];
+              if (q == di) d = __builtin_fma(-lik, u, d);
+              else lu[q] = __builtin_fma(-lik, u, lu[q]);
+              ++q;
+              ++b;
+            } else if (cq < cb) {
+              ++q;
+            } else {
+              ++b;
+            }
+          }
+        }
+        if (!(d > 0.0)) atomicOr(err, 1);
+        __threadfence();  // the row's other entries before its diagonal
+        store_ready<double>(lu + di, d);
+      }
+      __syncthreads();  // this level's rows before the next level reads them
+    }
+  }
+}
+
 // x[t] = v[rows[t]]: a sweep's input in sweep order
 template <class T>
 __global__ void k_gather(int n, const int* rows, const T* v, T* x) {
@@ -662,13 +737,30 @@ void build_ilu(Handle* h) {
   h->ilu.reset(&h->alloc, h->nnz);
   HIPX(hipMemcpyAsync(h->ilu, h->val.get(), h->nnz * sizeof(double), hipMemcpyDeviceToDevice,
                       h->stream));
-  for (int L = 0; L < h->lvl_lo.count(); ++L) {
-    int r0 = h->lvl_lo.ptr[L], r1 = h->lvl_lo.ptr[L + 1];
-    LAUNCH(h, "ilu_factor", k_ilu_rows, blocks_for(r1 - r0, kT), kT, 0, h->lvl_lo.rows.get(), r0,
-           r1, h->rp.get(), h->ci.get(), h->diag.get(), h->ilu.get(), err.get());
+  if (h->rng_lo.nranges > 0) {  // one launch on the range schedule
+    const Ranges& L = h->rng_lo;
+    DBuf<int> ticket(&h->alloc, 2);  // the ticket, then the wait error word
+    HIPX(hipMemsetAsync(ticket, 0, 2 * sizeof(int), h->stream));
+    LAUNCH(h, "ilu_factor", k_diag_arm, blocks_for(n, kT), kT, 0, n, h->diag.get(),
+           h->ilu.get());
+    LAUNCH(h, "ilu_factor", k_ilu_ranges, std::min(L.nranges, 2048), 256, 0, n, L.S, L.nranges,
+           L.rows.get(), L.seg.get(), L.segbase.get(), h->rp.get(), h->ci.get(), h->diag.get(),
+           h->val.get(), h->ilu.get(), ticket.get(), err.get(), ticket.get() + 1, wait_limit(h));
+    int we = 0;
+    HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipMemcpyAsync(&we, ticket.get() + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    FAMS_REQUIRE(e != 0 || we == 0, FAMS_ERR_DEVICE,
+                 "ILU(0) factorisation: a dependency wait exceeded its bound");
+  } else {
+    for (int L = 0; L < h->lvl_lo.count(); ++L) {
+      int r0 = h->lvl_lo.ptr[L], r1 = h->lvl_lo.ptr[L + 1];
+      LAUNCH(h, "ilu_factor", k_ilu_rows, blocks_for(r1 - r0, kT), kT, 0, h->lvl_lo.rows.get(),
+             r0, r1, h->rp.get(), h->ci.get(), h->diag.get(), h->ilu.get(), err.get());
+    }
+    HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
   }
-  HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIPX(hipStreamSynchronize(h->stream));
   FAMS_REQUIRE(e == 0, FAMS_ERR_ZERO_PIVOT_ILU, "non-positive ILU(0) pivot");
   pt.mark("ilu factor");
   if (h->precision == FAMS_PREC_MIXED) {
