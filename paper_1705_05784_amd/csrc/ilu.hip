@@ -556,43 +556,56 @@ unsigned long long wait_limit(Handle* h) {
 
 namespace {
 
-void levels(Handle* h, int upper, Levels* out, std::vector<int>* host_lev) {
+// dependency levels of both triangles: the two dataflow launches run side by
+// side (they share nothing), then each level array is sorted into a schedule
+void levels_both(Handle* h, Levels* outs[2], std::vector<int>* host_levs[2]) {
   const int n = h->n;
   unsigned g = blocks_for(n, kT);
-  DBuf<int> lev(&h->alloc, n), flags(&h->alloc, 2);
-  HIPX(hipMemsetAsync(lev, 0xFF, n * sizeof(int), h->stream));   // -1: not known yet
-  HIPX(hipMemsetAsync(flags, 0, 2 * sizeof(int), h->stream));     // ticket, error
+  DBuf<int> lev[2] = {DBuf<int>(&h->alloc, n), DBuf<int>(&h->alloc, n)};
+  DBuf<int> flags(&h->alloc, 4);  // per triangle: ticket, error
+  for (int u = 0; u < 2; ++u)
+    HIPX(hipMemsetAsync(lev[u], 0xFF, n * sizeof(int), h->stream));  // -1: not known yet
+  HIPX(hipMemsetAsync(flags, 0, 4 * sizeof(int), h->stream));
   const int groups = std::min<int>((n + 255) / 256, 1024);
-  if (upper)
-    LAUNCH(h, "ilu_levels", k_levels_df<true>, groups, 256, 0, n, h->rp.get(), h->ci.get(),
-           h->diag.get(), lev.get(), flags.get(), flags.get() + 1, wait_limit(h));
-  else
-    LAUNCH(h, "ilu_levels", k_levels_df<false>, groups, 256, 0, n, h->rp.get(), h->ci.get(),
-           h->diag.get(), lev.get(), flags.get(), flags.get() + 1, wait_limit(h));
-  int e = 0;
-  HIPX(hipMemcpyAsync(&e, flags.get() + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIPX(hipStreamSynchronize(h->stream));
-  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "ILU level computation did not complete");
-  DBuf<int> iota(&h->alloc, n), keys(&h->alloc, n);
-  out->rows.reset(&h->alloc, n);
-  LAUNCH(h, "iota", k_iota, g, kT, 0, n, iota.get());
-  int maxlev = 0;
   {
-    std::vector<int>& hl = *host_lev;
-    hl.resize(n);
-    HIPX(hipMemcpyAsync(hl.data(), lev.get(), n * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPX(hipStreamSynchronize(h->stream));
-    for (int v : hl) maxlev = std::max(maxlev, v);
+    Fork fork(h);
+    hipStream_t s0 = fork.next(), s1 = fork.next();
+    LAUNCH_ON(h, s0, "ilu_levels", k_levels_df<false>, groups, 256, 0, n, h->rp.get(),
+              h->ci.get(), h->diag.get(), lev[0].get(), flags.get(), flags.get() + 1,
+              wait_limit(h));
+    LAUNCH_ON(h, s1, "ilu_levels", k_levels_df<true>, groups, 256, 0, n, h->rp.get(),
+              h->ci.get(), h->diag.get(), lev[1].get(), flags.get() + 2, flags.get() + 3,
+              wait_limit(h));
+    fork.join();
   }
-  int bits = 1;
-  while ((1 << bits) <= maxlev) ++bits;
-  sort_pairs_i32(h, lev, keys, iota, out->rows, n, bits);
-  DBuf<int> ptr(&h->alloc, maxlev + 2);
-  LAUNCH(h, "level_ptr", k_level_ptr, g, kT, 0, n, keys.get(), ptr.get());
-  out->ptr.assign(maxlev + 2, 0);
-  HIPX(hipMemcpyAsync(out->ptr.data(), ptr.get(), (maxlev + 2) * sizeof(int),
-                      hipMemcpyDeviceToHost, h->stream));
+  int hf[4] = {0, 0, 0, 0};
+  HIPX(hipMemcpyAsync(hf, flags.get(), sizeof(hf), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
+  FAMS_REQUIRE(hf[1] == 0 && hf[3] == 0, FAMS_ERR_DEVICE, "ILU level computation did not complete");
+  for (int u = 0; u < 2; ++u) {
+    Levels* out = outs[u];
+    DBuf<int> iota(&h->alloc, n), keys(&h->alloc, n);
+    out->rows.reset(&h->alloc, n);
+    LAUNCH(h, "iota", k_iota, g, kT, 0, n, iota.get());
+    int maxlev = 0;
+    {
+      std::vector<int>& hl = *host_levs[u];
+      hl.resize(n);
+      HIPX(hipMemcpyAsync(hl.data(), lev[u].get(), n * sizeof(int), hipMemcpyDeviceToHost,
+                          h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+      for (int v : hl) maxlev = std::max(maxlev, v);
+    }
+    int bits = 1;
+    while ((1 << bits) <= maxlev) ++bits;
+    sort_pairs_i32(h, lev[u], keys, iota, out->rows, n, bits);
+    DBuf<int> ptr(&h->alloc, maxlev + 2);
+    LAUNCH(h, "level_ptr", k_level_ptr, g, kT, 0, n, keys.get(), ptr.get());
+    out->ptr.assign(maxlev + 2, 0);
+    HIPX(hipMemcpyAsync(out->ptr.data(), ptr.get(), (maxlev + 2) * sizeof(int),
+                        hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+  }
 }
 
 __global__ void k_d2f_ilu(int64_t n, const double* a, float* b) {
@@ -722,8 +735,11 @@ void build_ilu(Handle* h) {
   if (!h->smoother) return;
   PhaseTimer pt(h->stream);
   std::vector<int> lev_lo, lev_up;
-  levels(h, 0, &h->lvl_lo, &lev_lo);
-  levels(h, 1, &h->lvl_up, &lev_up);
+  {
+    Levels* outs[2] = {&h->lvl_lo, &h->lvl_up};
+    std::vector<int>* hls[2] = {&lev_lo, &lev_up};
+    levels_both(h, outs, hls);
+  }
   pt.mark("ilu levels");
   chunk_table(h, &h->lvl_lo);
   chunk_table(h, &h->lvl_up);
