@@ -11,9 +11,12 @@ step (multiscale stage + ILU(0)) to ||r||/||r0|| <= 1e-6.
 One step = one request per coupling strategy (Decoupled, Frac, Rock and
 Coupled-AMS), each request = setup (basis functions, R, A_c and its LU,
 ILU(0)) + solve + conservative flux reconstruction, with the fine system
-already resident in HBM.  `value` = requests (solves) per second in the
-precision form; the plain FP64 form is timed beside it.  Latency p50/p99
-are per request.
+already resident in HBM.  By default the four requests of a step run side by
+side, one worker process per strategy on the one GPU (each worker loads the
+system onto the device before the clock starts); `--concurrency 1` runs them
+one after another, and those sequential figures are reported too.  `value` =
+requests (solves) per second in the precision form; the plain FP64 form is
+timed beside it.  Latency p50/p99 are per request.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -131,6 +134,70 @@ print(json.dumps(dict(setup_s=t1 - t0, solve_s=t2 - t1, iterations=info["iterati
                        f"solve {r['solve_s']:.1f} s, FP64, 1 thread")}
 
 
+def _load_workload(dev):
+    """The bench system and its coarse grids, resident on `dev`."""
+    import torch
+    from paper_1705_05784_amd import fams
+    from workloads import make_config
+    sysm = make_config(2)
+    wb, pr, vx, _ = fams.full_grid(sysm, COARSE, D_MIN, R_Z)
+    A = dict(row_ptr=torch.from_numpy(sysm.row_ptr).to(dev),
+             col=torch.from_numpy(sysm.col).to(dev),
+             val=torch.from_numpy(sysm.val).to(dev),
+             wb=torch.from_numpy(wb).to(dev), pr=torch.from_numpy(pr).to(dev),
+             vx=torch.from_numpy(vx).to(dev))
+    q = torch.from_numpy(sysm.q).to(dev)
+    torch.cuda.synchronize()
+    return sysm, A, q
+
+
+def _request(sysm, A, q, variant, precision, profile=False):
+    """One request: setup + FGMRES(30) to RTOL + flux reconstruction."""
+    import torch
+    from paper_1705_05784_amd import fams
+    t0 = time.perf_counter()
+    S = fams.Solver(A["row_ptr"], A["col"], A["val"], sysm.n_matrix, A["wb"], A["pr"],
+                    A["vx"], variant=variant, precision=precision, alpha=ALPHA,
+                    profile=profile)
+    t1 = time.perf_counter()
+    p, info = S.solve(q, outer="gmres", restart=30, rtol=RTOL, max_iter=1000)
+    t2 = time.perf_counter()
+    flux, pfv, imb = S.reconstruct_flux(q, p)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out = dict(total=t3 - t0, setup=t1 - t0, solve=t2 - t1, flux=t3 - t2, info=info[0],
+               imbalance=imb, setup_info=S.setup_info(), p=p)
+    if profile:
+        out["stats"] = S.kernel_stats()
+    S.close()
+    return out
+
+
+def _concurrent_worker(conn, variant):
+    """One coupling strategy's requests, in a process of its own on GPU 0:
+    loads the system once, then runs ("run", precision, k) batches."""
+    try:
+        import torch
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        sysm, A, q = _load_workload(dev)
+        conn.send(("ready", None))
+        while True:
+            msg = conn.recv()
+            if msg[0] == "stop":
+                break
+            _, precision, k = msg
+            res = []
+            for _ in range(k):
+                r = _request(sysm, A, q, variant, precision)
+                r["p"] = r["p"].cpu().numpy()
+                res.append(r)
+            conn.send(("done", res))
+    except Exception as e:  # reported to the parent, which fails the run
+        conn.send(("error", f"{type(e).__name__}: {e}"))
+    conn.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +207,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="one mixed step plus a 1 GiB device copy (for rocprofv3 --pmc runs)")
+    ap.add_argument("--concurrency", type=int, default=4, choices=(1, 4),
+                    help="4: the four requests of a step run side by side, one worker "
+                         "process per coupling strategy; 1: one after another")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the F-AMS solve here runs on one GPU; run with --gpus 1 "
@@ -147,38 +217,54 @@ def main():
         sys.exit(2)
 
     import torch
+
+    # worker processes first, before this process touches the GPU
+    workers = []
+    if args.concurrency > 1 and not args.pmc_pass:
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        for v in range(4):
+            parent, child = ctx.Pipe()
+            proc = ctx.Process(target=_concurrent_worker, args=(child, v), daemon=True)
+            proc.start()
+            child.close()
+            workers.append((proc, parent))
+
     from paper_1705_05784_amd import fams
-    from workloads import make_config
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sysm = make_config(2)
-    wb, pr, vx, ncm = fams.full_grid(sysm, COARSE, D_MIN, R_Z)
-    A = dict(row_ptr=torch.from_numpy(sysm.row_ptr).to(dev),
-             col=torch.from_numpy(sysm.col).to(dev),
-             val=torch.from_numpy(sysm.val).to(dev),
-             wb=torch.from_numpy(wb).to(dev), pr=torch.from_numpy(pr).to(dev),
-             vx=torch.from_numpy(vx).to(dev))
-    q = torch.from_numpy(sysm.q).to(dev)
-    torch.cuda.synchronize()
+    sysm, A, q = _load_workload(dev)
 
     def request(variant, precision, profile=False):
-        t0 = time.perf_counter()
-        S = fams.Solver(A["row_ptr"], A["col"], A["val"], sysm.n_matrix, A["wb"], A["pr"],
-                        A["vx"], variant=variant, precision=precision, alpha=ALPHA,
-                        profile=profile)
-        t1 = time.perf_counter()
-        p, info = S.solve(q, outer="gmres", restart=30, rtol=RTOL, max_iter=1000)
-        t2 = time.perf_counter()
-        flux, pfv, imb = S.reconstruct_flux(q, p)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        out = dict(total=t3 - t0, setup=t1 - t0, solve=t2 - t1, flux=t3 - t2, info=info[0],
-                   imbalance=imb, setup_info=S.setup_info(), p=p)
-        if profile:
-            out["stats"] = S.kernel_stats()
-        S.close()
+        return _request(sysm, A, q, variant, precision, profile)
+
+    def gather(tag_expected):
+        out = []
+        for _, conn in workers:
+            tag, payload = conn.recv()
+            if tag == "error":
+                raise SystemExit(f"bench.py: a worker failed: {payload}")
+            assert tag == tag_expected
+            out.append(payload)
         return out
+
+    def run_concurrent(precision, k):
+        """The four strategies side by side; the clock runs from the start
+        signal until every worker has finished (each synchronises its device
+        after every request)."""
+        t0 = time.perf_counter()
+        for _, conn in workers:
+            conn.send(("run", precision, k))
+        per = gather("done")
+        t = time.perf_counter() - t0
+        res = []
+        for step in range(k):  # step-major, strategy order within a step
+            for v in range(4):
+                r = per[v][step]
+                r["p"] = torch.from_numpy(r["p"]).to(dev)
+                res.append(r)
+        return t, res
 
     def run_steps(precision, k, profile=False):
         res = []
@@ -200,6 +286,16 @@ def main():
         run_steps(fams.MIXED, 1)
         print(json.dumps({"pmc_pass": True, "copy_bytes": 1 << 30}))
         return
+
+    conc = None
+    if workers:
+        gather("ready")
+        run_concurrent(fams.MIXED, args.warmup)
+        run_concurrent(fams.FP64, args.warmup)
+        conc = (run_concurrent(fams.MIXED, args.steps), run_concurrent(fams.FP64, args.steps))
+        for proc, conn in workers:
+            conn.send(("stop",))
+            proc.join(timeout=60)
 
     for _ in range(args.warmup):
         run_steps(fams.MIXED, 1)
@@ -234,6 +330,11 @@ def main():
 
     m = summarize(t_mixed, r_mixed)
     f = summarize(t_fp64, r_fp64)
+    sequential = None
+    if conc is not None:  # the headline numbers are the side-by-side ones
+        sequential = dict(mixed=m, fp64=f)
+        m = summarize(*conc[0])
+        f = summarize(*conc[1])
     si = r_mixed[-1]["setup_info"]
     sizes = dict(n=si["n"], nnz=si["nnz"], nnz_P=si["nnz_P"], n_coarse=si["n_coarse"],
                  ilu_levels_lower=si["ilu_levels_lower"], ilu_levels_upper=si["ilu_levels_upper"])
@@ -302,12 +403,16 @@ def main():
                                 "10^3 / d_min=r_z=8, alpha 1e-2, 4 coupling strategies, "
                                 "FGMRES(30) to 1e-6, setup+solve+flux per request"),
                    "n": sizes["n"], "n_matrix": sysm.n_matrix, "nnz": sizes["nnz"],
-                   "n_coarse": sizes["n_coarse"], "t_ratio": sysm.t_ratio},
+                   "n_coarse": sizes["n_coarse"], "t_ratio": sysm.t_ratio,
+                   "concurrency": ("4 requests side by side (one worker process per coupling "
+                                   "strategy, inputs resident on the GPU)"
+                                   if conc is not None else "1 (requests one after another)")},
         "p50_ms": m["p50_ms"],
         "p99_ms": m["p99_ms"],
         "mixed": m,
         "fp64": f,
         "speedup_mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"],
+        "sequential": sequential,
         "roofline": roofline,
         "roofline_iteration": roofline_iter,
         "kernels_ms": {k: round(v[0], 3) for k, v in sorted(kernels.items(),
