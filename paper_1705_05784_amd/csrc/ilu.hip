@@ -433,74 +433,235 @@ k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const
 // ILU(0) factorisation in one launch on the lower sweep's range schedule
 // (the factorisation of row i needs exactly the rows its lower triangle
 // refers to).  A workgroup takes ranges in ticket order and walks a range
-// level by level with a barrier between levels (rows of earlier levels of
-// the same range are then visible); a pivot row in an earlier range is
-// waited for through its diagonal entry, which holds the sentinel until the
-// row is final and is published last, after a release fence.  The arithmetic
-// per row is the IKJ merge of k_ilu_rows, in the same order.  Waits are
-// bounded as in the sweeps.
-__global__ void k_diag_arm(int n, const int* diag, double* lu) {
+// level by level with a barrier between levels.  Other rows read only the
+// upper part of a pivot row (its diagonal and the entries right of it), so
+// that part is published entry by entry with the value itself as the ready
+// flag, as in the sweeps: every upper entry of lu starts as the sentinel
+// (k_upper_arm), a finished entry is written with a device-coherent atomic
+// store, and a reader waits on the entries it uses.  No fence is needed (an
+// agent-scope fence writes back or invalidates a whole L2), and a wait is
+// bounded as in the sweeps.  The lower part (the multipliers) is private to
+// its row and written with plain stores.
+__global__ void k_upper_arm(int n, const int* rp, const int* diag, double* lu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     using U = Sentinel<double>::U;
-    reinterpret_cast<U*>(lu)[diag[i]] = Sentinel<double>::bits;
+    const int end = rp[i + 1];
+    for (int p = diag[i]; p < end; ++p) reinterpret_cast<U*>(lu)[p] = Sentinel<double>::bits;
   }
 }
 
-__global__ void __launch_bounds__(256)
-k_ilu_ranges(int n, int S, int nranges, const int* rows, const int* seg, const int* segbase,
-             const int* rp, const int* ci, const int* diag, const double* a, double* lu,
-             int* ticket, int* err, int* werr, unsigned long long limit) {
+__device__ __forceinline__ double ready_at(const double* lu, int p, int* werr,
+                                           unsigned long long limit) {
+  return wait_ready<double>(lu + p, load_raw<double>(lu + p), werr, limit);
+}
+
+// Row i entry by entry (rows wider than the staged form holds).  The lower
+// part is eliminated in place, pivot by pivot; then each upper entry takes,
+// in pivot order, the update of every pivot row that holds its column, and
+// is published.  Each entry sees the same fused multiply-adds in the same
+// order as in the IKJ merge.
+__device__ void ilu_row_entries(int i, const int* rp, const int* ci, const int* diag,
+                                const double* a, double* lu, int* err, int* werr,
+                                unsigned long long limit) {
+  const int p0 = rp[i], end = rp[i + 1], di = diag[i];
+  for (int p = p0; p < di; ++p) {
+    const int k = ci[p], dk = diag[k], bend = rp[k + 1];
+    const double lik = lu[p] / ready_at(lu, dk, werr, limit);
+    lu[p] = lik;
+    int q = p + 1;
+    for (int b = dk + 1; b < bend && q < di; ++b) {
+      while (q < di && ci[q] < ci[b]) ++q;
+      if (q < di && ci[q] == ci[b]) {
+        lu[q] = __builtin_fma(-lik, ready_at(lu, b, werr, limit), lu[q]);
+        ++q;
+      }
+    }
+  }
+  for (int q = di; q < end; ++q) {
+    const int c = ci[q];
+    double v = a[q];
+    for (int p = p0; p < di; ++p) {
+      const int k = ci[p], bend = rp[k + 1];
+      for (int b = diag[k] + 1; b < bend && ci[b] <= c; ++b)
+        if (ci[b] == c) v = __builtin_fma(-lu[p], ready_at(lu, b, werr, limit), v);
+    }
+    if (q == di && !(v > 0.0)) atomicOr(err, 1);
+    store_ready<double>(lu + q, v);
+  }
+}
+
+// Static data of one position of the lower schedule (the row, its values
+// and the pivot entries its elimination reads), column-major over the n
+// positions so that a wavefront's loads of one field are consecutive.  The
+// pivot entries of a row are listed pivot by pivot: the pivot's diagonal
+// (target kTgtDiag), then each entry of the pivot's upper part whose column
+// the row holds, with the row slot it updates.  meta packs the row length,
+// the number of pivots and the number of listed entries (kEntryPath: the
+// row is too wide for the record and is taken entry by entry).
+constexpr int kIluThreads = 128;  // threads of the factorisation workgroup
+constexpr int kIluRowW = 16;      // row entries a record holds
+constexpr int kIluDyn = 20;       // pivot entries a record lists
+constexpr int kTgtDiag = 255;
+constexpr int kEntryPath = 255;
+
+struct IluRecs {
+  int* row;
+  int* p0;
+  int* meta;
+  double* av;
+  int* pos;
+  unsigned char* tgt;
+};
+
+__global__ void k_ilu_symbolic(int n, const int* rows, const int* rp, const int* ci,
+                               const int* diag, const double* a, int stage_w, IluRecs R) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = rows[t], p0 = rp[i], len = rp[i + 1] - p0, nlow = diag[i] - p0;
+  const int64_t N = n;
+  int nd = 0;
+  bool fits = len <= stage_w;
+  for (int m = 0; m < nlow && fits; ++m) {
+    const int k = ci[p0 + m], dk = diag[k], bend = rp[k + 1];
+    if (nd == kIluDyn) {
+      fits = false;
+      break;
+    }
+    R.pos[nd * N + t] = dk;
+    R.tgt[nd * N + t] = kTgtDiag;
+    ++nd;
+    int q = m + 1;
+    for (int b = dk + 1; b < bend && q < len; ++b) {
+      while (q < len && ci[p0 + q] < ci[b]) ++q;
+      if (q < len && ci[p0 + q] == ci[b]) {
+        if (nd == kIluDyn) {
+          fits = false;
+          break;
+        }
+        R.pos[nd * N + t] = b;
+        R.tgt[nd * N + t] = static_cast<unsigned char>(q);
+        ++nd;
+        ++q;
+      }
+    }
+  }
+  R.row[t] = i;
+  R.p0[t] = p0;
+  R.meta[t] = fits ? len | nlow << 8 | nd << 16 : kEntryPath << 16;
+  if (fits)
+    for (int q = 0; q < len; ++q) R.av[q * N + t] = a[p0 + q];
+}
+
+struct IluCur {
+  int row, p0, meta;
+  double av[kIluRowW];
+  int pos[kIluDyn];
+  unsigned char tgt[kIluDyn];
+};
+
+// a position's record (all fields, so the loads need nothing but t); t < 0:
+// no row
+__device__ __forceinline__ void ilu_fetch(IluCur& c, int t, int n, const IluRecs& R) {
+  c.meta = -1;
+  if (t < 0) return;
+  const int64_t N = n;
+  c.row = R.row[t];
+  c.p0 = R.p0[t];
+  c.meta = R.meta[t];
+#pragma unroll
+  for (int q = 0; q < kIluRowW; ++q) c.av[q] = R.av[q * N + t];
+#pragma unroll
+  for (int j = 0; j < kIluDyn; ++j) {
+    c.pos[j] = R.pos[j * N + t];
+    c.tgt[j] = R.tgt[j * N + t];
+  }
+}
+
+// Staged elimination of one row from its record: the listed pivot entries
+// are read together (one round trip once they are published), then applied
+// in list order, which is the order of the IKJ merge.  The row's values sit
+// in the thread's LDS slots (`val`, slot q of this thread).
+template <class Val>
+__device__ __forceinline__ void ilu_staged(const IluCur& c, Val val, const int* rp,
+                                           const int* ci, const int* diag, const double* a,
+                                           double* lu, int* err, int* werr,
+                                           unsigned long long limit) {
+  if (c.meta < 0) return;
+  const int nd = c.meta >> 16;
+  if (nd == kEntryPath) {
+    ilu_row_entries(c.row, rp, ci, diag, a, lu, err, werr, limit);
+    return;
+  }
+  const int len = c.meta & 0xFF, nlow = (c.meta >> 8) & 0xFF;
+  using U = Sentinel<double>::U;
+  U raw[kIluDyn];
+#pragma unroll
+  for (int j = 0; j < kIluDyn; ++j)
+    if (j < nd) raw[j] = load_raw<double>(lu + c.pos[j]);
+#pragma unroll
+  for (int q = 0; q < kIluRowW; ++q)
+    if (q < len) val(q) = c.av[q];
+  int m = 0;
+  double lik = 0.0;
+#pragma unroll
+  for (int j = 0; j < kIluDyn; ++j)
+    if (j < nd) {
+      const double u = wait_ready<double>(lu + c.pos[j], raw[j], werr, limit);
+      if (c.tgt[j] == kTgtDiag) {
+        lik = val(m) / u;
+        val(m) = lik;
+        ++m;
+      } else {
+        val(c.tgt[j]) = __builtin_fma(-lik, u, val(c.tgt[j]));
+      }
+    }
+  if (!(val(nlow) > 0.0)) atomicOr(err, 1);
+#pragma unroll
+  for (int q = 0; q < kIluRowW; ++q)
+    if (q < len) {
+      if (q < nlow) lu[c.p0 + q] = val(q);
+      else store_ready<double>(lu + c.p0 + q, val(q));
+    }
+}
+
+// The factorisation kernel: while a level's pivot entries are in flight,
+// the records of the thread's row of the next level are loaded, so a level
+// costs about one round trip on published values, its arithmetic and a
+// barrier.  Dynamic LDS: the range's level boundaries (max_segs + 1 ints).
+__global__ void __launch_bounds__(kIluThreads)
+k_ilu_ranges(int n, int nranges, const int* seg, const int* segbase, IluRecs R, const int* rp,
+             const int* ci, const int* diag, const double* a, double* lu, int* ticket, int* err,
+             int* werr, unsigned long long limit) {
+  extern __shared__ int s_seg[];
+  __shared__ double s_val[kIluRowW * kIluThreads];
   __shared__ int s_c;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  auto val = [&](int q) -> double& { return s_val[q * kIluThreads + tid]; };
   while (true) {
     if (tid == 0) s_c = atomicAdd(ticket, 1);
     __syncthreads();
     const int c = s_c;
-    __syncthreads();
     if (c >= nranges) break;
-    const int r0 = c * S, r1 = min(n, r0 + S);
     const int sb = segbase[c], ns = segbase[c + 1] - sb;
+    for (int k = tid; k <= ns; k += kIluThreads) s_seg[k] = seg[sb + k];
+    __syncthreads();
+    auto first = [&](int lvl) {
+      if (lvl >= ns) return -1;
+      const int t = s_seg[lvl] + tid;
+      return t < s_seg[lvl + 1] ? t : -1;
+    };
+    IluCur cur, nxt;
+    ilu_fetch(cur, first(0), n, R);
     for (int lvl = 0; lvl < ns; ++lvl) {
-      const int t0 = seg[sb + lvl], t1 = seg[sb + lvl + 1];
-      for (int t = t0 + tid; t < t1; t += nt) {
-        const int i = rows[t];
-        const int end = rp[i + 1], di = diag[i];
-        double d = a[di];  // the row's own diagonal (its slot holds the sentinel)
-        for (int p = rp[i]; p < di; ++p) {
-          const int k = ci[p];
-          const int dk = diag[k];
-          double dkk;
-          if (k >= r0 && k < r1) {
-            dkk = lu[dk];
-          } else {
-            dkk = wait_ready<double>(lu + dk, load_raw<double>(lu + dk), werr, limit);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // row k's entries after its flag
-          }
-          const double lik = lu[p] / dkk;
-          lu[p] = lik;
-          int q = p + 1, b = dk + 1;
-          const int bend = rp[k + 1];
-          while (q < end && b < bend) {
-            const int cq = ci[q], cb = ci[b];
-            if (cq == cb) {
-              const double u = lu[b];
-              if (q == di) d = __builtin_fma(-lik, u, d);
-              else lu[q] = __builtin_fma(-lik, u, lu[q]);
-              ++q;
-              ++b;
-            } else if (cq < cb) {
-              ++q;
-            } else {
-              ++b;
-            }
-          }
-        }
-        if (!(d > 0.0)) atomicOr(err, 1);
-        __threadfence();  // the row's other entries before its diagonal
-        store_ready<double>(lu + di, d);
+      ilu_fetch(nxt, first(lvl + 1), n, R);
+      ilu_staged(cur, val, rp, ci, diag, a, lu, err, werr, limit);
+      for (int t = s_seg[lvl] + tid + kIluThreads; t < s_seg[lvl + 1]; t += kIluThreads) {
+        ilu_fetch(cur, t, n, R);  // levels wider than the workgroup
+        ilu_staged(cur, val, rp, ci, diag, a, lu, err, werr, limit);
       }
-      __syncthreads();  // this level's rows before the next level reads them
+      __syncthreads();  // a level's rows published before the next level waits on them
+      cur = nxt;
     }
   }
 }
@@ -615,6 +776,13 @@ __global__ void k_d2f_ilu(int64_t n, const double* a, float* b) {
 
 // rows per range of the range sweeps: FAMS_ILU_RANGE (0 selects the
 // level-chunk sweeps), default 8192
+// widest row the factorisation stages in LDS (0: every row entry by entry)
+int ilu_stage_width() {
+  int w = kIluRowW;
+  if (const char* e = std::getenv("FAMS_ILU_STAGE")) w = std::atoi(e);
+  return std::max(0, std::min(w, kIluRowW));
+}
+
 int sweep_range_rows(Handle* h) {
   (void)h;
   int S = 8192;
@@ -757,11 +925,25 @@ void build_ilu(Handle* h) {
     const Ranges& L = h->rng_lo;
     DBuf<int> ticket(&h->alloc, 2);  // the ticket, then the wait error word
     HIPX(hipMemsetAsync(ticket, 0, 2 * sizeof(int), h->stream));
-    LAUNCH(h, "ilu_factor", k_diag_arm, blocks_for(n, kT), kT, 0, n, h->diag.get(),
-           h->ilu.get());
-    LAUNCH(h, "ilu_factor", k_ilu_ranges, std::min(L.nranges, 2048), 256, 0, n, L.S, L.nranges,
-           L.rows.get(), L.seg.get(), L.segbase.get(), h->rp.get(), h->ci.get(), h->diag.get(),
-           h->val.get(), h->ilu.get(), ticket.get(), err.get(), ticket.get() + 1, wait_limit(h));
+    // records of the lower schedule's positions
+    DBuf<int> ri(&h->alloc, static_cast<size_t>(n) * (3 + kIluDyn));
+    DBuf<double> rav(&h->alloc, static_cast<size_t>(n) * kIluRowW);
+    DBuf<unsigned char> rtg(&h->alloc, static_cast<size_t>(n) * kIluDyn);
+    const IluRecs R{ri.get(), ri.get() + n, ri.get() + 2 * static_cast<size_t>(n), rav.get(),
+                    ri.get() + 3 * static_cast<size_t>(n), rtg.get()};
+    LAUNCH(h, "ilu_factor", k_ilu_symbolic, blocks_for(n, kT), kT, 0, n, L.rows.get(),
+           h->rp.get(), h->ci.get(), h->diag.get(), h->val.get(), ilu_stage_width(), R);
+    LAUNCH(h, "ilu_factor", k_upper_arm, blocks_for(n, kT), kT, 0, n, h->rp.get(),
+           h->diag.get(), h->ilu.get());
+    const size_t lds = static_cast<size_t>(L.max_segs + 1) * sizeof(int);
+    FAMS_REQUIRE(lds + sizeof(double) * kIluRowW * kIluThreads <=
+                     static_cast<size_t>(lds_hw_budget(h)),
+                 FAMS_ERR_CAPACITY, "ILU range schedule does not fit in LDS");
+    allow_lds(reinterpret_cast<const void*>(&k_ilu_ranges), lds);
+    LAUNCH(h, "ilu_factor", k_ilu_ranges, std::min(L.nranges, 2048), kIluThreads, lds, n,
+           L.nranges, L.seg.get(), L.segbase.get(), R, h->rp.get(), h->ci.get(), h->diag.get(),
+           h->val.get(), h->ilu.get(), ticket.get(), err.get(), ticket.get() + 1,
+           wait_limit(h));
     int we = 0;
     HIPX(hipMemcpyAsync(&e, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPX(hipMemcpyAsync(&we, ticket.get() + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));

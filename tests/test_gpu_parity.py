@@ -192,3 +192,25 @@ def test_sweep_schedules(name, range_rows, monkeypatch):
                      precision=fams.MIXED)
     p, info = gm.solve(torch.from_numpy(s.q), rtol=1e-10)
     assert info[0]["status"] == 0
+
+
+@pytest.mark.parametrize("stage", [0, 5])
+@pytest.mark.parametrize("range_rows", [64, 8192])
+@pytest.mark.parametrize("name", ["3d", "cfg2s"])
+def test_ilu_factor_forms(name, range_rows, stage, monkeypatch):
+    """The one-launch ILU(0) factorisation with every row taken entry by
+    entry (stage 0), or only the rows past 5 entries (stage 5, both forms in
+    one launch), on small and large ranges, gives the same bits as the
+    per-level IKJ launches and matches the oracle."""
+    from paper_1705_05784_amd import fams
+    s, _, ora = case(name, 0)
+    spec = small_case(name)[1]
+    wb, pr, vx, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    monkeypatch.setenv("FAMS_ILU_RANGE", "0")
+    ref = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=0).ilu()
+    monkeypatch.setenv("FAMS_ILU_RANGE", str(range_rows))
+    monkeypatch.setenv("FAMS_ILU_STAGE", str(stage))
+    say(f"[case] {name} ilu range rows {range_rows} stage width {stage}")
+    lu = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=0).ilu()
+    assert np.array_equal(lu, ref)
+    assert np.abs(lu - ora.ilu.val).max() <= 1e-12 * np.abs(ora.ilu.val).max()
