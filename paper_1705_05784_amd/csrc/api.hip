@@ -94,6 +94,8 @@ AuxStreams::~AuxStreams() {
     if (join[i]) (void)hipEventDestroy(join[i]);
   }
   if (fork) (void)hipEventDestroy(fork);
+  for (hipEvent_t e : step)
+    if (e) (void)hipEventDestroy(e);
 }
 
 Fork::Fork(Handle* h) : h_(h) {
@@ -104,6 +106,7 @@ Fork::Fork(Handle* h) : h_(h) {
       HIPX(hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking));
       HIPX(hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming));
     }
+    for (hipEvent_t& e : a.step) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   HIPX(hipEventRecord(a.fork, h->stream));
 }

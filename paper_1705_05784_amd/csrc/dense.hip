@@ -285,30 +285,106 @@ k_panel(double* a, int n, int k0, int nb, int* ipiv, int* info) {
 // costs two barriers and no memory traffic; the rows are written back to
 // their final positions at the end.  Pivot choice (first maximal |a| in
 // position order) and every update are the same as in k_panel.
+//
+// With kpn > 0 the kernel first applies the previous panel (columns
+// [k0 - kpn, k0), already factored) to its own columns, as the separate
+// launches would: that panel's interchanges (as a row map built in LDS, so
+// the columns are read once, through it), the unit lower triangular solve
+// for rows [k0 - kpn, k0) (written back: they are rows of U), then
+// the update of rows [k0, n) by L21 U12 while the panel is loaded.
 constexpr int kRegNb = 16;
 constexpr int kRegThreads = 512;
 
 template <int RT>
 __global__ void __launch_bounds__(kRegThreads)
-k_panel_reg(double* a, int n, int k0, int nb, int* ipiv, int* info) {
+k_panel_reg(double* a, int n, int k0, int nb, int* ipiv, int* info, int kpn) {
   __shared__ int at_pos[kRegThreads * RT];
   __shared__ double s_best[kRegThreads / 64];
   __shared__ int s_bpos[kRegThreads / 64];
   __shared__ double s_prow[kRegNb];
+  __shared__ int s_src[kRegThreads * RT + kRegNb];  // row map of [k0 - kpn, n)
+  __shared__ double s_u[kRegNb * kRegNb];           // U12: [row j][column c]
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int m = n - k0;
+  const int m = n - k0, kp0 = k0 - kpn;
+  if (kpn > 0) {
+    for (int l = tid; l < m + kpn; l += kRegThreads) s_src[l] = l;
+    __syncthreads();
+    if (tid == 0) {  // the previous panel's interchanges, in order
+      int pv[kRegNb];
+#pragma clang loop unroll(full)
+      for (int j = 0; j < kRegNb; ++j)
+        if (j < kpn) pv[j] = ipiv[kp0 + j] - kp0;
+#pragma clang loop unroll(full)
+      for (int j = 0; j < kRegNb; ++j)
+        if (j < kpn && pv[j] != j) {
+          const int t = s_src[j];
+          s_src[j] = s_src[pv[j]];
+          s_src[pv[j]] = t;
+        }
+    }
+    __syncthreads();
+  }
+  // every old value is read before the U rows of the previous panel are
+  // written (a row of [k0 - kpn, k0) may be the source of a row below)
+  double x[kRegNb];
+  if (kpn > 0 && tid < nb) {
+    const double* cc = a + static_cast<int64_t>(k0 + tid) * n + kp0;
+#pragma clang loop unroll(full)
+    for (int j = 0; j < kRegNb; ++j) x[j] = j < kpn ? cc[s_src[j]] : 0.0;
+  }
   double v[RT][kRegNb];
   int pos[RT];
 #pragma clang loop unroll(full)
   for (int q = 0; q < RT; ++q) {
     const int r = tid + q * kRegThreads;
     pos[q] = r < m ? r : INT_MAX;
+    const int src = r < m ? (kpn > 0 ? s_src[kpn + r] : r) : 0;
 #pragma clang loop unroll(full)
     for (int c = 0; c < kRegNb; ++c)
-      v[q][c] = (r < m && c < nb) ? a[static_cast<int64_t>(k0 + c) * n + k0 + r] : 0.0;
+      v[q][c] = (r < m && c < nb) ? a[static_cast<int64_t>(k0 + c) * n + kp0 + src] : 0.0;
     if (r < m) at_pos[r] = r;
   }
   __syncthreads();
+  if (kpn > 0) {
+    if (tid < nb) {  // U12 column k0 + tid: unit lower solve with L11
+      const double* l11 = a + static_cast<int64_t>(kp0) * n + kp0;
+#pragma clang loop unroll(full)
+      for (int r = 1; r < kRegNb; ++r)
+        if (r < kpn) {
+          double s = x[r];
+#pragma clang loop unroll(full)
+          for (int t = 0; t < r; ++t) s -= l11[static_cast<int64_t>(t) * n + r] * x[t];
+          x[r] = s;
+        }
+      double* cc = a + static_cast<int64_t>(k0 + tid) * n + kp0;
+#pragma clang loop unroll(full)
+      for (int j = 0; j < kRegNb; ++j)
+        if (j < kpn) {
+          cc[j] = x[j];
+          s_u[j * kRegNb + tid] = x[j];
+        }
+    }
+    __syncthreads();
+#pragma clang loop unroll(full)
+    for (int q = 0; q < RT; ++q) {
+      const int r = tid + q * kRegThreads;
+      if (r < m) {
+        double l[kRegNb];
+#pragma clang loop unroll(full)
+        for (int j = 0; j < kRegNb; ++j)
+          l[j] = j < kpn ? a[static_cast<int64_t>(kp0 + j) * n + k0 + r] : 0.0;
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kRegNb; ++c) {
+          if (c >= nb) continue;
+          double acc = 0.0;
+#pragma clang loop unroll(full)
+          for (int j = 0; j < kRegNb; ++j)
+            if (j < kpn) acc += l[j] * s_u[j * kRegNb + c];
+          v[q][c] -= acc;
+        }
+      }
+    }
+  }
 #pragma clang loop unroll(full)
   for (int j = 0; j < kRegNb; ++j) {
     if (j < nb) {
@@ -413,19 +489,21 @@ __global__ void k_trsm_lower_unit(const double* l, int n, int k0, int nb, double
   for (int r = 0; r < nb; ++r) col[r] = x[r];
 }
 
-// the panel's row interchanges applied to every column outside the panel,
-// then, for the columns after it, B[k0:k0+nb, c] <- L11^{-1} B[...] (unit
-// lower L11 of the factored panel); one thread per column
-__global__ void k_swap_trsm(double* a, int n, int k0, int nb, const int* ipiv) {
+// the panel's row interchanges applied to the columns [lo1, lo1 + n1) and
+// [lo2, lo2 + n2) (none of them in the panel), then, for those after the
+// panel, B[k0:k0+nb, c] <- L11^{-1} B[...] (unit lower L11 of the factored
+// panel); one thread per column
+__global__ void k_swap_trsm(double* a, int n, int k0, int nb, const int* ipiv, int lo1, int n1,
+                            int lo2, int n2) {
   __shared__ double L[kNb * kNb];
   for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
     int r = t % nb, c = t / nb;
     L[t] = a[static_cast<int64_t>(k0 + c) * n + k0 + r];
   }
   __syncthreads();
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k0) c += nb;  // skip the panel's own columns
-  if (c >= n) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n1 + n2) return;
+  const int c = t < n1 ? lo1 + t : lo2 + (t - n1);
   double* cc = a + static_cast<int64_t>(c) * n;
   for (int j = k0; j < k0 + nb; ++j) {
     int p = ipiv[j];
@@ -540,10 +618,10 @@ __global__ void k_gemv_reduce(int n, int nchunks, const double* part, double* y)
 }
 
 void gemm_sub(Handle* h, int m, int p, int k, const double* A, const double* B, double* C,
-              int ld) {
+              int ld, hipStream_t st = nullptr) {
   if (m <= 0 || p <= 0 || k <= 0) return;
   dim3 grid(blocks_for(m, 64), blocks_for(p, 64));
-  LAUNCH(h, "gemm_f64", k_gemm_sub, grid, 256, 0, m, p, k, A, B, C, ld);
+  LAUNCH_ON(h, st ? st : h->stream, "gemm_f64", k_gemm_sub, grid, 256, 0, m, p, k, A, B, C, ld);
 }
 
 // ---- FP64 MFMA GEMM ----------------------------------------------------------
@@ -824,31 +902,69 @@ void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const do
 void lu_factor(Handle* h, double* a, int n, int* perm_out) {
   DBuf<int> ipiv(&h->alloc, n), info(&h->alloc, 1);
   HIPX(hipMemsetAsync(info, 0, sizeof(int), h->stream));
-  for (int k0 = 0; k0 < n;) {
+  // panels of at most 4 * 512 rows live in registers (16 columns), larger
+  // ones are factored in place (32 columns)
+  auto width = [&](int k0) {
     const int m = n - k0;
-    // panels of at most 4 * 512 rows live in registers (16 columns), larger
-    // ones are factored in place (32 columns)
-    int nb;
-    if (m <= 4 * kRegThreads) {
-      nb = std::min(kRegNb, m);
-      if (m <= kRegThreads)
-        LAUNCH(h, "lu_panel", k_panel_reg<1>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(), info.get());
-      else if (m <= 2 * kRegThreads)
-        LAUNCH(h, "lu_panel", k_panel_reg<2>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(), info.get());
-      else
-        LAUNCH(h, "lu_panel", k_panel_reg<4>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(), info.get());
-    } else {
-      nb = std::min(kNb, m);
+    return m <= 4 * kRegThreads ? std::min(kRegNb, m) : std::min(kNb, m);
+  };
+  // a register panel can take in the update by a previous panel of at most
+  // kRegNb columns (kpn > 0); a panel of k_panel cannot
+  auto fusable = [&](int k0, int kpn) { return n - k0 <= 4 * kRegThreads && kpn <= kRegNb; };
+  auto panel = [&](int k0, int nb, int kpn) {
+    const int m = n - k0;
+    if (m > 4 * kRegThreads)
       LAUNCH(h, "lu_panel", k_panel, 1, 1024, 0, a, n, k0, nb, ipiv.get(), info.get());
+    else if (m > 2 * kRegThreads)
+      LAUNCH(h, "lu_panel", k_panel_reg<4>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(),
+             info.get(), kpn);
+    else if (m > kRegThreads)
+      LAUNCH(h, "lu_panel", k_panel_reg<2>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(),
+             info.get(), kpn);
+    else
+      LAUNCH(h, "lu_panel", k_panel_reg<1>, 1, kRegThreads, 0, a, n, k0, nb, ipiv.get(),
+             info.get(), kpn);
+  };
+  auto swap_trsm = [&](hipStream_t st, int k0, int nb, int lo1, int n1, int lo2, int n2) {
+    if (n1 + n2 > 0)
+      LAUNCH_ON(h, st, "lu_trsm", k_swap_trsm, blocks_for(n1 + n2, 64), 64, 0, a, n, k0, nb,
+                ipiv.get(), lo1, n1, lo2, n2);
+  };
+  auto col = [&](int c) { return a + static_cast<int64_t>(c) * n; };
+  // Look-ahead: after panel k a side stream applies step k (interchanges,
+  // triangular solve, trailing update) to every column except the next
+  // panel's, while the main stream brings the next panel's columns up to
+  // date (inside its panel kernel where it can, else by the same two
+  // launches) and factors it.  The two streams touch disjoint columns; the
+  // main stream waits for the side stream's previous step before the next
+  // panel (those columns took that step's update there), and the side
+  // stream waits for each panel.
+  Fork fork(h);
+  fork.next();  // the main stream
+  const hipStream_t side = fork.next();
+  hipEvent_t ev_panel = h->aux.step[0], ev_rest = h->aux.step[1];
+  int k0 = 0, nb = width(0);
+  panel(k0, nb, 0);
+  while (true) {
+    const int c0 = k0 + nb;
+    const int nb2 = c0 < n ? width(c0) : 0, c1 = c0 + nb2;
+    HIPX(hipEventRecord(ev_panel, h->stream));
+    HIPX(hipStreamWaitEvent(side, ev_panel, 0));
+    swap_trsm(side, k0, nb, 0, k0, c1, n - c1);
+    gemm_sub(h, n - c0, n - c1, nb, col(k0) + c0, col(c1) + k0, col(c1) + c0, n, side);
+    if (k0 > 0) HIPX(hipStreamWaitEvent(h->stream, ev_rest, 0));
+    HIPX(hipEventRecord(ev_rest, side));
+    if (c0 >= n) break;
+    const bool fuse = fusable(c0, nb);
+    if (!fuse) {
+      swap_trsm(h->stream, k0, nb, c0, nb2, 0, 0);
+      gemm_sub(h, n - c0, nb2, nb, col(k0) + c0, col(c0) + k0, col(c0) + c0, n);
     }
-    int c0 = k0 + nb;
-    if (n - nb > 0)
-      LAUNCH(h, "lu_trsm", k_swap_trsm, blocks_for(n - nb, 64), 64, 0, a, n, k0, nb, ipiv.get());
-    if (c0 < n)
-      gemm_sub(h, n - c0, n - c0, nb, a + static_cast<int64_t>(k0) * n + c0,
-               a + static_cast<int64_t>(c0) * n + k0, a + static_cast<int64_t>(c0) * n + c0, n);
-    k0 += nb;
+    panel(c0, nb2, fuse ? nb : 0);
+    k0 = c0;
+    nb = nb2;
   }
+  fork.join();
   int hinfo = 0;
   std::vector<int> hp(n);
   HIPX(hipMemcpyAsync(&hinfo, info.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));

@@ -124,6 +124,7 @@ struct AuxStreams {
   hipStream_t s[kAuxStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kAuxStreams] = {};
+  hipEvent_t step[2] = {};  // free for one user's step-by-step hand-offs
   ~AuxStreams();
 };
 
