@@ -57,6 +57,8 @@ __global__ void k_level_ptr(int n, const int* key_sorted, int* ptr) {
 // next pass, so a row that depends on a row of the same wavefront is finished
 // one pass after it.  The loop is bounded by the wall-clock limit and the
 // shared error flag, like the sweeps.
+constexpr int kLevDeps = 8;
+
 template <bool kUpper>
 __global__ void __launch_bounds__(256)
 k_levels_df(int n, const int* rp, const int* ci, const int* diag, int* lev, int* ticket,
@@ -75,6 +77,18 @@ k_levels_df(int n, const int* rp, const int* ci, const int* diag, int* lev, int*
     const int p0 = done ? 0 : (kUpper ? diag[i] + 1 : rp[i]);
     const int p1 = done ? 0 : (kUpper ? rp[i + 1] : diag[i]);
     const unsigned long long t0 = wall_clock64();
+    // a row of at most kLevDeps dependencies keeps their columns in registers
+    // and, pass by pass, reloads only the levels it has not seen yet
+    const bool few = p1 - p0 <= kLevDeps;
+    int dep[kLevDeps];
+    unsigned pending = 0;
+#pragma unroll
+    for (int k = 0; k < kLevDeps; ++k)
+      if (few && p0 + k < p1) {
+        dep[k] = ci[p0 + k];
+        pending |= 1u << k;
+      }
+    int Lk = 0;  // level bound from the dependencies seen so far (few)
     // the exit test is a wavefront vote, so a lane that finishes publishes in
     // the pass where it finishes (no lane leaves the loop on its own, which
     // would let the compiler move the store past the loop)
@@ -82,13 +96,30 @@ k_levels_df(int n, const int* rp, const int* ci, const int* diag, int* lev, int*
       if (!done) {
         int L = 0;
         bool ready = true;
-        for (int p = p0; p < p1; ++p) {
-          const int v = __hip_atomic_load(lev + ci[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (v < 0) {
-            ready = false;
-            break;
+        if (few) {
+          int v[kLevDeps];
+#pragma unroll
+          for (int k = 0; k < kLevDeps; ++k)
+            if (pending >> k & 1)
+              v[k] = __hip_atomic_load(lev + dep[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+          for (int k = 0; k < kLevDeps; ++k)
+            if ((pending >> k & 1) && v[k] >= 0) {
+              Lk = max(Lk, v[k] + 1);
+              pending &= ~(1u << k);
+            }
+          L = Lk;
+          ready = pending == 0;
+        } else {
+          for (int p = p0; p < p1; ++p) {
+            const int v =
+                __hip_atomic_load(lev + ci[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v < 0) {
+              ready = false;
+              break;
+            }
+            L = max(L, v + 1);
           }
-          L = max(L, v + 1);
         }
         if (ready) {
           __hip_atomic_store(lev + i, L, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
