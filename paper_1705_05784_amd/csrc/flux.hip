@@ -379,9 +379,12 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
       DBuf<int> loc0(A, n);
       LAUNCH(h, "flux_block_local", k_block_local, g, kT, 0, n, h->fv_order.get(),
              h->primal.get(), h->fv_ptr.get(), loc0.get());
-      LAUNCH(h, "flux_order", k_local_order<PrimalEdge>, nc, 256, 0, h->fv_ptr.get(),
-             h->fv_order.get(), h->rp.get(), h->ci.get(), PrimalEdge{h->primal.get(), h->ci.get()},
-             loc0.get());
+      const int cap = order_adj_cap(lds_hw_budget(h));
+      allow_lds(reinterpret_cast<const void*>(&k_local_order<PrimalEdge>),
+                cap * sizeof(unsigned short));
+      LAUNCH(h, "flux_order", k_local_order<PrimalEdge>, nc, kOrderThreads,
+             cap * sizeof(unsigned short), h->fv_ptr.get(), h->fv_order.get(), h->rp.get(),
+             h->ci.get(), PrimalEdge{h->primal.get(), h->ci.get()}, loc0.get(), cap);
     }
     h->Afv.reset(A, static_cast<size_t>(nc) * nc);
     build_coarse_operator(h, h->fv_ptr, h->fv_order, nullptr, nc, h->Afv);

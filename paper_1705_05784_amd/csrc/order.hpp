@@ -31,21 +31,67 @@ __device__ inline void block_bitonic_sort(int* a, int cnt) {
   }
 }
 
+// exclusive prefix sum of a[0, cnt) in place (LDS); a[cnt] receives the
+// total.  s_part holds blockDim.x + 1 ints; every thread of the block calls it.
+__device__ inline void block_exclusive_scan(int* a, int cnt, int* s_part) {
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int per = (cnt + T - 1) / T, b = min(cnt, tid * per), e = min(cnt, b + per);
+  int sum = 0;
+  for (int l = b; l < e; ++l) sum += a[l];
+  s_part[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int t = 0; t < T; ++t) {
+      const int v = s_part[t];
+      s_part[t] = run;
+      run += v;
+    }
+    s_part[T] = run;
+  }
+  __syncthreads();
+  int run = s_part[tid];
+  for (int l = b; l < e; ++l) {
+    const int v = a[l];
+    a[l] = run;
+    run += v;
+  }
+  if (tid == 0) a[cnt] = s_part[T];
+  __syncthreads();
+}
+
 // Local order of a block: breadth-first levels from a pseudo-peripheral cell,
 // cells of one level by ascending natural position.  Irregular blocks (fracture
 // regions, merged Coupled-AMS blocks) get a bandwidth tens of times smaller
 // than in ascending-index order; structured dual blocks keep their natural
 // order, which is narrower for them.  The order used is the narrower one.
 // `edge(p, i, K)` tells whether CSR entry p of row i couples two cells of
-// block K (the block's own couplings).
+// block K (the block's own couplings).  The block's couplings are first
+// staged in LDS as a local adjacency (16-bit local indices, at most adj_cap
+// of them, in the dynamic LDS), so the breadth-first levels and both
+// bandwidth measurements read LDS only; a block with more couplings reads
+// them from the CSR each time.
 constexpr int kOrderMax = 6144;
+constexpr int kOrderThreads = 256;
+constexpr int kOrderStaticBytes = (kOrderMax + 8192 + kOrderMax + 1 + kOrderThreads + 1 + 4) * 4;
+constexpr int kOrderAdjMax = 40960;
+
+// couplings a block can stage, given the LDS of one workgroup (bytes)
+inline int order_adj_cap(int64_t lds_bytes) {
+  const int64_t room = (lds_bytes - kOrderStaticBytes - 256) / 2;
+  return static_cast<int>(room < 0 ? 0 : (room > kOrderAdjMax ? kOrderAdjMax : room));
+}
+
 template <class Edge>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kOrderThreads)
 k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edge edge,
-              int* local_idx) {
+              int* local_idx, int adj_cap) {
   __shared__ int lvl[kOrderMax];
   __shared__ int key[8192];
+  __shared__ int s_off[kOrderMax + 1];
+  __shared__ int s_part[kOrderThreads + 1];
   __shared__ int s_changed, s_bnat, s_bbfs, s_start;
+  extern __shared__ unsigned short s_adj[];
   int K = blockIdx.x;
   int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
   if (n <= 2 || n > kOrderMax) return;
@@ -53,13 +99,38 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edg
     s_bnat = 0;
     s_bbfs = 0;
   }
-  __syncthreads();
-  int bnat = 0;
   for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    int i = cells[beg + l];
+    const int i = cells[beg + l];
+    int cnt = 0;
     for (int p = rp[i]; p < rp[i + 1]; ++p)
-      if (edge(p, i, K)) bnat = max(bnat, abs(local_idx[ci[p]] - l));
+      if (edge(p, i, K)) ++cnt;
+    s_off[l] = cnt;
   }
+  __syncthreads();
+  block_exclusive_scan(s_off, n, s_part);
+  const bool staged = s_off[n] <= adj_cap;
+  if (staged) {
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+      const int i = cells[beg + l];
+      int o = s_off[l];
+      for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (edge(p, i, K)) s_adj[o++] = static_cast<unsigned short>(local_idx[ci[p]]);
+    }
+    __syncthreads();
+  }
+  // f(local index) for every coupling of local cell l
+  auto for_nbrs = [&](int l, auto f) {
+    if (staged) {
+      for (int o = s_off[l]; o < s_off[l + 1]; ++o) f(static_cast<int>(s_adj[o]));
+    } else {
+      const int i = cells[beg + l];
+      for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (edge(p, i, K)) f(local_idx[ci[p]]);
+    }
+  };
+  int bnat = 0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x)
+    for_nbrs(l, [&](int lj) { bnat = max(bnat, abs(lj - l)); });
   atomicMax(&s_bnat, bnat);
   // Two breadth-first passes: the second starts from the lowest cell of the
   // first pass's last level (a pseudo-peripheral cell), which narrows the
@@ -74,15 +145,12 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edg
       __syncthreads();
       for (int l = threadIdx.x; l < n; l += blockDim.x) {
         if (lvl[l] != d) continue;
-        int i = cells[beg + l];
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-          if (!edge(p, i, K)) continue;
-          int lj = local_idx[ci[p]];
+        for_nbrs(l, [&](int lj) {
           if (lvl[lj] < 0) {
             lvl[lj] = d + 1;
             s_changed = 1;
           }
-        }
+        });
       }
       __syncthreads();
       const int changed = s_changed;
@@ -108,11 +176,8 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edg
   for (int t = threadIdx.x; t < n; t += blockDim.x) lvl[key[t] & 8191] = t;  // lvl := position
   __syncthreads();
   int bb = 0;
-  for (int l = threadIdx.x; l < n; l += blockDim.x) {
-    int i = cells[beg + l];
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-      if (edge(p, i, K)) bb = max(bb, abs(lvl[local_idx[ci[p]]] - lvl[l]));
-  }
+  for (int l = threadIdx.x; l < n; l += blockDim.x)
+    for_nbrs(l, [&](int lj) { bb = max(bb, abs(lvl[lj] - lvl[l])); });
   atomicMax(&s_bbfs, bb);
   __syncthreads();
   if (s_bbfs >= s_bnat) return;
@@ -123,13 +188,6 @@ k_local_order(const int* comp_ptr, int* cells, const int* rp, const int* ci, Edg
     local_idx[key[l]] = lvl[l];
   }
 }
-
-
-// Blocks above kOrderMax cells (fracture regions that percolate through plate
-// intersections): the same two-pass breadth-first order with its levels in
-// global scratch, one workgroup for the block.  Writes keys[l] = (level << 16)
-// | l and vals[l] = the cell, for a stable radix sort on the host side, and
-// the natural-order bandwidth to info[0].  Blocks of at most 32768 cells.
 template <class Edge>
 __global__ void __launch_bounds__(256)
 k_bfs_levels(int K, int beg, int n, const int* cells, const int* rp, const int* ci, Edge edge,

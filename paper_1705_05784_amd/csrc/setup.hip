@@ -983,9 +983,14 @@ void build_prolongation(Handle* h, const int8_t* wb) {
     LAUNCH(h, "local_idx", k_local_idx, blocks_for(m, kThreads), kThreads, 0, m, kks.get(),
            cells.get(), comp_ptr.get(), local_idx.get());
   }
-  if (ncomp)
-    LAUNCH(h, "local_order", k_local_order<KeptEdge>, ncomp, kThreads, 0, comp_ptr.get(),
-           cells.get(), h->rp.get(), h->ci.get(), KeptEdge{ecls.get()}, local_idx.get());
+  if (ncomp) {
+    const int cap = order_adj_cap(lds_hw_budget(h));
+    allow_lds(reinterpret_cast<const void*>(&k_local_order<KeptEdge>),
+              cap * sizeof(unsigned short));
+    LAUNCH(h, "local_order", k_local_order<KeptEdge>, ncomp, kOrderThreads,
+           cap * sizeof(unsigned short), comp_ptr.get(), cells.get(), h->rp.get(), h->ci.get(),
+           KeptEdge{ecls.get()}, local_idx.get(), cap);
+  }
   std::vector<int> h_cks(ncomp), h_comp_ptr(ncomp + 1, 0);
   if (ncomp) {
     HIPX(hipMemcpyAsync(h_cks.data(), cks.get(), ncomp * sizeof(int), hipMemcpyDeviceToHost,
