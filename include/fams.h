@@ -75,6 +75,12 @@ typedef enum { FAMS_PREC_FP64 = 0, FAMS_PREC_MIXED = 1 } fams_precision_t;
 /* Outer iteration: the Table 1 loop, or GMRES with Table 1 steps 5-7 as a
  * right preconditioner (flexible GMRES, Sec. 4.4). */
 typedef enum { FAMS_RICHARDSON = 0, FAMS_GMRES = 1 } fams_outer_t;
+/* Restriction operator R of the coarse stage (Sec. 3, 3.2): MSFE (R = P^T, the
+   default and the paper's choice for its experiments; SPD coarse operator for
+   SPD A), MSFV (row i has a 1 on every cell of primal block i; coarse-scale
+   mass conservation) or MSMIX (MSFV rows for the coarse nodes that lie in a
+   fracture, MSFE rows for the matrix ones). */
+typedef enum { FAMS_RESTRICT_FE = 0, FAMS_RESTRICT_FV = 1, FAMS_RESTRICT_MIX = 2 } fams_restriction_t;
 
 /* Fine system A (Eq. A-dis-mf).  Rows/columns: matrix cells 0..n_matrix-1 in
  * natural grid order, then fracture cells.  CSR with columns sorted within
@@ -117,6 +123,9 @@ typedef struct {
   int32_t smoother;           /* 1 = ILU(0) post-smoothing (Table 1 step 7), 0 = none */
   int32_t profile;            /* 1 = time every kernel launch of this handle with HIP
                                  events from setup on (see fams_get_kernel_stats) */
+  int32_t restriction;        /* fams_restriction_t; MSFV and MSMIX make the coarse
+                                 operator non-symmetric: its inverse then comes from LU
+                                 with partial pivoting.  Other values: FAMS_ERR_INVALID_ARG */
 } fams_setup_opts_t;
 
 typedef struct {

@@ -38,7 +38,11 @@ Readings where the paper is silent (listed in the design notes):
     largest entry (lowest column on ties) is kept; rows that lose nothing are
     left untouched;
   * restriction in the iteration: R = P^T (MSFE, the paper's choice for all of
-    its experiments, Sec. 3);
+    its experiments, Sec. 3) by default; MSFV (row i of R has a 1 on every
+    cell of primal block i, Sec. 3.2) and MSMIX (Sec. 3 and 3.2: FV for the
+    fractures, FE for the rock -- read as: the MSFV row for a coarse node whose
+    vertex is a fracture cell, the MSFE row for a matrix one) on request; the
+    coarse operator is then R A P with the same R;
   * GMRES: right preconditioned, restarted, modified Gram-Schmidt, the
     F-AMS two-stage step as preconditioner (Sec. 4.4), stopping on the true
     relative residual ||q - A p|| / ||q|| (p0 = 0).
@@ -58,6 +62,7 @@ DECOUPLED, FRAC, ROCK, COUPLED = 0, 1, 2, 3
 VARIANTS = {"decoupled": DECOUPLED, "frac": FRAC, "rock": ROCK, "coupled": COUPLED}
 KEPT, LUMPED, RHS = 1, 2, 3
 OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
+RESTRICT_FE, RESTRICT_FV, RESTRICT_MIX = 0, 1, 2
 
 
 def ranks(wb_type, n_matrix, variant):
@@ -226,6 +231,23 @@ def truncate(P, alpha, is_vertex_row):
                          shape=P.shape)
 
 
+def restriction(P, primal, vertex, n_matrix, kind=RESTRICT_FE):
+    """The restriction operator R (Sec. 3.2): MSFE R = P^T; MSFV R[i, j] = 1
+    when cell j lies in primal block i; MSMIX the MSFV row for a coarse node
+    whose vertex is a fracture cell and the MSFE row otherwise."""
+    RT = sp.csr_matrix(P.T)
+    if kind == RESTRICT_FE:
+        return RT
+    primal = np.asarray(primal, dtype=np.int64)
+    nc, n = RT.shape
+    RFV = sp.csr_matrix((np.ones(n), (primal, np.arange(n))), shape=(nc, n))
+    if kind == RESTRICT_FV:
+        return RFV
+    frac = np.asarray(vertex, dtype=np.int64) >= n_matrix
+    pick = sp.diags(frac.astype(np.float64))
+    return sp.csr_matrix(pick @ RFV + (sp.identity(nc) - pick) @ RT)
+
+
 def coarse_operator(A, P, R=None):
     """A_c = R A P as a dense matrix (R = P^T unless given)."""
     if R is None:
@@ -269,13 +291,15 @@ class FAMS:
     """Setup (basis functions, coarse LU, ILU(0)) and the iteration."""
 
     def __init__(self, A, wb_type, vertex, n_matrix, variant=DECOUPLED, alpha=0.0,
-                 merge_cap=4096, smoothing=True):
+                 merge_cap=4096, smoothing=True, primal=None, restriction_kind=RESTRICT_FE):
         self.A = sp.csr_matrix(A)
         self.A.sort_indices()
         self.n_matrix = n_matrix
         self.variant = variant
         self.P = prolongation(self.A, wb_type, vertex, n_matrix, variant, alpha, merge_cap)
-        self.R = sp.csr_matrix(self.P.T)
+        if restriction_kind != RESTRICT_FE and primal is None:
+            raise ValueError("the MSFV and MSMIX restrictions need the primal blocks")
+        self.R = restriction(self.P, primal, vertex, n_matrix, restriction_kind)
         self.Ac = coarse_operator(self.A, self.P, self.R)
         self.lu = sla.lu_factor(self.Ac)
         self.ilu = ILU0(self.A) if smoothing else None

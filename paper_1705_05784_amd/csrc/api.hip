@@ -269,6 +269,7 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   build_ilu(h);                 // diagonal positions (+ ILU(0) factors)
   pt.mark("ilu");
   build_prolongation(h, wb);    // P, R = P^T
+  if (h->restriction != FAMS_RESTRICT_FE) build_restriction(h);  // MSFV / MSMIX rows of R
   pt.mark("prolongation");
   const int nc = h->nc;
   h->Ac.reset(al, static_cast<size_t>(nc) * nc);
@@ -276,9 +277,10 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   pt.mark("coarse operator");
   {
     // A_c = P^T A P is SPD for SPD A: Gauss-Jordan without pivoting; if a
-    // pivot is not positive, LU with partial pivoting
+    // pivot is not positive, or the restriction is not P^T, LU with partial
+    // pivoting
     h->Ainv.reset(al, static_cast<size_t>(nc) * nc);
-    if (!spd_inverse(h, h->Ac, h->Ainv, nc)) {
+    if (h->restriction != FAMS_RESTRICT_FE || !spd_inverse(h, h->Ac, h->Ainv, nc)) {
       DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
       HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
                           h->stream));
@@ -358,7 +360,8 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
       G->n_coarse > 65536)
     return FAMS_ERR_INVALID_ARG;
   if (o->variant < 0 || o->variant > 3 || o->precision < 0 || o->precision > 1 ||
-      !(o->trunc_alpha >= 0.0 && o->trunc_alpha < 1.0) || o->merge_cap < 1)
+      !(o->trunc_alpha >= 0.0 && o->trunc_alpha < 1.0) || o->merge_cap < 1 ||
+      o->restriction < FAMS_RESTRICT_FE || o->restriction > FAMS_RESTRICT_MIX)
     return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     std::unique_ptr<fams_handle_s> h(new fams_handle_s());
@@ -374,6 +377,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->alpha = o->trunc_alpha;
     h->merge_cap = o->merge_cap;
     h->smoother = o->smoother ? 1 : 0;
+    h->restriction = o->restriction;
     h->prof.on = o->profile != 0;
     h->n = static_cast<int>(A->n);
     h->nm = static_cast<int>(A->n_matrix);

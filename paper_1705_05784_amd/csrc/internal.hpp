@@ -184,6 +184,7 @@ struct Handle {
   double alpha = 0.0;
   int64_t merge_cap = 4096;
   int smoother = 1;
+  int restriction = 0;  // fams_restriction_t
 
   // sizes
   int n = 0, nm = 0, nc = 0;
@@ -283,6 +284,8 @@ void exclusive_scan_i64(Handle* h, const int64_t* in, int64_t* out, int64_t n);
 // setup.hip
 void build_prolongation(Handle* h, const int8_t* wb);
 // dense.hip
+// the MSFV / MSMIX restriction in place of R = P^T (setup.hip)
+void build_restriction(Handle* h);
 void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const double* R_val,
                            int rows, double* out);
 void lu_inverse(Handle* h, double* a, double* inv, int n);

@@ -908,6 +908,91 @@ void print_block_timing(const unsigned long long* dev, int nb, int first) {
   }
 }
 
+namespace {
+
+// ---- MSFV / MSMIX restriction (Sec. 3, 3.2) --------------------------------
+__global__ void k_block_count(int n, int nc, const int* primal, int* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[primal[i]], 1);
+}
+
+__global__ void k_iota_r(int n, int* v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+// row i takes the primal block's cells (MSFV) or keeps its row of P^T
+__device__ __forceinline__ bool fv_row(int i, int restriction, int nm, const int* vertex) {
+  return restriction == FAMS_RESTRICT_FV || vertex[i] >= nm;
+}
+
+__global__ void k_r_counts(int nc, int restriction, int nm, const int* vertex, const int* bptr,
+                           const int* r_rp, int* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc)
+    cnt[i] = fv_row(i, restriction, nm, vertex) ? bptr[i + 1] - bptr[i] : r_rp[i + 1] - r_rp[i];
+  if (i == nc) cnt[nc] = 0;
+}
+
+__global__ void k_r_rows(int nc, int restriction, int nm, const int* vertex, const int* bptr,
+                         const int* cells, const int* r_rp, const int* r_ci, const double* r_val,
+                         const int* nrp, int* nci, double* nval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int o = nrp[i];
+  if (fv_row(i, restriction, nm, vertex)) {
+    for (int t = bptr[i]; t < bptr[i + 1]; ++t, ++o) {
+      nci[o] = cells[t];
+      nval[o] = 1.0;
+    }
+  } else {
+    for (int p = r_rp[i]; p < r_rp[i + 1]; ++p, ++o) {
+      nci[o] = r_ci[p];
+      nval[o] = r_val[p];
+    }
+  }
+}
+
+}  // namespace
+
+// R^FV: row i has a 1 on every cell of primal block i (the cells in
+// ascending order, from a stable sort by block); MSMIX takes these rows for
+// the coarse nodes whose vertex is a fracture cell and keeps the rows of
+// P^T for the matrix ones.  Replaces R (and its FP32 copy).
+void build_restriction(Handle* h) {
+  const int n = h->n, nc = h->nc;
+  Allocator* A = &h->alloc;
+  DBuf<int> cnt(A, nc + 1), bptr(A, nc + 1), keys(A, n), iota(A, n), cells(A, n);
+  HIPX(hipMemsetAsync(cnt, 0, (nc + 1) * sizeof(int), h->stream));
+  LAUNCH(h, "r_blocks", k_block_count, blocks_for(n, kThreads), kThreads, 0, n, nc,
+         h->primal.get(), cnt.get());
+  exclusive_scan_i32(h, cnt, bptr, nc + 1);
+  LAUNCH(h, "r_blocks", k_iota_r, blocks_for(n, kThreads), kThreads, 0, n, iota.get());
+  sort_pairs_i32(h, h->primal, keys, iota, cells, n, bits_for(nc));
+  LAUNCH(h, "r_rows", k_r_counts, blocks_for(nc + 1, kThreads), kThreads, 0, nc, h->restriction,
+         h->nm, h->vertex.get(), bptr.get(), h->r_rp.get(), cnt.get());
+  DBuf<int> nrp(A, nc + 1);
+  exclusive_scan_i32(h, cnt, nrp, nc + 1);
+  int nnz = 0;
+  HIPX(hipMemcpyAsync(&nnz, nrp.get() + nc, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  DBuf<int> nci(A, std::max(nnz, 1));
+  DBuf<double> nval(A, std::max(nnz, 1));
+  LAUNCH(h, "r_rows", k_r_rows, blocks_for(nc, kThreads), kThreads, 0, nc, h->restriction, h->nm,
+         h->vertex.get(), bptr.get(), cells.get(), h->r_rp.get(), h->r_ci.get(),
+         h->r_val.get(), nrp.get(), nci.get(), nval.get());
+  HIPX(hipStreamSynchronize(h->stream));
+  h->r_rp = std::move(nrp);
+  h->r_ci = std::move(nci);
+  h->r_val = std::move(nval);
+  if (h->precision == FAMS_PREC_MIXED) {
+    h->r_val32.reset(A, std::max(nnz, 1));
+    LAUNCH(h, "d2f", k_d2f, blocks_for(nnz, kThreads), kThreads, 0, static_cast<int64_t>(nnz),
+           h->r_val.get(), h->r_val32.get());
+  }
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
 void build_prolongation(Handle* h, const int8_t* wb) {
   const int n = h->n, nm = h->nm, nc = h->nc;
   unsigned g = blocks_for(n, kThreads);

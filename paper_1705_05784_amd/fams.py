@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libfams.so")
 DECOUPLED, FRAC, ROCK, COUPLED = 0, 1, 2, 3
 VARIANTS = {"decoupled": DECOUPLED, "frac": FRAC, "rock": ROCK, "coupled": COUPLED}
 FP64, MIXED = 0, 1
+RESTRICT_FE, RESTRICT_FV, RESTRICT_MIX = 0, 1, 2
+RESTRICTIONS = {"fe": RESTRICT_FE, "fv": RESTRICT_FV, "mix": RESTRICT_MIX}
 RICHARDSON, GMRES = 0, 1
 OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
 
@@ -42,7 +44,8 @@ class Grid(C.Structure):
 
 class SetupOpts(C.Structure):
     _fields_ = [("variant", C.c_int32), ("precision", C.c_int32), ("trunc_alpha", C.c_double),
-                ("merge_cap", C.c_int64), ("smoother", C.c_int32), ("profile", C.c_int32)]
+                ("merge_cap", C.c_int64), ("smoother", C.c_int32), ("profile", C.c_int32),
+                ("restriction", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -148,7 +151,8 @@ class Solver:
     """An F-AMS setup resident on the GPU (one fams_handle_t)."""
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
-                 precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False):
+                 precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False,
+                 restriction=0):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -166,8 +170,10 @@ class Solver:
         grid = Grid(self.n_coarse, _ptr(wb), _ptr(pr), _ptr(vx))
         if isinstance(variant, str):
             variant = VARIANTS[variant]
+        if isinstance(restriction, str):
+            restriction = RESTRICTIONS[restriction]
         opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
-                         1 if smoother else 0, 1 if profile else 0)
+                         1 if smoother else 0, 1 if profile else 0, int(restriction))
         h = C.c_void_p()
         self._h = None
         _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, _stream(),

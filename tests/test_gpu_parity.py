@@ -214,3 +214,63 @@ def test_ilu_factor_forms(name, range_rows, stage, monkeypatch):
     lu = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=0).ilu()
     assert np.array_equal(lu, ref)
     assert np.abs(lu - ora.ilu.val).max() <= 1e-12 * np.abs(ora.ilu.val).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_restriction_forms(name, variant, kind, precision):
+    """MSFV (kind 1) and MSMIX (kind 2) restrictions (Sec. 3.2): R, A_c = R A P
+    and its pivoted-LU inverse built on the GPU give the oracle's two-stage
+    step (FP64 form, 1e-10), and GMRES reaches the oracle's solution (1e-8;
+    the precision form to the same tolerance after convergence)."""
+    from paper_1705_05784_amd import fams
+    s, spec = small_case(name)
+    wb, primal, vertex, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    say(f"[case] {name} variant {variant} restriction {kind} precision {precision}")
+    gpu = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, primal, vertex, variant=variant,
+                      precision=precision, restriction=kind)
+    ora = ofams.FAMS(s.csr(), wb, vertex, s.n_matrix, variant, primal=primal,
+                     restriction_kind=kind)
+    if precision == 0:
+        r = np.random.default_rng(11).standard_normal(s.n)
+        z = gpu.apply_stage(torch.from_numpy(r)).cpu().numpy()
+        zr = ora.stage(r)
+        assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    p, info = gpu.solve(torch.from_numpy(s.q), outer="gmres", rtol=1e-10, max_iter=400)
+    p = p.cpu().numpy()
+    pr, oi = ora.gmres(s.q, rtol=1e-10)
+    assert info[0]["status"] == 0
+    if precision == 0:
+        assert abs(info[0]["iterations"] - oi["iterations"]) <= 1
+    assert np.linalg.norm(p - pr) <= 1e-8 * np.linalg.norm(pr)
+    gpu.close()
+
+
+@pytest.mark.parametrize("iters", [1, 3])
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_approximate_mode(name, iters):
+    """A few F-AMS iterations with the MSFV restriction, then the flux
+    reconstruction (Sec. 4.6: an approximate, conservative solution): the
+    unconverged iterate still yields a flux field whose every cell balances
+    (1e-10), equal to the oracle's reconstruction from the same pressure."""
+    from oracle import flux as oflux
+    from paper_1705_05784_amd import fams
+    s, spec = small_case(name)
+    wb, primal, vertex, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    say(f"[case] {name} MSFV, {iters} iterations, then flux")
+    gpu = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, primal, vertex,
+                      restriction=fams.RESTRICT_FV)
+    ora = ofams.FAMS(s.csr(), wb, vertex, s.n_matrix, 0, primal=primal,
+                     restriction_kind=ofams.RESTRICT_FV)
+    p, info = gpu.solve(torch.from_numpy(s.q), outer="richardson", rtol=1e-14, max_iter=iters)
+    assert info[0]["status"] == 1 and info[0]["iterations"] == iters  # not converged
+    fl, pfv, imb = gpu.reconstruct_flux(torch.from_numpy(s.q), p)
+    fr, p1, _, _ = oflux.reconstruct_flux(ora.A, ora.P, primal, vertex, s.q, p.cpu().numpy())
+    assert imb <= 1e-10
+    assert np.abs(pfv.cpu().numpy() - p1).max() <= 1e-9 * np.abs(p1).max()
+    assert np.abs(fl.cpu().numpy() - fr).max() <= 1e-8 * np.abs(fr).max()
+    pr, _ = ora.richardson(s.q, rtol=1e-14, max_iter=iters)
+    assert np.linalg.norm(p.cpu().numpy() - pr) <= 1e-9 * np.linalg.norm(pr)
+    gpu.close()
