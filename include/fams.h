@@ -120,7 +120,10 @@ typedef struct {
   int32_t precision;          /* fams_precision_t */
   double trunc_alpha;         /* drop |P_ij| < alpha, rescale row (Sec. 4.3); 0 = off */
   int64_t merge_cap;          /* Coupled-AMS: max cells of a merged block (Sec. 3.1) */
-  int32_t smoother;           /* 1 = ILU(0) post-smoothing (Table 1 step 7), 0 = none */
+  int32_t smoother;           /* 1 = ILU(0) post-smoothing (Table 1 step 7), 0 = none,
+                                 2 = ILU(0) followed by a second stage on the per-medium
+                                 sub-systems (Sec. 3.2): one ILU(0) application of
+                                 diag(A^mm, A^ff) to the updated residual */
   int32_t profile;            /* 1 = time every kernel launch of this handle with HIP
                                  events from setup on (see fams_get_kernel_stats) */
   int32_t restriction;        /* fams_restriction_t; MSFV and MSMIX make the coarse

@@ -43,6 +43,9 @@ Readings where the paper is silent (listed in the design notes):
     fractures, FE for the rock -- read as: the MSFV row for a coarse node whose
     vertex is a fracture cell, the MSFE row for a matrix one) on request; the
     coarse operator is then R A P with the same R;
+  * the extra smoothing stage on the per-medium systems (Sec. 3.2 names it
+    and leaves it to future work), on request: after the ILU(0) stage, one
+    ILU(0) application of diag(A^mm, A^ff) to the updated residual;
   * GMRES: right preconditioned, restarted, modified Gram-Schmidt, the
     F-AMS two-stage step as preconditioner (Sec. 4.4), stopping on the true
     relative residual ||q - A p|| / ||q|| (p0 = 0).
@@ -248,6 +251,14 @@ def restriction(P, primal, vertex, n_matrix, kind=RESTRICT_FE):
     return sp.csr_matrix(pick @ RFV + (sp.identity(nc) - pick) @ RT)
 
 
+def media_blocks(A, n_matrix):
+    """diag(A^mm, A^ff) of Eq. (dis-mf): A without the couplings A^mf, A^fm
+    between matrix cells (rows [0, n_matrix)) and fracture cells."""
+    A = sp.coo_matrix(A)
+    keep = (A.row < n_matrix) == (A.col < n_matrix)
+    return sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
+
+
 def coarse_operator(A, P, R=None):
     """A_c = R A P as a dense matrix (R = P^T unless given)."""
     if R is None:
@@ -291,7 +302,8 @@ class FAMS:
     """Setup (basis functions, coarse LU, ILU(0)) and the iteration."""
 
     def __init__(self, A, wb_type, vertex, n_matrix, variant=DECOUPLED, alpha=0.0,
-                 merge_cap=4096, smoothing=True, primal=None, restriction_kind=RESTRICT_FE):
+                 merge_cap=4096, smoothing=True, primal=None, restriction_kind=RESTRICT_FE,
+                 media_smoothing=False):
         self.A = sp.csr_matrix(A)
         self.A.sort_indices()
         self.n_matrix = n_matrix
@@ -303,6 +315,9 @@ class FAMS:
         self.Ac = coarse_operator(self.A, self.P, self.R)
         self.lu = sla.lu_factor(self.Ac)
         self.ilu = ILU0(self.A) if smoothing else None
+        # the extra smoothing stage on the per-medium systems (Sec. 3.2)
+        self.ilu_media = (ILU0(media_blocks(self.A, n_matrix))
+                          if smoothing and media_smoothing else None)
 
     # Table 1, steps 5-7, applied to a residual r: returns dp_{1/2} + dp_{2/2}
     def stage(self, r):
@@ -311,7 +326,10 @@ class FAMS:
         if self.ilu is None:
             return d1
         r_half = r - self.A @ d1
-        return d1 + self.ilu.solve(r_half)
+        d2 = self.ilu.solve(r_half)
+        if self.ilu_media is None:
+            return d1 + d2
+        return d1 + d2 + self.ilu_media.solve(r_half - self.A @ d2)
 
     def richardson(self, q, rtol=1e-6, max_iter=500, history=False):
         q = np.asarray(q, dtype=np.float64)

@@ -267,6 +267,7 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   PhaseTimer pt(h->stream);
   pt.mark("validate");
   build_ilu(h);                 // diagonal positions (+ ILU(0) factors)
+  if (h->smoother == 2) build_block_smoother(h);  // ILU(0) of diag(A^mm, A^ff)
   pt.mark("ilu");
   build_prolongation(h, wb);    // P, R = P^T
   if (h->restriction != FAMS_RESTRICT_FE) build_restriction(h);  // MSFV / MSMIX rows of R
@@ -361,7 +362,8 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     return FAMS_ERR_INVALID_ARG;
   if (o->variant < 0 || o->variant > 3 || o->precision < 0 || o->precision > 1 ||
       !(o->trunc_alpha >= 0.0 && o->trunc_alpha < 1.0) || o->merge_cap < 1 ||
-      o->restriction < FAMS_RESTRICT_FE || o->restriction > FAMS_RESTRICT_MIX)
+      o->restriction < FAMS_RESTRICT_FE || o->restriction > FAMS_RESTRICT_MIX ||
+      o->smoother < 0 || o->smoother > 2)
     return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     std::unique_ptr<fams_handle_s> h(new fams_handle_s());
@@ -376,7 +378,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->precision = o->precision;
     h->alpha = o->trunc_alpha;
     h->merge_cap = o->merge_cap;
-    h->smoother = o->smoother ? 1 : 0;
+    h->smoother = o->smoother;
     h->restriction = o->restriction;
     h->prof.on = o->profile != 0;
     h->n = static_cast<int>(A->n);
@@ -384,7 +386,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->nnz = A->nnz;
     h->nc = static_cast<int>(G->n_coarse);
     fams::setup_impl(h.get(), A, G);
-    h->info.device_bytes = h->alloc.live_bytes;
+    h->info.device_bytes = h->alloc.live_bytes + (h->blk ? h->blk->alloc.live_bytes : 0);
     *out = h.release();
     return FAMS_OK;
   });

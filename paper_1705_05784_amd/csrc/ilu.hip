@@ -999,6 +999,76 @@ void build_ilu(Handle* h) {
   }
 }
 
+namespace {
+
+// the couplings of the per-medium systems A^mm and A^ff: both ends in the
+// matrix, or both in the fractures (rows [0, nm) are matrix cells)
+__global__ void k_media_count(int n, int nm, const int* rp, const int* ci, int* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  int c = 0;
+  if (i < n) {
+    const bool mi = i < nm;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += (ci[p] < nm) == mi;
+  }
+  cnt[i] = c;
+}
+
+__global__ void k_media_fill(int n, int nm, const int* rp, const int* ci, const double* val,
+                             const int* nrp, int* nci, double* nval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool mi = i < nm;
+  int o = nrp[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p)
+    if ((ci[p] < nm) == mi) {
+      nci[o] = ci[p];
+      nval[o] = val[p];
+      ++o;
+    }
+}
+
+}  // namespace
+
+// The extra smoothing stage on the per-medium sub-systems (Sec. 3.2: another
+// smoothing stage with iterations on A^mm and A^ff): one ILU(0) application
+// of diag(A^mm, A^ff), i.e. of A without the couplings between the media,
+// whose factors and sweep schedules live in a handle of their own built by
+// the same code as the main ILU(0).
+void build_block_smoother(Handle* h) {
+  const int n = h->n;
+  std::unique_ptr<Handle> b(new Handle());
+  b->stream = h->stream;
+  b->alloc.stream = h->stream;
+  b->alloc.hook = h->alloc.hook;
+  b->alloc.has_hook = h->alloc.has_hook;
+  b->prof.stream = h->stream;
+  b->precision = h->precision;
+  b->smoother = 1;
+  b->n = n;
+  b->nm = h->nm;
+  {
+    DBuf<int> cnt(&b->alloc, n + 1);
+    LAUNCH(h, "media_split", k_media_count, blocks_for(n + 1, kT), kT, 0, n, h->nm, h->rp.get(),
+           h->ci.get(), cnt.get());
+    b->rp.reset(&b->alloc, n + 1);
+    exclusive_scan_i32(h, cnt, b->rp, n + 1);
+    int nnz = 0;
+    HIPX(hipMemcpyAsync(&nnz, b->rp.get() + n, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    b->nnz = nnz;
+    b->ci.reset(&b->alloc, nnz);
+    b->val.reset(&b->alloc, nnz);
+    LAUNCH(h, "media_split", k_media_fill, blocks_for(n, kT), kT, 0, n, h->nm, h->rp.get(),
+           h->ci.get(), h->val.get(), b->rp.get(), b->ci.get(), b->val.get());
+  }
+  build_ilu(b.get());
+  if (h->precision == FAMS_PREC_MIXED) h->blk_x32.reset(&h->alloc, n);
+  else h->blk_x.reset(&h->alloc, n);
+  HIPX(hipStreamSynchronize(h->stream));
+  h->blk = std::move(b);
+}
+
 // x = U^{-1} L^{-1} b.  `y` is scratch of n entries.
 template <class T>
 void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {

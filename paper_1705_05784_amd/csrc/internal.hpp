@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -243,6 +244,13 @@ struct Handle {
   size_t wk_vectors = 0;
 
   fams_setup_info_t info{};
+
+  // per-medium smoothing stage (smoother 2): a handle of its own holding
+  // A without the couplings between the media and its ILU(0) factors, and
+  // the stage's correction vector
+  std::unique_ptr<Handle> blk;
+  DBuf<double> blk_x;
+  DBuf<float> blk_x32;
 };
 
 // Fork-join of independent launches: next() hands out the handle's stream
@@ -300,6 +308,8 @@ void dense_gemm_add(Handle* h, int m, int p, int k, double alpha, const double* 
 void coarse_apply(Handle* h, const double* inv, int nc, const double* x, double* y, double* part);
 // ilu.hip
 void build_ilu(Handle* h);
+// the per-medium smoothing stage's handle (smoother 2)
+void build_block_smoother(Handle* h);
 template <class T>
 void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y);
 // solve.hip

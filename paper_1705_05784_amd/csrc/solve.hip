@@ -332,6 +332,21 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
   if (h->smoother) {
     resid<T, T, T, T>(h, av, d1, rT, rh);
     ilu_apply<T>(h, lu, rh, x, ysc);
+    if (h->blk) {  // per-medium stage: r <- r - A x (row by row, in place), x += M_B^{-1} r
+      Handle* b = h->blk.get();
+      T* xb;
+      const T* blu;
+      if constexpr (std::is_same<T, double>::value) {
+        xb = h->blk_x.get();
+        blu = b->ilu.get();
+      } else {
+        xb = h->blk_x32.get();
+        blu = b->ilu32.get();
+      }
+      resid<T, T, T, T>(h, av, x, rh, rh);
+      ilu_apply<T>(b, blu, rh, xb, ysc);
+      LAUNCH(h, "add", (k_add<T, T, T>), blocks_for(n, kT), kT, 0, (int64_t)n, x, xb, x);
+    }
     LAUNCH(h, "add", (k_add<T, T, double>), blocks_for(n, kT), kT, 0, (int64_t)n, d1, x, z);
   } else {
     LAUNCH(h, "cast", (k_cast<T, double>), blocks_for(n, kT), kT, 0, (int64_t)n, d1, z);

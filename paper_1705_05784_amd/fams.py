@@ -173,7 +173,7 @@ class Solver:
         if isinstance(restriction, str):
             restriction = RESTRICTIONS[restriction]
         opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
-                         1 if smoother else 0, 1 if profile else 0, int(restriction))
+                         int(smoother), 1 if profile else 0, int(restriction))
         h = C.c_void_p()
         self._h = None
         _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, _stream(),
