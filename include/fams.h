@@ -180,6 +180,19 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* grid,
                          const fams_setup_opts_t* opts, const fams_allocator_t* allocator,
                          void* hip_stream, fams_handle_t* out);
 
+/* New values of A on the setup's pattern (same n, nnz, row_ptr and col_idx;
+   `val` is a device pointer to nnz doubles, copied).  Table 1, steps 2 and 4,
+   and Sec. 3.1: the basis functions follow the fine-scale properties only
+   when these change beyond a threshold.  The ILU(0) factors, A_c and its
+   inverse are always rebuilt from the new A; P (and R) are recomputed when
+   max |a_new - a_basis| / |a_basis| over the entries exceeds `threshold`
+   (a_basis: the values P was last computed from; threshold < 0 always
+   recomputes), and *basis_recomputed says which happened.  The flux stage's
+   FV operator is rebuilt on its next use.  Errors as fams_setup; after an
+   error the handle is to be destroyed. */
+fams_status_t fams_update_values(fams_handle_t h, const double* val, double threshold,
+                                 int32_t* basis_recomputed);
+
 /* Solve A p = q for nrhs right-hand sides (device, column-major [n x nrhs]).
  * info (host, [nrhs], may be NULL).  Returns the worst status. */
 fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nrhs,

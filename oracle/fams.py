@@ -308,16 +308,53 @@ class FAMS:
         self.A.sort_indices()
         self.n_matrix = n_matrix
         self.variant = variant
-        self.P = prolongation(self.A, wb_type, vertex, n_matrix, variant, alpha, merge_cap)
         if restriction_kind != RESTRICT_FE and primal is None:
             raise ValueError("the MSFV and MSMIX restrictions need the primal blocks")
-        self.R = restriction(self.P, primal, vertex, n_matrix, restriction_kind)
+        self._grid = (wb_type, vertex, primal)
+        self._opts = (alpha, merge_cap, restriction_kind, smoothing, media_smoothing)
+        self._basis()
+        self._operators()
+
+    def _basis(self):
+        """P (and R) from the current A; remembers the values they follow."""
+        wb_type, vertex, primal = self._grid
+        alpha, merge_cap, kind = self._opts[:3]
+        self.P = prolongation(self.A, wb_type, vertex, self.n_matrix, self.variant, alpha,
+                              merge_cap)
+        self.R = restriction(self.P, primal, vertex, self.n_matrix, kind)
+        self.A_basis = self.A.copy()
+
+    def _operators(self):
+        """A_c = R A P, its LU and the smoothers, from the current A."""
+        smoothing, media_smoothing = self._opts[3:]
         self.Ac = coarse_operator(self.A, self.P, self.R)
         self.lu = sla.lu_factor(self.Ac)
         self.ilu = ILU0(self.A) if smoothing else None
         # the extra smoothing stage on the per-medium systems (Sec. 3.2)
-        self.ilu_media = (ILU0(media_blocks(self.A, n_matrix))
+        self.ilu_media = (ILU0(media_blocks(self.A, self.n_matrix))
                           if smoothing and media_smoothing else None)
+
+    def update_values(self, A_new, threshold=0.0):
+        """New values of A on the same pattern (Table 1, steps 2 and 4).  The
+        basis functions follow only when the largest relative change of an
+        entry since they were computed exceeds `threshold` (Sec. 3.1; an
+        entry that was zero counts its absolute change); A_c, its LU and the
+        smoothers always follow.  Returns True when P was recomputed."""
+        A_new = sp.csr_matrix(A_new)
+        A_new.sort_indices()
+        if not (np.array_equal(A_new.indptr, self.A_basis.indptr)
+                and np.array_equal(A_new.indices, self.A_basis.indices)):
+            raise ValueError("update_values: the pattern of A changed")
+        old, new = self.A_basis.data, A_new.data
+        d = np.abs(new - old)
+        rel = np.where(old != 0.0, d / np.where(old != 0.0, np.abs(old), 1.0), d)
+        change = rel.max() if rel.size else 0.0
+        recompute = not (change <= threshold)
+        self.A = A_new
+        if recompute:
+            self._basis()
+        self._operators()
+        return recompute
 
     # Table 1, steps 5-7, applied to a residual r: returns dp_{1/2} + dp_{2/2}
     def stage(self, r):

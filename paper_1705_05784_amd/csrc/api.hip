@@ -233,6 +233,80 @@ fams_status_t guard(F&& f) {
   }
 }
 
+// A_c = R A P and its inverse, and the FP32 copy of A (precision form): the
+// parts of the setup that follow the values of A for a fixed basis
+void coarse_setup(Handle* h) {
+  Allocator* al = &h->alloc;
+  h->ap_state = 0;  // A P follows A and P
+  const int nc = h->nc;
+  h->Ac.reset(al, static_cast<size_t>(nc) * nc);
+  build_coarse_operator(h, h->r_rp, h->r_ci, h->r_val, nc, h->Ac);
+  {
+    // A_c = P^T A P is SPD for SPD A: Gauss-Jordan without pivoting; if a
+    // pivot is not positive, or the restriction is not P^T, LU with partial
+    // pivoting
+    h->Ainv.reset(al, static_cast<size_t>(nc) * nc);
+    if (h->restriction != FAMS_RESTRICT_FE || !spd_inverse(h, h->Ac, h->Ainv, nc)) {
+      DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
+      HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
+                          h->stream));
+      lu_inverse(h, lu, h->Ainv, nc);
+    }
+    HIPX(hipStreamSynchronize(h->stream));
+  }
+  if (h->precision == FAMS_PREC_MIXED) {
+    h->val32.reset(al, h->nnz);
+    LAUNCH(h, "d2f", k_d2f_api, blocks_for(h->nnz, 256), 256, 0, h->nnz, h->val.get(),
+           h->val32.get());
+  }
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
+// largest relative change |a_new - a_old| / |a_old| over the entries of A
+// (absolute where a_old = 0), as the bits of a non-negative double, so that
+// an integer maximum orders them (NaN sorts above every number)
+__global__ void k_rel_change(int64_t nnz, const double* a_new, const double* a_old,
+                             unsigned long long* out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  const double d = fabs(a_new[i] - a_old[i]);
+  const double r = a_old[i] != 0.0 ? d / fabs(a_old[i]) : d;
+  atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(r)));
+}
+
+// New values of A on the setup's pattern (Table 1, steps 2 and 4; Sec. 3.1:
+// the basis functions are updated only when the fine-scale properties
+// change beyond a threshold).  The ILU(0) factors, A_c and its inverse
+// always follow the new A; P (and R) are recomputed when the largest
+// relative change since the last basis exceeds `threshold`.
+void update_impl(Handle* h, const double* val, double threshold, int* recomputed) {
+  Allocator* al = &h->alloc;
+  HIPX(hipMemcpyAsync(h->val, val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                      h->stream));
+  DBuf<unsigned long long> mx(al, 1);
+  HIPX(hipMemsetAsync(mx, 0, sizeof(unsigned long long), h->stream));
+  LAUNCH(h, "update", k_rel_change, blocks_for(h->nnz, 256), 256, 0, h->nnz, h->val.get(),
+         h->val_basis.get(), mx.get());
+  unsigned long long bits = 0;
+  HIPX(hipMemcpyAsync(&bits, mx.get(), sizeof(bits), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  double change;
+  std::memcpy(&change, &bits, sizeof(change));
+  const bool basis = !(change <= threshold);
+  build_ilu(h);
+  if (h->smoother == 2) build_block_smoother(h);
+  if (basis) {
+    build_prolongation(h, h->wb.get());
+    if (h->restriction != FAMS_RESTRICT_FE) build_restriction(h);
+    HIPX(hipMemcpyAsync(h->val_basis, h->val.get(), h->nnz * sizeof(double),
+                        hipMemcpyDeviceToDevice, h->stream));
+  }
+  coarse_setup(h);
+  h->fv_ready = false;  // the FV operator of the flux stage follows A: rebuilt on next use
+  HIPX(hipStreamSynchronize(h->stream));
+  *recomputed = basis ? 1 : 0;
+}
+
 void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = A->n;
@@ -250,8 +324,9 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
                       h->stream));
   LAUNCH(h, "copy_in", k_cols_check, blocks_for(A->nnz, 256), 256, 0, A->nnz, (int)n, h->ci.get(),
          err.get());
-  DBuf<int8_t> wb(al, n);
-  HIPX(hipMemcpyAsync(wb, G->wb_type, n, hipMemcpyDeviceToDevice, h->stream));
+  h->wb.reset(al, n);
+  HIPX(hipMemcpyAsync(h->wb, G->wb_type, n, hipMemcpyDeviceToDevice, h->stream));
+  const int8_t* wb = h->wb.get();
   h->primal.reset(al, n);
   HIPX(hipMemcpyAsync(h->primal, G->primal, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
   h->vertex.reset(al, h->nc);
@@ -272,30 +347,13 @@ void setup_impl(Handle* h, const fams_csr_t* A, const fams_grid_t* G) {
   build_prolongation(h, wb);    // P, R = P^T
   if (h->restriction != FAMS_RESTRICT_FE) build_restriction(h);  // MSFV / MSMIX rows of R
   pt.mark("prolongation");
-  const int nc = h->nc;
-  h->Ac.reset(al, static_cast<size_t>(nc) * nc);
-  build_coarse_operator(h, h->r_rp, h->r_ci, h->r_val, nc, h->Ac);
-  pt.mark("coarse operator");
-  {
-    // A_c = P^T A P is SPD for SPD A: Gauss-Jordan without pivoting; if a
-    // pivot is not positive, or the restriction is not P^T, LU with partial
-    // pivoting
-    h->Ainv.reset(al, static_cast<size_t>(nc) * nc);
-    if (h->restriction != FAMS_RESTRICT_FE || !spd_inverse(h, h->Ac, h->Ainv, nc)) {
-      DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
-      HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
-                          h->stream));
-      lu_inverse(h, lu, h->Ainv, nc);
-    }
-    HIPX(hipStreamSynchronize(h->stream));
-  }
+  coarse_setup(h);
   pt.mark("coarse inverse");
-  if (h->precision == FAMS_PREC_MIXED) {
-    h->val32.reset(al, h->nnz);
-    LAUNCH(h, "d2f", k_d2f_api, blocks_for(h->nnz, 256), 256, 0, h->nnz, h->val.get(),
-           h->val32.get());
-  }
+  h->val_basis.reset(al, h->nnz);
+  HIPX(hipMemcpyAsync(h->val_basis, h->val.get(), h->nnz * sizeof(double),
+                      hipMemcpyDeviceToDevice, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
+  const int nc = h->nc;
   h->info.n = n;
   h->info.n_matrix = h->nm;
   h->info.nnz = h->nnz;
@@ -338,6 +396,7 @@ fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t p
   const double zp = 16.0 * n;  // nnz(P) bound used for admission (<= 16 per row)
   double b = 0;
   b += nnz * (4 + 8 + 8) + (n + 1) * 4 + n * (4 + 4 + 4);       // A, ILU, diag, primal
+  b += nnz * 8.0 + n;                                            // basis values, classes
   b += 2 * zp * (4 + 8) + (n + n_coarse + 2) * 4;                // P and R
   b += 2.0 * 8 * n_coarse * n_coarse;                            // A_c and its inverse
   b += 2.0 * 8 * n_coarse * n_coarse;                            // FV operator and inverse
@@ -388,6 +447,18 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     fams::setup_impl(h.get(), A, G);
     h->info.device_bytes = h->alloc.live_bytes + (h->blk ? h->blk->alloc.live_bytes : 0);
     *out = h.release();
+    return FAMS_OK;
+  });
+}
+
+fams_status_t fams_update_values(fams_handle_t h, const double* val, double threshold,
+                                 int32_t* basis_recomputed) {
+  if (!h || !val || !basis_recomputed) return FAMS_ERR_INVALID_ARG;
+  return fams::guard([&]() -> fams_status_t {
+    int rec = 0;
+    fams::update_impl(h, val, threshold, &rec);
+    *basis_recomputed = rec;
+    h->info.device_bytes = h->alloc.live_bytes + (h->blk ? h->blk->alloc.live_bytes : 0);
     return FAMS_OK;
   });
 }

@@ -868,6 +868,10 @@ void range_table(Handle* h, const std::vector<int>& lev, int S, int upper, Range
   LAUNCH(h, "ilu_ell", k_ell_build, blocks_for(n, kT), kT, 0, n, upper, R->rows.get(),
          h->rp.get(), h->diag.get(), h->ci.get(), R->ecol.get(), R->epos.get(), R->ecnt.get(),
          R->ep0.get());
+  R->eval64.free();  // the ELL values follow the factors: taken again on the next sweep
+  R->ediag64.free();
+  R->eval32.free();
+  R->ediag32.free();
   HIPX(hipStreamSynchronize(h->stream));
 }
 

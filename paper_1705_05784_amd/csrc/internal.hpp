@@ -196,6 +196,8 @@ struct Handle {
   DBuf<double> val;
   DBuf<float> val32;
   DBuf<int> primal, vertex;
+  DBuf<int8_t> wb;           // wirebasket class of every cell
+  DBuf<double> val_basis;    // the values of A the basis functions were computed from
 
   // prolongation / restriction (CSR)
   int64_t p_nnz = 0;

@@ -998,6 +998,8 @@ void build_prolongation(Handle* h, const int8_t* wb) {
   unsigned g = blocks_for(n, kThreads);
   Allocator* A = &h->alloc;
   PhaseTimer pt(h->stream);
+  h->info.local_flops = 0;  // counted afresh for every basis
+  h->info.local_subst_flops = 0;
 
   DBuf<int> coarse_of(A, n), err(A, 1);
   DBuf<int8_t> rho(A, n), ecls(A, h->nnz);

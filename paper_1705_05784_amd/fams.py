@@ -74,6 +74,8 @@ EXPORTS = {
                         C.POINTER(C.c_size_t)], C.c_int),
     "fams_setup": ([C.POINTER(CSR), C.POINTER(Grid), C.POINTER(SetupOpts), C.c_void_p,
                     C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "fams_update_values": ([C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_int32)],
+                           C.c_int),
     "fams_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(SolveOpts),
                     C.POINTER(Info)], C.c_int),
     "fams_reconstruct_flux": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -211,6 +213,18 @@ class Solver:
         _check(st, "fams_solve")
         return p, [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
                         ms=i.ms) for i in infos]
+
+    def update_values(self, val, threshold=0.0):
+        """New values of A on the setup's pattern; True when P was recomputed
+        (largest relative change above `threshold`; negative: always)."""
+        import torch
+        v = torch.as_tensor(val).to(self.device, torch.float64).contiguous()
+        if v.numel() != self.nnz:
+            raise ValueError("update_values: expected nnz values")
+        rec = C.c_int32()
+        _check(lib().fams_update_values(self._h, _ptr(v), float(threshold), C.byref(rec)),
+               "fams_update_values")
+        return bool(rec.value)
 
     def reconstruct_flux(self, q, p):
         import torch

@@ -304,3 +304,83 @@ def test_media_smoothing(name, variant, precision):
         assert abs(info[0]["iterations"] - oi["iterations"]) <= 1
     assert np.linalg.norm(p - pr) <= 1e-8 * np.linalg.norm(pr)
     gpu.close()
+
+
+def _scaled_values(s, amp, seed=0):
+    """A's values with every transmissibility scaled by 1 + amp sin(i + j +
+    seed) (symmetric) and the diagonal moved so that every row sum is kept:
+    still a TPFA M-matrix with the same boundary terms (a permeability
+    change), in A's CSR slots."""
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    off = rows != s.col
+    v = s.val.copy()
+    v[off] *= 1.0 + amp * np.sin(rows[off] + s.col[off] + seed)
+    moved = np.bincount(rows[off], weights=(v - s.val)[off], minlength=s.n)
+    v[~off] -= moved[rows[~off]]
+    return v
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_update_recompute_matches_fresh_setup(name, variant, precision):
+    """fams_update_values with a recomputed basis leaves the handle exactly
+    as a fresh setup on the new values: P, A_c, the ILU(0) factors, one stage
+    and the reconstructed fluxes agree bit for bit (no stale state)."""
+    from paper_1705_05784_amd import fams
+    s, spec = small_case(name)
+    wb, primal, vertex, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    say(f"[case] {name} variant {variant} update (recompute) precision {precision}")
+    v2 = _scaled_values(s, 0.2)
+    g = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, primal, vertex, variant=variant,
+                    precision=precision)
+    r = np.random.default_rng(17).standard_normal(s.n)
+    g.apply_stage(torch.from_numpy(r))
+    g.reconstruct_flux(torch.from_numpy(s.q), torch.zeros(s.n, dtype=torch.float64))
+    assert g.update_values(v2, threshold=0.01)
+    f = fams.Solver(s.row_ptr, s.col, v2, s.n_matrix, wb, primal, vertex, variant=variant,
+                    precision=precision)
+    for a, b in zip(g.prolongation(), f.prolongation()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(g.coarse_matrix(), f.coarse_matrix())
+    assert np.array_equal(g.ilu(), f.ilu())
+    za = g.apply_stage(torch.from_numpy(r)).cpu().numpy()
+    zb = f.apply_stage(torch.from_numpy(r)).cpu().numpy()
+    assert np.array_equal(za, zb)
+    p = torch.from_numpy(np.random.default_rng(19).standard_normal(s.n))
+    fa = g.reconstruct_flux(torch.from_numpy(s.q), p)
+    fb = f.reconstruct_flux(torch.from_numpy(s.q), p)
+    assert np.array_equal(fa[0].cpu().numpy(), fb[0].cpu().numpy())
+    g.close()
+    f.close()
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("name", ["2d", "3d", "cfg2s"])
+def test_update_kept_basis(name, variant):
+    """Below the threshold the basis stays: the GPU keeps P and rebuilds A_c,
+    its inverse and ILU(0) from the new A, like the oracle's update (one stage
+    1e-10, GMRES 1e-8 and within one iteration)."""
+    from paper_1705_05784_amd import fams
+    s, spec = small_case(name)
+    wb, primal, vertex, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    say(f"[case] {name} variant {variant} update (basis kept)")
+    v2 = _scaled_values(s, 0.3, seed=1)
+    g = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, primal, vertex, variant=variant)
+    ora = ofams.FAMS(s.csr(), wb, vertex, s.n_matrix, variant)
+    P0 = g.prolongation()
+    assert not g.update_values(v2, threshold=1e9)
+    A2 = sp.csr_matrix((v2, s.col, s.row_ptr), shape=(s.n, s.n))
+    assert not ora.update_values(A2, threshold=1e9)
+    for a, b in zip(g.prolongation(), P0):
+        assert np.array_equal(a, b)
+    r = np.random.default_rng(23).standard_normal(s.n)
+    z = g.apply_stage(torch.from_numpy(r)).cpu().numpy()
+    zr = ora.stage(r)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    p, info = g.solve(torch.from_numpy(s.q), outer="gmres", rtol=1e-10, max_iter=400)
+    pr, oi = ora.gmres(s.q, rtol=1e-10)
+    assert info[0]["status"] == 0
+    assert abs(info[0]["iterations"] - oi["iterations"]) <= 1
+    assert np.linalg.norm(p.cpu().numpy() - pr) <= 1e-8 * np.linalg.norm(pr)
+    g.close()
