@@ -131,3 +131,24 @@ def test_flux_exact_pressure_gives_tpfa_fluxes():
     off = r != A.indices
     expect = -A.data[off] * (p[r[off]] - p[A.indices[off]])
     assert np.abs(fl[off] - expect).max() <= 1e-8 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_solution_independent_of_strategy(name):
+    """Table 1's fixed point is A p = q whatever builds the preconditioner:
+    the converged pressure is the same for all four coupling strategies,
+    with and without truncation, and with MSFE or MSFV restriction."""
+    s, spec = small_case(name)
+    wb, primal, vertex, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    sols = []
+    for variant in VARIANTS:
+        for alpha in (0.0, 1e-2):
+            for kind in (fams.RESTRICT_FE, fams.RESTRICT_FV):
+                F = fams.FAMS(s.csr(), wb, vertex, s.n_matrix, variant, alpha, primal=primal,
+                              restriction_kind=kind)
+                p, info = F.gmres(s.q, rtol=1e-12)
+                assert info["status"] == fams.OK
+                sols.append(p)
+    ref = sols[0]
+    for p in sols[1:]:
+        assert np.linalg.norm(p - ref) <= 1e-9 * np.linalg.norm(ref)
