@@ -236,6 +236,8 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
  *   op 2: out = a^{-1} by LU with partial pivoting and triangular solves
  *   op 3: out = a^{-1} column by column with the one-workgroup LU solve
  *         (the FV stage's solver; n <= 12288)
+ *   op 4: out = the packed LU factors of P a (unit L below the diagonal, U on
+ *         and above it, rows interchanged as LAPACK getrf leaves them)
  * For tests of those kernels; blocking. */
 fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out);
 

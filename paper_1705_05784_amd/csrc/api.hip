@@ -567,7 +567,7 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z) {
 }
 
 fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out) {
-  if (op < 0 || op > 3 || n <= 0 || n > 65536 || !a || !out) return FAMS_ERR_INVALID_ARG;
+  if (op < 0 || op > 4 || n <= 0 || n > 65536 || !a || !out) return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     std::unique_ptr<fams_handle_s> h(new fams_handle_s());
     fams::Handle* H = h.get();
@@ -580,6 +580,10 @@ fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out)
     } else if (op == 1) {
       FAMS_REQUIRE(fams::spd_inverse(H, a, out, n), FAMS_ERR_SINGULAR_COARSE,
                    "not positive definite");
+    } else if (op == 4) {  // the packed LU factors of P A (row interchanges as in getrf)
+      fams::DBuf<int> perm(&H->alloc, n);
+      HIPX(hipMemcpyAsync(out, a, nn * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
+      fams::lu_factor(H, out, n, perm);
     } else if (op == 2) {
       fams::DBuf<double> lu(&H->alloc, nn);
       HIPX(hipMemcpyAsync(lu, a, nn * sizeof(double), hipMemcpyDeviceToDevice, nullptr));

@@ -279,6 +279,47 @@ k_panel(double* a, int n, int k0, int nb, int* ipiv, int* info) {
   }
 }
 
+// One step of the wavefront argmax below: every lane enabled by kRowMask
+// combines its candidate with the one the DPP pattern kCtrl routes to it
+// (lanes without a source keep their own).  Larger |a| wins, then the lower
+// position: a total order, so the combining order does not matter.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void argmax_dpp(double& v, int& p) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = static_cast<int>(static_cast<unsigned>(u));
+  const int hi = static_cast<int>(static_cast<unsigned>(u >> 32));
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, kCtrl, kRowMask, 0xf, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, kCtrl, kRowMask, 0xf, false);
+  const int op = __builtin_amdgcn_update_dpp(p, p, kCtrl, kRowMask, 0xf, false);
+  const double ov = __builtin_bit_cast(
+      double, (static_cast<unsigned long long>(static_cast<unsigned>(ohi)) << 32) |
+                  static_cast<unsigned>(olo));
+  if (ov > v || (ov == v && op < p)) {
+    v = ov;
+    p = op;
+  }
+}
+
+// (max |a|, its lowest position) over the wavefront, in every lane: an
+// inclusive scan within each row of 16 lanes (row_shr 1, 2, 4, 8), then the
+// last lane of a row is passed on to the next rows (row_bcast 15 and 31),
+// which leaves the whole wavefront's result in lane 63.
+__device__ __forceinline__ void wave_argmax(double& v, int& p) {
+  argmax_dpp<0x111, 0xf>(v, p);  // row_shr:1
+  argmax_dpp<0x112, 0xf>(v, p);  // row_shr:2
+  argmax_dpp<0x114, 0xf>(v, p);  // row_shr:4
+  argmax_dpp<0x118, 0xf>(v, p);  // row_shr:8
+  argmax_dpp<0x142, 0xa>(v, p);  // row_bcast:15 into rows 1 and 3
+  argmax_dpp<0x143, 0xc>(v, p);  // row_bcast:31 into rows 2 and 3
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = static_cast<unsigned>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), 63));
+  const unsigned hi = static_cast<unsigned>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), 63));
+  v = __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+  p = __builtin_amdgcn_readlane(p, 63);
+}
+
 // Panel of nb <= 16 columns held in registers (rows [k0, n), at most 512*RT
 // of them; thread t owns rows t, t+512, ...).  Row interchanges are logical:
 // pos[] is each row's current position and at_pos[] its inverse, so a step
@@ -400,14 +441,7 @@ k_panel_reg(double* a, int n, int k0, int nb, int* ipiv, int* info, int kpn) {
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int op = __shfl_xor(bpos, off);
-      if (ob > best || (ob == best && op < bpos)) {
-        best = ob;
-        bpos = op;
-      }
-    }
+    wave_argmax(best, bpos);
     if (lane == 0) {
       s_best[wave] = best;
       s_bpos[wave] = bpos;

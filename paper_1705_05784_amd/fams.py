@@ -336,7 +336,8 @@ def setup(sysm, coarse, d_min, r_z, **kw) -> Solver:
 def dense_op(op: int, a):
     """Run one of the coarse system's dense kernels on a (n x n, float64):
     0 a@a, 1 SPD Gauss-Jordan inverse, 2 pivoted LU inverse, 3 LU-solve
-    inverse.  Returns a torch tensor on the current device."""
+    inverse, 4 packed LU factors (getrf layout).  Returns a torch tensor on
+    the current device."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     a = torch.as_tensor(a).to(device=dev, dtype=torch.float64)

@@ -55,3 +55,18 @@ def test_lu_solve(n):
     x = fams.dense_op(3, a).cpu().numpy()
     ref = np.linalg.inv(a)
     assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [1, 17, 37, 600, 1500, 2100])
+def test_lu_factors_match_getrf(n):
+    """The pivoted LU makes the pivot choices of LAPACK getrf (first maximal
+    |a| in the column): the packed factors equal scipy's to rounding, which a
+    single different pivot would break at O(1).  n = 2100 starts with the
+    32-column panels and then takes the 16-column register panels."""
+    import scipy.linalg as sla
+    from paper_1705_05784_amd import fams
+    _say(f"[dense] lu factors n={n}")
+    a = np.random.default_rng(n + 5).standard_normal((n, n))
+    lu = fams.dense_op(4, a).cpu().numpy()
+    ref, _ = sla.lu_factor(a)
+    assert np.abs(lu - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
