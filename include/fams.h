@@ -10,8 +10,8 @@
  * strategies, the coarse operator A_c = R A P with R = P^T (Sec. 3, App. A),
  * and iterates the two-stage scheme of Table 1 (multiscale stage + ILU(0)
  * smoothing) either as a Richardson loop or as the preconditioner of GMRES
- * (Sec. 4.4-4.5).  From any iterate, a finite-volume stage yields a
- * mass-conservative fine-scale flux field (Sec. 3.2, Sec. 4.5).
+ * (Sec. 4.6).  From any iterate, a finite-volume stage yields a
+ * mass-conservative fine-scale flux field (Sec. 3.2, Sec. 4.6).
  *
  * Memory and ownership
  *   - Every array argument marked "device" is caller-owned GPU memory (e.g. a
@@ -73,7 +73,7 @@ typedef enum { FAMS_DECOUPLED = 0, FAMS_FRAC = 1, FAMS_ROCK = 2, FAMS_COUPLED = 
 typedef enum { FAMS_PREC_FP64 = 0, FAMS_PREC_MIXED = 1 } fams_precision_t;
 
 /* Outer iteration: the Table 1 loop, or GMRES with Table 1 steps 5-7 as a
- * right preconditioner (flexible GMRES, Sec. 4.4). */
+ * right preconditioner (flexible GMRES, Sec. 4.6). */
 typedef enum { FAMS_RICHARDSON = 0, FAMS_GMRES = 1 } fams_outer_t;
 /* Restriction operator R of the coarse stage (Sec. 3, 3.2): MSFE (R = P^T, the
    default and the paper's choice for its experiments; SPD coarse operator for
@@ -198,7 +198,7 @@ fams_status_t fams_update_values(fams_handle_t h, const double* val, double thre
 fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nrhs,
                          const fams_solve_opts_t* opts, fams_info_t* info);
 
-/* Conservative flux reconstruction after an FV stage (Sec. 3.2, Sec. 4.5):
+/* Conservative flux reconstruction after an FV stage (Sec. 3.2, Sec. 4.6):
  * flux (device [nnz], in A's CSR slots): off-diagonal slot (i,j) holds the
  * flux F_ij from i to j; the diagonal slot holds E_i, the boundary/source
  * exchange, so that sum_j F_ij + E_i = 0 for every cell.  p_fv (device [n],

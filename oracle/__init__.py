@@ -15,7 +15,7 @@ Modules:
               truncation (Sec. 4.3), coarse operator R A P with R = P^T
               (Sec. 3.2, App. A), ILU(0) (Sec. 3.2), the two-stage iteration
               (Table 1) as a Richardson loop or inside right-preconditioned
-              GMRES (Sec. 4.4-4.5).
+              GMRES (Sec. 4.6).
   flux     -- finite-volume stage and conservative flux reconstruction
               (Sec. 3.2; the paper states it exists after any R^FV stage but
               gives no algorithm -- the standard MSFV reconstruction is used).

@@ -47,7 +47,7 @@ Readings where the paper is silent (listed in the design notes):
     and leaves it to future work), on request: after the ILU(0) stage, one
     ILU(0) application of diag(A^mm, A^ff) to the updated residual;
   * GMRES: right preconditioned, restarted, modified Gram-Schmidt, the
-    F-AMS two-stage step as preconditioner (Sec. 4.4), stopping on the true
+    F-AMS two-stage step as preconditioner (Sec. 4.6), stopping on the true
     relative residual ||q - A p|| / ||q|| (p0 = 0).
 """
 from __future__ import annotations

@@ -2,7 +2,7 @@
 
 Test infrastructure only (see the package docstring).
 
-The paper states (Sec. 1, Sec. 3, Sec. 3.2, Sec. 4.5) that after any stage
+The paper states (Sec. 1, Sec. 3, Sec. 3.2, Sec. 4.6) that after any stage
 that uses the finite-volume restriction R^FV -- the 0/1 matrix whose row K
 marks the fine cells of primal block K -- the fine-scale fluxes can be made
 mass conservative, but gives no algorithm.  The reconstruction here

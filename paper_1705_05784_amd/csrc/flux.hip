@@ -1,6 +1,6 @@
 // Conservative fine-scale flux reconstruction (Sec. 3.2: a stage with the
 // finite-volume restriction R^FV makes a mass-conservative fine-scale flux
-// field available; Sec. 4.5).  The paper gives no algorithm; this is the
+// field available; Sec. 4.6).  The paper gives no algorithm; this is the
 // standard multiscale finite-volume reconstruction:
 //
 //  1. FV stage: A_FV = R^FV A P (dense; R^FV sums the cells of a primal

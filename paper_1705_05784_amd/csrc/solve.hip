@@ -1,5 +1,5 @@
 // The F-AMS iteration (Table 1) on the GPU, as a Richardson loop or as the
-// right preconditioner of restarted GMRES (Sec. 4.4-4.5).
+// right preconditioner of restarted GMRES (Sec. 4.6).
 //
 // Stage (Table 1 steps 5-7) applied to a residual r:
 //   r_c = R r;  x_c = A_c^{-1} r_c;  dp1 = P x_c;       (multiscale stage)
