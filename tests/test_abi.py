@@ -68,3 +68,28 @@ def test_invalid_arguments_rejected():
         fams.grid_structured(0, 1, 1, 1, 1, 1)
     with pytest.raises(fams.FamsError):
         fams.footprint(0, 1, 1)
+
+
+def test_setup_options_validated_before_any_device_work():
+    """Out-of-range setup options are refused with FAMS_ERR_INVALID_ARG before
+    the library touches a pointer or the device (the CSR and grid pointers
+    here are never dereferenced), and a null handle is refused by the value
+    update and the solve."""
+    import ctypes as C
+    from paper_1705_05784_amd import fams
+    L = fams.lib()
+    dummy = C.c_void_p(16)
+    csr = fams.CSR(100, 100, 500, dummy, dummy, dummy)
+    grid = fams.Grid(10, dummy, dummy, dummy)
+    h = C.c_void_p()
+    for opts in (fams.SetupOpts(0, 0, 0.0, 4096, 1, 0, 3),    # restriction beyond MSMIX
+                 fams.SetupOpts(0, 0, 0.0, 4096, 3, 0, 0),    # smoother beyond 2
+                 fams.SetupOpts(0, 0, 0.0, 4096, -1, 0, 0),
+                 fams.SetupOpts(4, 0, 0.0, 4096, 1, 0, 0),    # no such coupling strategy
+                 fams.SetupOpts(0, 2, 0.0, 4096, 1, 0, 0),    # no such precision
+                 fams.SetupOpts(0, 0, 1.5, 4096, 1, 0, 0)):   # truncation threshold >= 1
+        assert L.fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, None,
+                            C.byref(h)) == -1
+    rec = C.c_int32()
+    assert L.fams_update_values(None, dummy, 0.0, C.byref(rec)) == -1
+    assert L.fams_solve(None, dummy, dummy, 1, None, None) == -1
