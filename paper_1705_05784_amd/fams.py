@@ -150,7 +150,14 @@ def footprint(n, nnz, n_coarse, precision=FP64, restart=30) -> int:
 
 
 class Solver:
-    """An F-AMS setup resident on the GPU (one fams_handle_t)."""
+    """An F-AMS setup resident on the GPU (one fams_handle_t).
+
+    variant: coupling strategy (0 Decoupled, 1 Frac, 2 Rock, 3 Coupled-AMS, or
+    its name); precision: FP64 or MIXED; alpha: truncation threshold of P;
+    smoother: 0 none, 1 (or True) ILU(0), 2 ILU(0) plus the per-medium stage;
+    restriction: RESTRICT_FE (P^T), RESTRICT_FV or RESTRICT_MIX (or "fe",
+    "fv", "mix").  Arrays may be numpy or torch; the handle copies them.
+    """
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
                  precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False,
