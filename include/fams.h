@@ -167,7 +167,9 @@ typedef struct {
 
 /* Upper bound of the device memory a handle for this system will hold
  * (host-only estimate from sizes; used for admission).  max_nrhs and
- * restart size the solve workspace. */
+ * restart size the solve workspace.  It covers the default smoother; with
+ * smoother 2 the handle also holds the ILU(0) factors and sweep schedules of
+ * diag(A^mm, A^ff), about nnz * 20 + n * 100 bytes more. */
 fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t precision,
                              int32_t restart, size_t* bytes_upper_bound);
 
