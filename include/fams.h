@@ -169,7 +169,7 @@ typedef struct {
  * (host-only estimate from sizes; used for admission).  max_nrhs and
  * restart size the solve workspace.  It covers the default smoother; with
  * smoother 2 the handle also holds the ILU(0) factors and sweep schedules of
- * diag(A^mm, A^ff), about nnz * 20 + n * 100 bytes more. */
+ * diag(A^mm, A^ff), up to about nnz * 24 + n * 400 bytes more. */
 fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t precision,
                              int32_t restart, size_t* bytes_upper_bound);
 
