@@ -198,3 +198,54 @@ def test_truncation_rule():
     assert np.allclose(T[1], [0, 0, 0, 0.01], atol=1e-15)      # only the largest survives
     assert np.array_equal(T[2], [0.3, 0.3, 0.4, 0.0])           # untouched row
     assert np.array_equal(T[3], [1.0, 0, 0, 0])
+
+
+# ---- Coupled-AMS merge under a size cap (Sec. 3.1) ---------------------------
+
+def _cut_lumped(Ad, pairs):
+    """A with the couplings in `pairs` taken out and added to the diagonal."""
+    B = Ad.copy()
+    for i, j in pairs:
+        B[i, i] += B[i, j]
+        B[i, j] = 0.0
+    return B
+
+
+@pytest.mark.parametrize("cap", [12, 20])
+def test_coupled_merge_cap(cap):
+    """With a merge cap that binds: every block that spans both media holds
+    at most `cap` cells; a cross-media coupling between equal classes is cut
+    only when the two blocks it joins could not have been united under the
+    cap (their sizes add up to more than cap: blocks only grow, so this holds
+    at the end if it held when the coupling was refused); P still gives a
+    partition of unity on a Neumann A; and P equals App. A.4's Coupled-AMS
+    block formulas evaluated densely on A with the cut couplings lumped into
+    the diagonal."""
+    s, spec = small_case("3d", neumann=True)
+    wb, _, vertex, _ = _grid(s, spec)
+    A = s.csr()
+    nm = s.n_matrix
+    _, free = fams.prolongation(A, wb, vertex, nm, fams.COUPLED, merge_cap=10**9,
+                                return_blocks=True)
+    med = np.arange(s.n) >= nm
+    sizes_free = np.bincount(free["comp"][free["comp"] >= 0])
+    assert sizes_free.max() > cap          # the cap binds on this case
+    P, info = fams.prolongation(A, wb, vertex, nm, fams.COUPLED, merge_cap=cap,
+                                return_blocks=True)
+    comp = info["comp"]
+    sizes = np.bincount(comp[comp >= 0])
+    for K in np.unique(comp[comp >= 0]):
+        cells = np.nonzero(comp == K)[0]
+        if med[cells].any() and (~med[cells]).any():
+            assert len(cells) <= cap
+    r = np.repeat(np.arange(s.n), np.diff(A.indptr))
+    c = A.indices
+    cross = (med[r] != med[c]) & (wb[r] == wb[c]) & (wb[r] != 3) & (r != c)
+    cut = cross & (comp[r] != comp[c])
+    assert cut.any()
+    for i, j in zip(r[cut], c[cut]):
+        assert sizes[comp[i]] + sizes[comp[j]] > cap
+    assert np.abs(np.asarray(P.sum(axis=1)).ravel() - 1).max() < 1e-12
+    Acut = _cut_lumped(A.toarray(), zip(r[cut], c[cut]))
+    P_ref = appendix_a(Acut, wb, nm, vertex, fams.COUPLED)
+    assert np.abs(P.toarray() - P_ref).max() < 1e-11

@@ -67,3 +67,12 @@ def make_small(kind: str, seed: int = 0, **kw):
         return build_system(nx, ny, nz, lnk, plates, kw.get("contrast", 1e3),
                             neumann=kw.get("neumann", False), meta=dict(kind=kind, seed=seed))
     raise ValueError(kind)
+
+
+def config_rhs(sysm, config_id: int, nrhs: int, instance: int = 0) -> np.ndarray:
+    """Right-hand sides of a config that reuses one setup (config 5: 64 of
+    them): the Dirichlet boundary term plus 2-8 point rates in matrix cells
+    summing to zero, as in the serving requests.  Row k is right-hand side k."""
+    from .serving import well_rhs
+    rng = _rng(config_id, 10**6 + instance)
+    return np.stack([well_rhs(sysm, int(rng.integers(2, 9)), rng) for _ in range(nrhs)])
