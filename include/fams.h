@@ -161,17 +161,22 @@ typedef struct {
                                  too wide for the wavefront solver) */
   double local_subst_flops;   /* arithmetic of the local substitutions done by
                                  the wavefront solver, all levels */
+  int64_t peak_device_bytes;  /* most device memory the handle has held at once
+                                 (setup, solves and flux reconstructions so far) */
 } fams_setup_info_t;
 
 /* ---- lifecycle -------------------------------------------------------- */
 
 /* Upper bound of the device memory a handle for this system will hold
- * (host-only estimate from sizes; used for admission).  max_nrhs and
- * restart size the solve workspace.  It covers the default smoother; with
- * smoother 2 the handle also holds the ILU(0) factors and sweep schedules of
- * diag(A^mm, A^ff), up to about nnz * 24 + n * 400 bytes more. */
+ * through its setup and its solves (host-only estimate from sizes; used for
+ * admission): `restart` sizes the GMRES work space and `max_nrhs` the
+ * lock-step work space of fams_solve with several right-hand sides (groups of
+ * up to 16).  Both smoother settings are covered.  Not covered: the flux
+ * reconstruction's work space (two dense n_coarse^2 FP64 matrices and the
+ * primal blocks' banded factors).  Errors: FAMS_ERR_INVALID_ARG for
+ * non-positive sizes, restart or max_nrhs. */
 fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t precision,
-                             int32_t restart, size_t* bytes_upper_bound);
+                             int32_t restart, int32_t max_nrhs, size_t* bytes_upper_bound);
 
 /* Setup (Table 1 step 4 and the coarse system of step 5, plus the ILU(0)
  * factors): ranks and local blocks, basis functions in wirebasket order
@@ -195,8 +200,14 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* grid,
 fams_status_t fams_update_values(fams_handle_t h, const double* val, double threshold,
                                  int32_t* basis_recomputed);
 
-/* Solve A p = q for nrhs right-hand sides (device, column-major [n x nrhs]).
- * info (host, [nrhs], may be NULL).  Returns the worst status. */
+/* Solve A p = q for nrhs right-hand sides (device, column-major [n x nrhs];
+ * pageable host memory is refused with FAMS_ERR_INVALID_ARG).  Several
+ * right-hand sides reuse the setup in lock-step groups of up to 16 (as many
+ * as the free device memory holds): every pass over A, P, R, the ILU(0)
+ * factors and A_c^{-1} serves the whole group, while each right-hand side
+ * keeps its own outer iteration and stopping test (Sec. 4.6 reuses one setup
+ * for a sequence of solves).  info (host, [nrhs], may be NULL).  Returns the
+ * worst status. */
 fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nrhs,
                          const fams_solve_opts_t* opts, fams_info_t* info);
 
@@ -236,8 +247,9 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
  *   op 1: out = a^{-1} by blocked Gauss-Jordan without pivoting (A_c, SPD);
  *         FAMS_ERR_SINGULAR_COARSE if a pivot is not positive
  *   op 2: out = a^{-1} by LU with partial pivoting and triangular solves
- *   op 3: out = a^{-1} column by column with the one-workgroup LU solve
- *         (the FV stage's solver; n <= 12288)
+ *   op 3: out = a^{-1} column by column with the dataflow LU solve (the FV
+ *         stage's solver: one wavefront per 64-row chunk, chunks handed over
+ *         through flags with bounded waits)
  *   op 4: out = the packed LU factors of P a (unit L below the diagonal, U on
  *         and above it, rows interchanged as LAPACK getrf leaves them)
  * For tests of those kernels; blocking. */

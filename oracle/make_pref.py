@@ -16,7 +16,6 @@ well under the 1e-6 pressure-error target it is used for.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,13 +29,6 @@ CACHE = os.path.join(HERE, "_pref")
 GRIDS = {2: ((10, 10, 10), 8, 8), 3: ((10, 10, 10), 10, 10), 5: ((10, 10, 10), 10, 10)}
 
 
-def system_key(row_ptr, col, val, q) -> str:
-    m = hashlib.sha256()
-    for a in (row_ptr, col, val, q):
-        m.update(np.ascontiguousarray(a).tobytes())
-    return m.hexdigest()[:24]
-
-
 def cache_path(key: str) -> str:
     return os.path.join(CACHE, key + ".npy")
 
@@ -44,18 +36,22 @@ def cache_path(key: str) -> str:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--config", type=int, default=5)
-    ap.add_argument("--rhs", type=int, default=0, help="index into the config's right-hand sides")
+    ap.add_argument("--rhs", type=int, default=0,
+                    help="index into the config's right-hand sides; -1: the boundary term alone")
+    ap.add_argument("--flux", action="store_true",
+                    help="also reconstruct the conservative flux and store its balance")
     ap.add_argument("--contrast", type=float, default=None)
     ap.add_argument("--rtol", type=float, default=1e-11)
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     from workloads import make_config
     from workloads.configs import config_rhs
+    from workloads.edfm import system_key
     from oracle import fams, grids
 
     t0 = time.perf_counter()
     s = make_config(args.config, contrast=args.contrast)
-    q = config_rhs(s, args.config, args.rhs + 1)[args.rhs]
+    q = s.q if args.rhs < 0 else config_rhs(s, args.config, args.rhs + 1)[args.rhs]
     key = system_key(s.row_ptr, s.col, s.val, q)
     coarse, d_min, r_z = GRIDS[args.config]
     wb, primal, vertex, _ = grids.full_grid(s, coarse, d_min, r_z)
@@ -64,11 +60,16 @@ def main():
     t2 = time.perf_counter()
     p, info = F.gmres(q, rtol=args.rtol, max_iter=2000)
     t3 = time.perf_counter()
+    balance = None
+    if args.flux:
+        from oracle import flux
+        balance = float(flux.reconstruct_flux(F.A, F.P, primal, vertex, q, p)[3])
     os.makedirs(CACHE, exist_ok=True)
     np.save(cache_path(key), p.astype(np.float32))
     meta = dict(config=args.config, rhs=args.rhs, contrast=args.contrast, key=key, n=int(s.n),
                 rtol=args.rtol, status=int(info["status"]), iterations=int(info["iterations"]),
                 rel_residual=float(info["rel_residual"]), variant="decoupled", alpha=0.0,
+                balance=balance,
                 input_s=t1 - t0, setup_s=t2 - t1, solve_s=t3 - t2)
     with open(os.path.join(CACHE, key + ".json"), "w") as f:
         json.dump(meta, f, indent=1)

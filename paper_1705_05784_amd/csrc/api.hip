@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
+#include <initializer_list>
 #include <memory>
 #include <string>
 #include <vector>
@@ -213,6 +215,29 @@ __global__ void k_d2f_api(int64_t n, const double* a, float* b) {
   if (i < n) b[i] = static_cast<float>(a[i]);
 }
 
+}  // namespace
+
+// an array the kernels read or write must be memory the device can address
+// (device, managed or pinned host memory); pageable host memory is refused
+// before any work is issued
+bool device_addressable(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.devicePointer != nullptr || a.isManaged != 0;
+}
+
+bool all_addressable(std::initializer_list<const void*> ps) {
+  for (const void* p : ps)
+    if (!device_addressable(p)) return false;
+  return true;
+}
+
+namespace {
+
 fams_status_t fail(const Error& e) {
   g_last_error = e.what();
   return e.status;
@@ -232,6 +257,12 @@ fams_status_t guard(F&& f) {
     return FAMS_ERR_DEVICE;
   }
 }
+
+}  // namespace
+
+fams_status_t guarded(const std::function<fams_status_t()>& f) { return guard(f); }
+
+namespace {
 
 // A_c = R A P and its inverse, and the FP32 copy of A (precision form): the
 // parts of the setup that follow the values of A for a fixed basis
@@ -391,19 +422,32 @@ const char* fams_status_string(fams_status_t s) {
 const char* fams_last_error(void) { return fams::g_last_error.c_str(); }
 
 fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t precision,
-                             int32_t restart, size_t* bytes) {
-  if (!bytes || n <= 0 || nnz <= 0 || n_coarse <= 0) return FAMS_ERR_INVALID_ARG;
+                             int32_t restart, int32_t max_nrhs, size_t* bytes) {
+  if (!bytes || n <= 0 || nnz <= 0 || n_coarse <= 0 || max_nrhs < 1 || restart < 1)
+    return FAMS_ERR_INVALID_ARG;
   const double zp = 16.0 * n;  // nnz(P) bound used for admission (<= 16 per row)
+  const double nc = static_cast<double>(n_coarse);
+  const bool mixed = precision == FAMS_PREC_MIXED;
   double b = 0;
   b += nnz * (4 + 8 + 8) + (n + 1) * 4 + n * (4 + 4 + 4);       // A, ILU, diag, primal
   b += nnz * 8.0 + n;                                            // basis values, classes
-  b += 2 * zp * (4 + 8) + (n + n_coarse + 2) * 4;                // P and R
-  b += 2.0 * 8 * n_coarse * n_coarse;                            // A_c and its inverse
-  b += 2.0 * 8 * n_coarse * n_coarse;                            // FV operator and inverse
+  b += 2 * zp * (4 + 8) + (n + 2 * nc + 2) * 4;                  // P and R
+  b += 2.0 * 8 * nc * nc;                                        // A_c and its inverse
+  b += 2.0 * 8 * 256 * nc + 8.0 * 256 * 256;                     // block Gauss-Jordan panels
   b += 3.0 * zp * (4 + 8) + 8.0 * (n + 1);                       // A P
   b += 48.0 * 8 * n;                                             // local solutions (setup)
-  b += 8.0 * n * (6 + 2 * std::max(restart, 1) + 1);             // iteration vectors
-  if (precision == FAMS_PREC_MIXED) b += nnz * 8.0 + 2 * zp * 4 + 16.0 * n;
+  b += 2.0 * (4 + 32 + 32 + 4 + 4 + 72 + 8) * n + 24.0 * n;     // sweep schedules, levels
+  b += 240.0 * n;                                                // factorisation records
+  b += nnz * 24.0 + n * 400.0;                                   // per-medium stage (smoother 2)
+  b += 8.0 * n * (6 + 2 * restart + 1);                          // iteration vectors
+  if (mixed) b += nnz * 8.0 + 2 * zp * 4 + 16.0 * n;
+  if (max_nrhs > 1) {  // lock-step groups of K right-hand sides
+    int K = 2;
+    while (K < 16 && K < max_nrhs) K *= 2;
+    const double nk = static_cast<double>(n) * K;
+    b += nk * 8 * (10 + 2 * restart + 1) + (mixed ? nk * 4 * 6 : 0.0);
+    b += (2 + 34) * nc * K * 8 + 512.0 * (restart + 2) * K * 8;
+  }
   b *= 1.10;
   *bytes = static_cast<size_t>(b) + (64u << 20);
   return FAMS_OK;
@@ -423,6 +467,8 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
       !(o->trunc_alpha >= 0.0 && o->trunc_alpha < 1.0) || o->merge_cap < 1 ||
       o->restriction < FAMS_RESTRICT_FE || o->restriction > FAMS_RESTRICT_MIX ||
       o->smoother < 0 || o->smoother > 2)
+    return FAMS_ERR_INVALID_ARG;
+  if (!fams::all_addressable({A->row_ptr, A->col_idx, A->val, G->wb_type, G->primal, G->vertex}))
     return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     std::unique_ptr<fams_handle_s> h(new fams_handle_s());
@@ -446,6 +492,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->nc = static_cast<int>(G->n_coarse);
     fams::setup_impl(h.get(), A, G);
     h->info.device_bytes = h->alloc.live_bytes + (h->blk ? h->blk->alloc.live_bytes : 0);
+    h->info.peak_device_bytes = h->alloc.peak_bytes + (h->blk ? h->blk->alloc.peak_bytes : 0);
     *out = h.release();
     return FAMS_OK;
   });
@@ -453,7 +500,8 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
 
 fams_status_t fams_update_values(fams_handle_t h, const double* val, double threshold,
                                  int32_t* basis_recomputed) {
-  if (!h || !val || !basis_recomputed) return FAMS_ERR_INVALID_ARG;
+  if (!h || !val || !basis_recomputed || !fams::device_addressable(val))
+    return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     int rec = 0;
     fams::update_impl(h, val, threshold, &rec);
@@ -469,9 +517,25 @@ fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nr
   if (o->outer != FAMS_RICHARDSON && o->outer != FAMS_GMRES) return FAMS_ERR_INVALID_ARG;
   if (o->outer == FAMS_GMRES && (o->restart < 1 || o->restart > 60)) return FAMS_ERR_INVALID_ARG;
   if (!(o->rtol >= 0.0) || o->max_iter < 0) return FAMS_ERR_INVALID_ARG;
+  if (nrhs > 0 && !fams::all_addressable({q, p})) return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     fams_status_t worst = FAMS_OK;
     const int64_t n = h->n;
+    if (nrhs > 1) {  // several right-hand sides: lock-step groups on the one setup
+      std::vector<fams_info_t> inf(nrhs);
+      for (int r = 0; r < nrhs; ++r) {
+        const double qq = fams::dev_dot(h, q + r * n, q + r * n, n);
+        if (!std::isfinite(qq)) {
+          inf[r].status = FAMS_ERR_INVALID_ARG;
+          if (info) info[r] = inf[r];
+          return FAMS_ERR_INVALID_ARG;
+        }
+      }
+      worst = fams::solve_block(h, q, p, nrhs, o, inf.data());
+      if (info)
+        for (int r = 0; r < nrhs; ++r) info[r] = inf[r];
+      return worst;
+    }
     for (int r = 0; r < nrhs; ++r) {
       const double* qr = q + r * n;
       double* pr = p + r * n;
@@ -492,7 +556,9 @@ fams_status_t fams_solve(fams_handle_t h, const double* q, double* p, int32_t nr
 
 fams_status_t fams_reconstruct_flux(fams_handle_t h, const double* q, const double* p,
                                     double* flux, double* p_fv, double* imbalance) {
-  if (!h || !q || !p || !flux) return FAMS_ERR_INVALID_ARG;
+  if (!h || !q || !p || !flux || !fams::all_addressable({q, p, flux}) ||
+      (p_fv && !fams::device_addressable(p_fv)))
+    return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     double imb = fams::reconstruct_flux(h, q, p, flux, p_fv);
     if (imbalance) *imbalance = imb;
@@ -503,7 +569,8 @@ fams_status_t fams_reconstruct_flux(fams_handle_t h, const double* q, const doub
 fams_status_t fams_get_setup_info(fams_handle_t h, fams_setup_info_t* info) {
   if (!h || !info) return FAMS_ERR_INVALID_ARG;
   *info = h->info;
-  info->device_bytes = h->alloc.live_bytes;
+  info->device_bytes = h->alloc.live_bytes + (h->blk ? h->blk->alloc.live_bytes : 0);
+  info->peak_device_bytes = h->alloc.peak_bytes + (h->blk ? h->blk->alloc.peak_bytes : 0);
   return FAMS_OK;
 }
 
@@ -559,7 +626,7 @@ fams_status_t fams_get_ilu(fams_handle_t h, double* lu_val) {
 }
 
 fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z) {
-  if (!h || !r || !z) return FAMS_ERR_INVALID_ARG;
+  if (!h || !r || !z || !fams::all_addressable({r, z})) return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     fams::apply_stage_fp64(h, r, z);
     return FAMS_OK;
@@ -567,7 +634,8 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z) {
 }
 
 fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out) {
-  if (op < 0 || op > 4 || n <= 0 || n > 65536 || !a || !out) return FAMS_ERR_INVALID_ARG;
+  if (op < 0 || op > 4 || n <= 0 || n > 65536 || !a || !out || !fams::all_addressable({a, out}))
+    return FAMS_ERR_INVALID_ARG;
   return fams::guard([&]() -> fams_status_t {
     std::unique_ptr<fams_handle_s> h(new fams_handle_s());
     fams::Handle* H = h.get();

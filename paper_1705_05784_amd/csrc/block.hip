@@ -1,0 +1,841 @@
+// Several right-hand sides on one setup, iterated in lock-step.
+//
+// The paper builds the F-AMS operators once per pressure system and reuses
+// them for every solve with that system (Sec. 4.6); Table 1's stage is linear
+// in the residual, so K right-hand sides can share every pass over the
+// operators.  Block vectors hold the K values of a row next to each other
+// (x[i * K + r]): the fine operator, P, R, the ILU(0) factors and the dense
+// A_c^{-1} are read once per stage for all K, and the K lanes of a row
+// gather the same neighbours.  Each right-hand side keeps its own outer
+// iteration (GMRES with its own Hessenberg matrix, Givens rotations, restart
+// and stopping test, or the Table 1 loop): a right-hand side that has met its
+// stopping test is masked out (its updates are multiplied by zero) while the
+// others continue, so every column follows the same iteration as a solve of
+// its own.  Right-hand sides are taken in groups of K in {2, 4, 8, 16}, as
+// many as the device memory holds.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace fams {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kRedBlocks = 2048;  // workgroups of the multi-dot passes
+
+// ---- layout ------------------------------------------------------------------
+// Q[i * K + r] = q[r * n + i] for r < nr, 0 for the padding lanes
+template <int K>
+__global__ void k_pack(int n, int nr, const double* q, double* Q) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * K) return;
+  const int i = static_cast<int>(e / K), r = static_cast<int>(e % K);
+  Q[e] = r < nr ? q[static_cast<int64_t>(r) * n + i] : 0.0;
+}
+
+template <int K>
+__global__ void k_unpack(int n, int nr, const double* Q, double* q) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * K) return;
+  const int i = static_cast<int>(e / K), r = static_cast<int>(e % K);
+  if (r < nr) q[static_cast<int64_t>(r) * n + i] = Q[e];
+}
+
+// ---- operators on block vectors ------------------------------------------------
+// Workgroups are dealt to the eight XCDs in turn; for the row-wise kernels
+// the grid is padded to a multiple of eight and workgroup b takes the b/8-th
+// part of XCD (b % 8)'s contiguous eighth of the rows, so the neighbours a
+// row gathers (the previous and next rows, lines and planes) were mostly
+// brought into the same XCD's L2 by its own earlier workgroups.
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t per = gridDim.x / kXcd;
+  return static_cast<int64_t>(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+}
+
+inline unsigned xcd_grid(int64_t blocks) {
+  return static_cast<unsigned>((blocks + kXcd - 1) / kXcd * kXcd);
+}
+
+// Y = M X (kResid: Y = B - M X, B may be null or alias Y): one thread per
+// (row, right-hand side); the K threads of a row read its entries once
+// (same addresses) and gather K consecutive values per neighbour
+template <class TV, class TX, class TB, class TY, int K, bool kResid>
+__global__ void __launch_bounds__(256)
+k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const TB* B, TY* Y) {
+  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * K) return;
+  const int i = static_cast<int>(e / K), r = static_cast<int>(e % K);
+  double s = 0.0;
+  const int p0 = rp[i], p1 = rp[i + 1];
+  // the row's entries eight at a time: their columns and values first, then
+  // all their gathers, so a row costs about two memory round trips
+  for (int pb = p0; pb < p1; pb += 8) {
+    int c[8];
+    TV v[8];
+    TX x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (pb + k < p1) {
+        c[k] = ci[pb + k];
+        v[k] = val[pb + k];
+      }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (pb + k < p1) x[k] = X[static_cast<int64_t>(c[k]) * K + r];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (pb + k < p1) s += static_cast<double>(v[k]) * static_cast<double>(x[k]);
+  }
+  if constexpr (kResid) s = (B ? static_cast<double>(B[e]) : 0.0) - s;
+  Y[e] = static_cast<TY>(s);
+}
+
+// sum over the lanes of a workgroup of 256 that hold the same r = tid % K
+// (fixed order: shuffles inside each wavefront, then the four wavefronts in
+// order); the result is valid in threads 0..K-1
+template <int K>
+__device__ double group_sum(double v) {
+  __shared__ double s[4][K];
+  for (int o = 32; o >= K; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l < K) s[w][l] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < K)
+    for (int q = 0; q < 4; ++q) t += s[q][threadIdx.x];
+  return t;
+}
+
+// Y[row * K + r] = sum_p M[row, p] X[col_p * K + r] for the fat rows of R =
+// P^T: one workgroup per row, 256 / K groups of K lanes stride over the
+// row's entries, then a fixed-order sum across the groups
+template <class TV, class TX, int K>
+__global__ void __launch_bounds__(256)
+k_brestrict(int nrows, const int* rp, const int* ci, const TV* val, const TX* X, double* Y) {
+  const int row = blockIdx.x;
+  const int r = threadIdx.x % K, g = threadIdx.x / K;
+  constexpr int G = 256 / K;
+  double s = 0.0;
+  const int p1 = rp[row + 1];
+  for (int pb = rp[row] + g; pb < p1; pb += 4 * G) {
+    int c[4];
+    TV v[4];
+    TX x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (pb + k * G < p1) {
+        c[k] = ci[pb + k * G];
+        v[k] = val[pb + k * G];
+      }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (pb + k * G < p1) x[k] = X[static_cast<int64_t>(c[k]) * K + r];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (pb + k * G < p1) s += static_cast<double>(v[k]) * static_cast<double>(x[k]);
+  }
+  s = group_sum<K>(s);
+  if (threadIdx.x < K) Y[static_cast<int64_t>(row) * K + threadIdx.x] = s;
+}
+
+// coarse solve X = A_c^{-1} Y with the dense inverse (column-major nc x nc):
+// a workgroup takes 256 rows and one chunk of `w` columns, stages the chunk's
+// right-hand sides in LDS 64 columns at a time and keeps K sums per row in
+// registers; partial results per chunk are added in chunk order afterwards
+template <int K>
+__global__ void __launch_bounds__(256)
+k_bcoarse_part(int nc, int w, const double* M, const double* Y, double* part) {
+  __shared__ double ys[64 * K];
+  const int I = blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * w, c1 = min(nc, c0 + w);
+  double acc[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[r] = 0.0;
+  for (int cb = c0; cb < c1; cb += 64) {
+    const int ce = min(64, c1 - cb);
+    __syncthreads();
+    for (int t = threadIdx.x; t < 64 * K; t += 256)
+      ys[t] = t < ce * K ? Y[static_cast<int64_t>(cb) * K + t] : 0.0;
+    __syncthreads();
+    if (I < nc) {
+      const double* col = M + static_cast<int64_t>(cb) * nc + I;
+#pragma unroll 16
+      for (int c = 0; c < ce; ++c) {
+        const double a = col[static_cast<int64_t>(c) * nc];
+#pragma unroll
+        for (int r = 0; r < K; ++r) acc[r] += a * ys[c * K + r];
+      }
+    }
+  }
+  if (I < nc) {
+    double* o = part + (static_cast<int64_t>(blockIdx.y) * nc + I) * K;
+#pragma unroll
+    for (int r = 0; r < K; ++r) o[r] = acc[r];
+  }
+}
+
+__global__ void k_bcoarse_red(int64_t nk, int nch, const double* part, double* X) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nk) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[static_cast<int64_t>(c) * nk + e];
+  X[e] = s;
+}
+
+template <class TA, class TY>
+__global__ void k_bcast(int64_t n, const TA* a, TY* y) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<TY>(a[i]);
+}
+
+template <class TA, class TB, class TY>
+__global__ void k_badd(int64_t n, const TA* a, const TB* b, TY* y) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<TY>(static_cast<double>(a[i]) + static_cast<double>(b[i]));
+}
+
+// ---- reductions and Krylov updates per right-hand side ---------------------------
+// part[(b * pstride + v) * K + r] = block b's share of sum_i V_v[i, r] w[i, r]
+// for v < nv, in batches of kDotBatch vectors so that w is read once per batch
+constexpr int kDotBatch = 8;
+
+template <int K>
+__device__ void store_dots(const double* acc, int nb, int v0, double* part, int pstride) {
+#pragma unroll
+  for (int u = 0; u < kDotBatch; ++u) {
+    if (u >= nb) break;
+    const double s = group_sum<K>(acc[u]);
+    if (threadIdx.x < K)
+      part[(static_cast<int64_t>(blockIdx.x) * pstride + v0 + u) * K + threadIdx.x] = s;
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_bmdot_part(int64_t nk, int nv, const double* V, int64_t ldv, const double* w, double* part,
+             int pstride) {
+  for (int v0 = 0; v0 < nv; v0 += kDotBatch) {
+    const int nb = min(kDotBatch, nv - v0);
+    double acc[kDotBatch];
+#pragma unroll
+    for (int u = 0; u < kDotBatch; ++u) acc[u] = 0.0;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nk;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+      const double we = w[e];
+#pragma unroll
+      for (int u = 0; u < kDotBatch; ++u)
+        if (u < nb) acc[u] += V[(v0 + u) * ldv + e] * we;
+    }
+    store_dots<K>(acc, nb, v0, part, pstride);
+  }
+}
+
+// the first Gram-Schmidt correction and the second pass's dots in one pass
+// over the rows: w <- w - sum_v coef[r, v] V_v, then the partial dots of the
+// new w with V_0..V_{nv-1}; each V value is loaded once and kept in a
+// register between the two uses (nv <= kFuseMax)
+constexpr int kFuseMax = 4 * kDotBatch;
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_bmaxpy_mdot(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef, int cstride,
+              double* w, double* part, int pstride) {
+  double acc[kFuseMax];
+#pragma unroll
+  for (int v = 0; v < kFuseMax; ++v) acc[v] = 0.0;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nk;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double* c = coef + static_cast<int64_t>(e % K) * cstride;
+    double vv[kFuseMax];
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < kFuseMax; ++v)
+      if (v < nv) {
+        vv[v] = V[v * ldv + e];
+        s += c[v] * vv[v];
+      }
+    const double we = w[e] - s;
+    w[e] = we;
+#pragma unroll
+    for (int v = 0; v < kFuseMax; ++v)
+      if (v < nv) acc[v] += vv[v] * we;
+  }
+#pragma unroll
+  for (int a = 0; a < kFuseMax / kDotBatch; ++a) {
+    if (a * kDotBatch >= nv) break;
+    store_dots<K>(acc + a * kDotBatch, min(kDotBatch, nv - a * kDotBatch), a * kDotBatch, part,
+                  pstride);
+  }
+}
+
+// the second correction and the norm: w <- w - sum_v coef[r, v] V_v, then
+// the partial sums of w^2 per right-hand side
+template <int K>
+__global__ void __launch_bounds__(256)
+k_bmaxpy_norm(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef, int cstride,
+              double* w, double* part) {
+  double acc = 0.0;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nk;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double* c = coef + static_cast<int64_t>(e % K) * cstride;
+    double s = 0.0;
+    for (int v = 0; v < nv; ++v) s += c[v] * V[v * ldv + e];
+    const double we = w[e] - s;
+    w[e] = we;
+    acc += we * we;
+  }
+  const double t = group_sum<K>(acc);
+  if (threadIdx.x < K) part[static_cast<int64_t>(blockIdx.x) * K + threadIdx.x] = t;
+}
+
+// out[r * ostride + v] = sum over blocks of the partials of (v, r): one
+// workgroup per (v, r), strided partial sums then a fixed tree
+__global__ void __launch_bounds__(256)
+k_breduce(int nblk, int K, const double* part, int pstride, double* out, int ostride) {
+  const int v = blockIdx.x, r = blockIdx.y;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+    s += part[(static_cast<int64_t>(b) * pstride + v) * K + r];
+  __shared__ double t[4];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  __syncthreads();
+  if (threadIdx.x % 64 == 0) t[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[static_cast<int64_t>(r) * ostride + v] = ((t[0] + t[1]) + t[2]) + t[3];
+}
+
+// w[i, r] += sign * sum_{v < nv} coef[r * cstride + v] V_v[i, r]
+template <int K>
+__global__ void k_bmaxpy(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef,
+                         int cstride, double sign, double* w) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nk) return;
+  const int r = static_cast<int>(e % K);
+  const double* c = coef + static_cast<int64_t>(r) * cstride;
+  double s = 0.0;
+  for (int v = 0; v < nv; ++v) s += c[v] * V[v * ldv + e];
+  w[e] += sign * s;
+}
+
+// y[i, r] = x[i, r] / d[r * dstride] for the right-hand sides in `mask`,
+// 0 for the others
+template <int K>
+__global__ void k_bscale(int64_t nk, const double* x, const double* d, int dstride, unsigned mask,
+                         double* y) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nk) return;
+  const int r = static_cast<int>(e % K);
+  y[e] = (mask >> r & 1u) ? x[e] / d[static_cast<int64_t>(r) * dstride] : 0.0;
+}
+
+// p[i, r] += z[i, r] for the right-hand sides in `mask`
+template <int K>
+__global__ void k_baxpy_mask(int64_t nk, unsigned mask, const double* z, double* p) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nk) return;
+  if (mask >> (e % K) & 1u) p[e] += z[e];
+}
+
+__global__ void k_bsqrt(int K, double* d, int stride) {
+  const int r = threadIdx.x;
+  if (r < K) d[static_cast<int64_t>(r) * stride] = sqrt(d[static_cast<int64_t>(r) * stride]);
+}
+
+// per right-hand side GMRES state in one array: S = base + r * stride
+struct BState {
+  int m, stride;
+  int H, cs, sn, g, y, hcol, out, beta;  // offsets inside one right-hand side's record
+  static BState make(int m) {
+    BState s{};
+    s.m = m;
+    int o = 0;
+    s.H = o; o += (m + 1) * m;
+    s.cs = o; o += m;
+    s.sn = o; o += m;
+    s.g = o; o += m + 1;
+    s.y = o; o += m;
+    s.hcol = o; o += m + 2;
+    s.out = o; o += 2;
+    s.beta = o; o += 2;
+    s.stride = o;
+    return s;
+  }
+};
+
+__global__ void k_bgmres_init(int K, BState s, double* base) {
+  const int r = threadIdx.x;
+  if (r >= K) return;
+  double* S = base + static_cast<int64_t>(r) * s.stride;
+  for (int k = 0; k <= s.m; ++k) S[s.g + k] = 0.0;
+  S[s.g] = S[s.beta];
+}
+
+// hcol += y (the second Gram-Schmidt pass), v < nv
+__global__ void k_bvadd(int K, int nv, BState s, double* base) {
+  const int r = blockIdx.x, v = threadIdx.x;
+  if (r < K && v < nv) {
+    double* S = base + static_cast<int64_t>(r) * s.stride;
+    S[s.hcol + v] += S[s.y + v];
+  }
+}
+
+// Hessenberg column j, the previous rotations, the new rotation and the
+// residual estimate, for every right-hand side in `mask`
+__global__ void k_bgivens(int K, BState s, double* base, int j, unsigned mask) {
+  const int r = threadIdx.x;
+  if (r >= K || !(mask >> r & 1u)) return;
+  double* S = base + static_cast<int64_t>(r) * s.stride;
+  const int m = s.m;
+  double* col = S + s.H + static_cast<int64_t>(j) * (m + 1);
+  const double* hcol = S + s.hcol;
+  double* cs = S + s.cs;
+  double* sn = S + s.sn;
+  double* g = S + s.g;
+  for (int i = 0; i <= j + 1; ++i) col[i] = hcol[i];
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  const double c = den == 0.0 ? 1.0 : col[j] / den;
+  const double sg = den == 0.0 ? 0.0 : col[j + 1] / den;
+  cs[j] = c;
+  sn[j] = sg;
+  col[j] = c * col[j] + sg * col[j + 1];
+  col[j + 1] = 0.0;
+  g[j + 1] = -sg * g[j];
+  g[j] = c * g[j];
+  S[s.out] = fabs(g[j + 1]);
+  S[s.out + 1] = hcol[j + 1];
+}
+
+struct KK {
+  int v[16];
+};
+
+// y = H(0:k, 0:k)^{-1} g(0:k) with each right-hand side's own k; y beyond k
+// is zero so that one update over max k columns serves all
+__global__ void k_bbacksolve(int K, BState s, double* base, KK kk) {
+  const int r = threadIdx.x;
+  if (r >= K) return;
+  double* S = base + static_cast<int64_t>(r) * s.stride;
+  const int m = s.m, k = kk.v[r];
+  double* y = S + s.y;
+  for (int i = k; i < m; ++i) y[i] = 0.0;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = S[s.g + i];
+    for (int c = i + 1; c < k; ++c) t -= S[s.H + static_cast<int64_t>(c) * (m + 1) + i] * y[c];
+    y[i] = t / S[s.H + static_cast<int64_t>(i) * (m + 1) + i];
+  }
+}
+
+// ---- the lock-step iteration -----------------------------------------------------
+struct BWork {
+  int K, m;
+  int64_t nk;
+  double *q, *p, *r, *w, *d1, *z, *rh, *x, *y, *xb, *V, *Z;
+  float *r32, *d1_32, *rh32, *x32, *y32, *xb32;
+  double *rc, *xc, *cpart;
+  int cw, nch;
+  double* part;
+  int nb;
+  double* small;
+  BState st;
+};
+
+size_t block_vectors(int m) { return static_cast<size_t>(10 + 2 * m + 1); }
+
+int coarse_chunk_width(int nc) { return 64 * std::max(1, (nc + 64 * 32 - 1) / (64 * 32)); }
+
+BWork block_work(Handle* h, int K, int m) {
+  BWork k{};
+  const int64_t n = h->n;
+  k.K = K;
+  k.m = m;
+  k.nk = n * K;
+  double* b = h->bwk.get();
+  double** seq[] = {&k.q, &k.p, &k.r, &k.w, &k.d1, &k.z, &k.rh, &k.x, &k.y, &k.xb};
+  for (double** s : seq) {
+    *s = b;
+    b += k.nk;
+  }
+  k.V = b;
+  k.Z = k.V + static_cast<int64_t>(m + 1) * k.nk;
+  if (h->precision == FAMS_PREC_MIXED) {
+    float* f = h->bwk32.get();
+    float** s32[] = {&k.r32, &k.d1_32, &k.rh32, &k.x32, &k.y32, &k.xb32};
+    for (float** s : s32) {
+      *s = f;
+      f += k.nk;
+    }
+  }
+  k.cw = coarse_chunk_width(h->nc);
+  k.nch = (h->nc + k.cw - 1) / k.cw;
+  k.rc = h->bpart.get();
+  k.xc = k.rc + static_cast<int64_t>(h->nc) * K;
+  k.cpart = k.xc + static_cast<int64_t>(h->nc) * K;
+  k.part = h->bred.get();
+  k.nb = static_cast<int>(std::min<int64_t>(kRedBlocks, blocks_for(k.nk, kT)));
+  k.st = BState::make(m);
+  k.small = h->bsmall.get();
+  return k;
+}
+
+size_t block_bytes(Handle* h, int K, int m) {
+  const size_t nk = static_cast<size_t>(h->n) * K;
+  size_t b = block_vectors(m) * nk * sizeof(double);
+  if (h->precision == FAMS_PREC_MIXED) b += 6 * nk * sizeof(float);
+  const int cw = coarse_chunk_width(h->nc);
+  const size_t nch = (h->nc + cw - 1) / cw;
+  b += (2 + nch) * static_cast<size_t>(h->nc) * K * sizeof(double);
+  return b;
+}
+
+void ensure_block_workspace(Handle* h, int K, int m) {
+  if (h->bK == K && h->bm >= m && h->bwk.get()) return;
+  h->bwk.free();
+  h->bwk32.free();
+  h->bpart.free();
+  const size_t nk = static_cast<size_t>(h->n) * K;
+  h->bwk.reset(&h->alloc, block_vectors(m) * nk);
+  if (h->precision == FAMS_PREC_MIXED) h->bwk32.reset(&h->alloc, 6 * nk);
+  const int cw = coarse_chunk_width(h->nc);
+  const size_t nch = (h->nc + cw - 1) / cw;
+  h->bpart.reset(&h->alloc, (2 + nch) * static_cast<size_t>(h->nc) * K);
+  h->bred.reset(&h->alloc, static_cast<size_t>(kRedBlocks) * (m + 2) * K + 16);
+  h->bsmall.reset(&h->alloc, static_cast<size_t>(BState::make(m).stride) * K + 16);
+  h->bK = K;
+  h->bm = m;
+}
+
+// y = b - A x on block vectors ("bspmv_resid" inside the stage, "bresid_outer"
+// for the FP64 residual of the outer iteration)
+template <class TV, class TX, class TB, class TY, int K>
+void bresid(Handle* h, const int* rp, const int* ci, const TV* val, const TX* x, const TB* b,
+            TY* y, const char* name = "bspmv_resid") {
+  const int64_t nk = static_cast<int64_t>(h->n) * K;
+  LAUNCH(h, name, (k_bspmv<TV, TX, TB, TY, K, true>), xcd_grid(blocks_for(nk, kT)), kT, 0, h->n, rp, ci,
+         val, x, b, y);
+}
+
+// Table 1 steps 5-7 on K residuals at once (FP64 in and out; T = stage type)
+template <class T, int K>
+void bstage(Handle* h, const BWork& k, const double* r, double* z) {
+  const int n = h->n, nc = h->nc;
+  const int64_t nk = k.nk;
+  const T *pv, *rv, *av, *lu;
+  const T* rT;
+  T *d1, *rh, *x, *ysc, *xb;
+  if constexpr (std::is_same<T, double>::value) {
+    pv = h->p_val.get();
+    rv = h->r_val.get();
+    av = h->val.get();
+    lu = h->ilu.get();
+    rT = r;
+    d1 = k.d1;
+    rh = k.rh;
+    x = k.x;
+    ysc = k.y;
+    xb = k.xb;
+  } else {
+    pv = h->p_val32.get();
+    rv = h->r_val32.get();
+    av = h->val32.get();
+    lu = h->ilu32.get();
+    LAUNCH(h, "bcast_d2f", (k_bcast<double, float>), blocks_for(nk, kT), kT, 0, nk, r, k.r32);
+    rT = k.r32;
+    d1 = k.d1_32;
+    rh = k.rh32;
+    x = k.x32;
+    ysc = k.y32;
+    xb = k.xb32;
+  }
+  LAUNCH(h, "brestrict", (k_brestrict<T, T, K>), nc, 256, 0, nc, h->r_rp.get(), h->r_ci.get(),
+         rv, rT, k.rc);
+  {
+    dim3 grid(blocks_for(nc, 256), k.nch);
+    LAUNCH(h, "bcoarse", k_bcoarse_part<K>, grid, 256, 0, nc, k.cw, h->Ainv.get(), k.rc, k.cpart);
+    const int64_t nck = static_cast<int64_t>(nc) * K;
+    LAUNCH(h, "bcoarse_red", k_bcoarse_red, blocks_for(nck, kT), kT, 0, nck, k.nch, k.cpart, k.xc);
+  }
+  LAUNCH(h, "bprolong", (k_bspmv<T, double, T, T, K, false>), xcd_grid(blocks_for(nk, kT)), kT, 0, n,
+         h->p_rp.get(), h->p_ci.get(), pv, k.xc, static_cast<const T*>(nullptr), d1);
+  if (h->smoother) {
+    bresid<T, T, T, T, K>(h, h->rp.get(), h->ci.get(), av, d1, rT, rh);
+    ilu_apply_block<T, K>(h, lu, rh, x, ysc);
+    if (h->blk) {  // per-medium stage on the residual left by the ILU(0) stage
+      Handle* b = h->blk.get();
+      const T* blu;
+      if constexpr (std::is_same<T, double>::value) blu = b->ilu.get();
+      else blu = b->ilu32.get();
+      bresid<T, T, T, T, K>(h, h->rp.get(), h->ci.get(), av, x, rh, rh);
+      ilu_apply_block<T, K>(b, blu, rh, xb, ysc);
+      LAUNCH(h, "badd", (k_badd<T, T, T>), blocks_for(nk, kT), kT, 0, nk, x, xb, x);
+    }
+    LAUNCH(h, "badd", (k_badd<T, T, double>), blocks_for(nk, kT), kT, 0, nk, d1, x, z);
+  } else {
+    LAUNCH(h, "bcast", (k_bcast<T, double>), blocks_for(nk, kT), kT, 0, nk, d1, z);
+  }
+}
+
+template <int K>
+void bstage_any(Handle* h, const BWork& k, const double* r, double* z) {
+  if (h->precision == FAMS_PREC_MIXED) bstage<float, K>(h, k, r, z);
+  else bstage<double, K>(h, k, r, z);
+}
+
+// ||x_r|| of every right-hand side into S[r * stride + off]
+template <int K>
+void bnorms(Handle* h, const BWork& k, const double* x, int off) {
+  LAUNCH(h, "bdot", k_bmdot_part<K>, k.nb, kT, 0, k.nk, 1, x, k.nk, x, k.part, 1);
+  LAUNCH(h, "breduce", k_breduce, dim3(1, K), 256, 0, k.nb, K, k.part, 1, k.small + off,
+         k.st.stride);
+  LAUNCH(h, "bsqrt", k_bsqrt, 1, 64, 0, K, k.small + off, k.st.stride);
+}
+
+std::vector<double> read_field(Handle* h, const BWork& k, int off, int cnt) {
+  std::vector<double> all(static_cast<size_t>(k.st.stride) * k.K);
+  HIPX(hipMemcpyAsync(all.data(), k.small, all.size() * sizeof(double), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  std::vector<double> v(static_cast<size_t>(k.K) * cnt);
+  for (int r = 0; r < k.K; ++r)
+    for (int c = 0; c < cnt; ++c) v[r * cnt + c] = all[static_cast<size_t>(r) * k.st.stride + off + c];
+  return v;
+}
+
+struct RhsState {
+  double r0 = 0.0, tol = 0.0, beta = 0.0;
+  int it = 0;
+  bool done = false;
+  fams_status_t st = FAMS_NOT_CONVERGED;
+};
+
+// the stopping tests at a restart (or a Table 1 step), from the true residual
+void check_rhs(RhsState& s, int max_iter) {
+  if (s.done) return;
+  if (s.beta <= s.tol) {
+    s.st = FAMS_OK;
+    s.done = true;
+  } else if (!std::isfinite(s.beta) || s.beta > 1e8 * s.r0) {
+    s.st = FAMS_DIVERGED;
+    s.done = true;
+  } else if (s.it >= max_iter) {
+    s.done = true;
+  }
+}
+
+template <int K>
+void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
+                 std::vector<RhsState>& rs) {
+  const int64_t n = h->n, nk = k.nk;
+  const int m = std::min(o->restart, k.m);
+  const BState& S = k.st;
+  bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p, k.q,
+                                              k.r, "bresid_outer");
+  bnorms<K>(h, k, k.r, S.beta);
+  std::vector<double> b = read_field(h, k, S.beta, 1);
+  for (int r = 0; r < K; ++r) {
+    rs[r].r0 = rs[r].beta = b[r];
+    rs[r].tol = o->rtol * b[r];
+    if (r >= nr) {  // padding lanes
+      rs[r].done = true;
+      rs[r].st = FAMS_OK;
+    }
+    if (rs[r].r0 == 0.0 && !rs[r].done) {
+      rs[r].done = true;
+      rs[r].st = FAMS_OK;
+    }
+  }
+  (void)n;
+  while (true) {
+    unsigned mask = 0;
+    for (int r = 0; r < K; ++r) {
+      check_rhs(rs[r], o->max_iter);
+      if (!rs[r].done) mask |= 1u << r;
+    }
+    if (!mask) break;
+    LAUNCH(h, "bscale", k_bscale<K>, blocks_for(nk, kT), kT, 0, nk, k.r, k.small + S.beta,
+           S.stride, mask, k.V);
+    LAUNCH(h, "bgmres_init", k_bgmres_init, 1, 64, 0, K, S, k.small);
+    KK kk{};
+    unsigned cyc = mask;
+    int jmax = 0;
+    for (int j = 0; j < m && cyc; ++j) {
+      double* vj = k.V + j * nk;
+      double* zj = k.Z + j * nk;
+      bstage_any<K>(h, k, vj, zj);
+      LAUNCH(h, "bspmv", (k_bspmv<double, double, double, double, K, false>),
+             xcd_grid(blocks_for(nk, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(), zj,
+             static_cast<const double*>(nullptr), k.w);
+      // CGS2 against V_0..V_j, per right-hand side: h = V^T w; w -= V h and
+      // c = V^T w in one pass; w -= V c and ||w|| in one pass; h += c
+      LAUNCH(h, "bmdot", k_bmdot_part<K>, k.nb, kT, 0, nk, j + 1, k.V, nk, k.w, k.part, m + 2);
+      LAUNCH(h, "breduce", k_breduce, dim3(j + 1, K), 256, 0, k.nb, K, k.part, m + 2,
+             k.small + S.hcol, S.stride);
+      if (j + 1 <= kFuseMax) {
+        LAUNCH(h, "bmaxpy_mdot", k_bmaxpy_mdot<K>, k.nb, kT, 0, nk, j + 1, k.V, nk,
+               k.small + S.hcol, S.stride, k.w, k.part, m + 2);
+      } else {  // more basis vectors than the fused pass holds sums for
+        LAUNCH(h, "bmaxpy", k_bmaxpy<K>, blocks_for(nk, kT), kT, 0, nk, j + 1, k.V, nk,
+               k.small + S.hcol, S.stride, -1.0, k.w);
+        LAUNCH(h, "bmdot", k_bmdot_part<K>, k.nb, kT, 0, nk, j + 1, k.V, nk, k.w, k.part, m + 2);
+      }
+      LAUNCH(h, "breduce", k_breduce, dim3(j + 1, K), 256, 0, k.nb, K, k.part, m + 2,
+             k.small + S.y, S.stride);
+      LAUNCH(h, "bmaxpy_norm", k_bmaxpy_norm<K>, k.nb, kT, 0, nk, j + 1, k.V, nk, k.small + S.y,
+             S.stride, k.w, k.part);
+      LAUNCH(h, "breduce", k_breduce, dim3(1, K), 256, 0, k.nb, K, k.part, 1,
+             k.small + S.hcol + j + 1, S.stride);
+      LAUNCH(h, "bsqrt", k_bsqrt, 1, 64, 0, K, k.small + S.hcol + j + 1, S.stride);
+      LAUNCH(h, "bvadd", k_bvadd, K, 64, 0, K, j + 1, S, k.small);
+      LAUNCH(h, "bgivens", k_bgivens, 1, 64, 0, K, S, k.small, j, cyc);
+      std::vector<double> est = read_field(h, k, S.out, 2);
+      unsigned next = 0;
+      for (int r = 0; r < K; ++r) {
+        if (!(cyc >> r & 1u)) continue;
+        ++rs[r].it;
+        kk.v[r] = j + 1;
+        const double e = est[2 * r], hn = est[2 * r + 1];
+        if (!(e <= rs[r].tol || rs[r].it >= o->max_iter || !(hn > 0.0) || !std::isfinite(e)))
+          next |= 1u << r;
+      }
+      jmax = j + 1;
+      cyc = next;
+      if (cyc)
+        LAUNCH(h, "bscale", k_bscale<K>, blocks_for(nk, kT), kT, 0, nk, k.w, k.small + S.hcol + j + 1,
+               S.stride, cyc, k.V + (j + 1) * nk);
+    }
+    LAUNCH(h, "bbacksolve", k_bbacksolve, 1, 64, 0, K, S, k.small, kk);
+    LAUNCH(h, "bmaxpy", k_bmaxpy<K>, blocks_for(nk, kT), kT, 0, nk, jmax, k.Z, nk, k.small + S.y,
+           S.stride, 1.0, k.p);
+    bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p,
+                                                k.q, k.r, "bresid_outer");
+    bnorms<K>(h, k, k.r, S.beta);
+    b = read_field(h, k, S.beta, 1);
+    for (int r = 0; r < K; ++r)
+      if (!rs[r].done) rs[r].beta = b[r];
+  }
+}
+
+template <int K>
+void block_richardson(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
+                      std::vector<RhsState>& rs) {
+  const int64_t nk = k.nk;
+  const BState& S = k.st;
+  bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p, k.q,
+                                              k.r, "bresid_outer");
+  bnorms<K>(h, k, k.r, S.beta);
+  std::vector<double> b = read_field(h, k, S.beta, 1);
+  for (int r = 0; r < K; ++r) {
+    rs[r].r0 = rs[r].beta = b[r];
+    rs[r].tol = o->rtol * b[r];
+    if (r >= nr || b[r] == 0.0) {
+      rs[r].done = true;
+      rs[r].st = FAMS_OK;
+    }
+  }
+  while (true) {
+    unsigned mask = 0;
+    for (int r = 0; r < K; ++r) {
+      check_rhs(rs[r], o->max_iter);
+      if (!rs[r].done) mask |= 1u << r;
+    }
+    if (!mask) break;
+    bstage_any<K>(h, k, k.r, k.z);
+    LAUNCH(h, "baxpy", k_baxpy_mask<K>, blocks_for(nk, kT), kT, 0, nk, mask, k.z, k.p);
+    bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p,
+                                                k.q, k.r, "bresid_outer");
+    bnorms<K>(h, k, k.r, S.beta);
+    b = read_field(h, k, S.beta, 1);
+    for (int r = 0; r < K; ++r)
+      if (mask >> r & 1u) {
+        ++rs[r].it;
+        rs[r].beta = b[r];
+      }
+  }
+}
+
+template <int K>
+void solve_group(Handle* h, const double* q, double* p, int nr, const fams_solve_opts_t* o,
+                 fams_info_t* info) {
+  const int m = o->outer == FAMS_GMRES ? o->restart : 1;
+  ensure_block_workspace(h, K, m);
+  BWork k = block_work(h, K, m);
+  const int n = h->n;
+  const int64_t nk = k.nk;
+  for (Handle* g : {h, h->blk.get()})
+    if (g && g->sweep_err.get()) HIPX(hipMemsetAsync(g->sweep_err, 0, sizeof(int), h->stream));
+  auto t0 = std::chrono::steady_clock::now();
+  LAUNCH(h, "bpack", k_pack<K>, blocks_for(nk, kT), kT, 0, n, nr, q, k.q);
+  if (o->use_initial_guess)
+    LAUNCH(h, "bpack", k_pack<K>, blocks_for(nk, kT), kT, 0, n, nr, static_cast<const double*>(p),
+           k.p);
+  else
+    HIPX(hipMemsetAsync(k.p, 0, nk * sizeof(double), h->stream));
+  std::vector<RhsState> rs(K);
+  if (o->outer == FAMS_GMRES) block_gmres<K>(h, k, nr, o, rs);
+  else block_richardson<K>(h, k, nr, o, rs);
+  LAUNCH(h, "bunpack", k_unpack<K>, blocks_for(nk, kT), kT, 0, n, nr, k.p, p);
+  HIPX(hipStreamSynchronize(h->stream));
+  int e = 0;
+  for (Handle* g : {h, h->blk.get()}) {
+    if (!g || !g->sweep_err.get()) continue;
+    int eg = 0;
+    HIPX(hipMemcpyAsync(&eg, g->sweep_err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    e |= eg;
+  }
+  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "ILU(0) sweep: a dependency wait exceeded its bound");
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < nr; ++r) {
+    info[r].status = rs[r].st;
+    info[r].iterations = rs[r].it;
+    info[r].rel_residual = rs[r].r0 > 0 ? rs[r].beta / rs[r].r0 : 0.0;
+    info[r].ms = ms;
+  }
+}
+
+}  // namespace
+
+fams_status_t solve_block(Handle* h, const double* q, double* p, int nrhs,
+                          const fams_solve_opts_t* o, fams_info_t* info) {
+  const int m = o->outer == FAMS_GMRES ? o->restart : 1;
+  // the widest group (up to 16 right-hand sides) whose work space fits in
+  // the free device memory with a margin
+  size_t free_b = 0, total_b = 0;
+  HIPX(hipMemGetInfo(&free_b, &total_b));
+  const size_t held = h->bwk.get() ? block_bytes(h, h->bK, h->bm) : 0;
+  int K = 16;
+  while (K > 2 && (K / 2 >= nrhs || block_bytes(h, K, m) > (free_b + held) / 10 * 9)) K /= 2;
+  FAMS_REQUIRE(block_bytes(h, K, m) <= free_b + held, FAMS_ERR_OOM,
+               "no room for the lock-step work space of two right-hand sides");
+  const int64_t n = h->n;
+  fams_status_t worst = FAMS_OK;
+  for (int r0 = 0; r0 < nrhs; r0 += K) {
+    const int nr = std::min(K, nrhs - r0);
+    fams_info_t* inf = info + r0;
+    const double* qg = q + r0 * n;
+    double* pg = p + r0 * n;
+    switch (K) {
+      case 2: solve_group<2>(h, qg, pg, nr, o, inf); break;
+      case 4: solve_group<4>(h, qg, pg, nr, o, inf); break;
+      case 8: solve_group<8>(h, qg, pg, nr, o, inf); break;
+      default: solve_group<16>(h, qg, pg, nr, o, inf); break;
+    }
+    for (int r = 0; r < nr; ++r)
+      if (inf[r].status > worst) worst = static_cast<fams_status_t>(inf[r].status);
+  }
+  return worst;
+}
+
+}  // namespace fams

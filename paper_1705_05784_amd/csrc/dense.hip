@@ -580,49 +580,6 @@ __global__ void k_trsm_upper(const double* u, int n, int k0, int nb, double* b, 
   for (int r = 0; r < nb; ++r) col[r] = x[r];
 }
 
-// C[m x p] -= A[m x k] * B[k x p], column-major with leading dimension ld.
-// 64 x 64 tiles, 256 threads, 4 x 4 outputs per thread, k in steps of 16.
-__global__ void __launch_bounds__(256)
-k_gemm_sub(int m, int p, int k, const double* A, const double* B, double* C, int ld) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < k; k0 += 16) {
-    for (int t = threadIdx.x; t < 16 * 64; t += 256) {
-      int kk = t / 64, r = t % 64;
-      int gr = row0 + r, gk = k0 + kk;
-      As[kk][r] = (gr < m && gk < k) ? A[static_cast<int64_t>(gk) * ld + gr] : 0.0;
-      int c = t % 64, kb = t / 64;
-      int gc = col0 + c, gk2 = k0 + kb;
-      Bs[kb][c] = (gc < p && gk2 < k) ? B[static_cast<int64_t>(gc) * ld + gk2] : 0.0;
-    }
-    __syncthreads();
-#pragma clang loop unroll(full)
-    for (int kk = 0; kk < 16; ++kk) {
-      double av[4], bv[4];
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 4; ++u) {
-        av[u] = As[kk][tx + 16 * u];
-        bv[u] = Bs[kk][ty + 16 * u];
-      }
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 4; ++u)
-#pragma clang loop unroll(full)
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-    }
-    __syncthreads();
-  }
-#pragma clang loop unroll(full)
-  for (int u = 0; u < 4; ++u)
-#pragma clang loop unroll(full)
-    for (int v = 0; v < 4; ++v) {
-      int r = row0 + tx + 16 * u, c = col0 + ty + 16 * v;
-      if (r < m && c < p) C[static_cast<int64_t>(c) * ld + r] -= acc[u][v];
-    }
-}
-
 __global__ void k_perm_identity(int n, const int* perm, double* x) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<int64_t>(n) * n) return;
@@ -651,11 +608,14 @@ __global__ void k_gemv_reduce(int n, int nchunks, const double* part, double* y)
   y[I] = s;
 }
 
+void gemm_mfma(Handle* h, int m, int p, int k, double alpha, const double* A, int lda,
+               const double* B, int ldb, double* C, int ldc, int skip0 = 0, int skip1 = 0,
+               hipStream_t st = nullptr, bool overwrite = false);
+
+// C[m x p] -= A[m x k] B[k x p] (common leading dimension) on FP64 MFMA
 void gemm_sub(Handle* h, int m, int p, int k, const double* A, const double* B, double* C,
               int ld, hipStream_t st = nullptr) {
-  if (m <= 0 || p <= 0 || k <= 0) return;
-  dim3 grid(blocks_for(m, 64), blocks_for(p, 64));
-  LAUNCH_ON(h, st ? st : h->stream, "gemm_f64", k_gemm_sub, grid, 256, 0, m, p, k, A, B, C, ld);
+  gemm_mfma(h, m, p, k, -1.0, A, ld, B, ld, C, ld, 0, 0, st);
 }
 
 // ---- FP64 MFMA GEMM ----------------------------------------------------------
@@ -669,7 +629,7 @@ constexpr int kGT = 64, kGK = 16;
 
 __global__ void __launch_bounds__(256)
 k_gemm_mfma(int m, int p, int k, double alpha, const double* A, int lda, const double* B,
-            int ldb, double* C, int ldc, int skip0, int skip1) {
+            int ldb, double* C, int ldc, int skip0, int skip1, int overwrite) {
   __shared__ double As[kGK][kGT + 1];
   __shared__ double Bs[kGK][kGT + 1];
   const int r0 = blockIdx.x * kGT, c0 = blockIdx.y * kGT;
@@ -712,17 +672,112 @@ k_gemm_mfma(int m, int p, int k, double alpha, const double* A, int lda, const d
       for (int q = 0; q < 4; ++q) {
         const int r = r0 + wr + a * 16 + 4 * q + lane / 16;
         const int c = c0 + wc + b * 16 + lane % 16;
-        if (r < m && c < p && (r < skip0 || r >= skip1) && (c < skip0 || c >= skip1))
-          C[static_cast<int64_t>(c) * ldc + r] += alpha * acc[a][b][q];
+        if (r < m && c < p && (r < skip0 || r >= skip1) && (c < skip0 || c >= skip1)) {
+          double* o = C + static_cast<int64_t>(c) * ldc + r;
+          *o = overwrite ? alpha * acc[a][b][q] : *o + alpha * acc[a][b][q];
+        }
+      }
+}
+
+// Large-tile form: a workgroup forms a 128 x 128 tile, each wavefront a
+// 64 x 64 quarter of 4 x 4 blocks of v_mfma_f64_16x16x4 (16 accumulators of
+// four doubles).  The k dimension advances 16 at a time through two LDS
+// buffers: while the MFMAs consume one buffer, every thread holds the next
+// 16-wide slices of A and B in registers and stores them into the other
+// buffer after the step, so one barrier per step and the global loads
+// overlap the arithmetic.
+constexpr int kBT = 128, kBK = 16, kBPad = kBT + 4;
+
+__global__ void __launch_bounds__(256)
+k_gemm_mfma128(int m, int p, int k, double alpha, const double* A, int lda, const double* B,
+               int ldb, double* C, int ldc, int skip0, int skip1, int overwrite) {
+  __shared__ double As[2][kBK][kBPad];
+  __shared__ double Bs[2][kBK][kBPad];
+  const int r0 = blockIdx.x * kBT, c0 = blockIdx.y * kBT;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wr = (wave % 2) * 64, wc = (wave / 2) * 64;
+  // global slice loads: A column-major, 128 rows x 16 k: thread t loads rows
+  // (t % 128) at k = t / 128 + 2u; B column-major, 16 k x 128 columns: thread
+  // t loads k = t % 16 of columns t / 16 + 16u
+  const int ar = tid % kBT, ak = tid / kBT;
+  const int bk = tid % kBK, bc = tid / kBK;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int kk = k0 + ak + 2 * u, rr = r0 + ar;
+      ra[u] = (rr < m && kk < k) ? A[static_cast<int64_t>(kk) * lda + rr] : 0.0;
+      const int kb = k0 + bk, cc = c0 + bc + 16 * u;
+      rb[u] = (cc < p && kb < k) ? B[static_cast<int64_t>(cc) * ldb + kb] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      As[buf][ak + 2 * u][ar] = ra[u];
+      Bs[buf][bk][bc + 16 * u] = rb[u];
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < k; k0 += kBK) {
+    const bool more = k0 + kBK < k;
+    if (more) load(k0 + kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 4) {
+      double fa[4], fb[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        fa[t] = As[buf][kk + lane / 16][wr + t * 16 + lane % 16];
+        fb[t] = Bs[buf][kk + lane / 16][wc + t * 16 + lane % 16];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + wr + a * 16 + 4 * q + lane / 16;
+        const int c = c0 + wc + b * 16 + lane % 16;
+        if (r < m && c < p && (r < skip0 || r >= skip1) && (c < skip0 || c >= skip1)) {
+          double* o = C + static_cast<int64_t>(c) * ldc + r;
+          *o = overwrite ? alpha * acc[a][b][q] : *o + alpha * acc[a][b][q];
+        }
       }
 }
 
 void gemm_mfma(Handle* h, int m, int p, int k, double alpha, const double* A, int lda,
-               const double* B, int ldb, double* C, int ldc, int skip0 = 0, int skip1 = 0) {
+               const double* B, int ldb, double* C, int ldc, int skip0, int skip1,
+               hipStream_t st, bool overwrite) {
   if (m <= 0 || p <= 0 || k <= 0) return;
-  dim3 grid(blocks_for(m, kGT), blocks_for(p, kGT));
-  LAUNCH(h, "gemm_mfma", k_gemm_mfma, grid, 256, 0, m, p, k, alpha, A, lda, B, ldb, C, ldc,
-         skip0, skip1);
+  hipStream_t s = st ? st : h->stream;
+  const int ow = overwrite ? 1 : 0;
+  if (static_cast<int64_t>(blocks_for(m, kBT)) * blocks_for(p, kBT) >= 192) {
+    dim3 grid(blocks_for(m, kBT), blocks_for(p, kBT));
+    LAUNCH_ON(h, s, "gemm_mfma", k_gemm_mfma128, grid, 256, 0, m, p, k, alpha, A, lda, B, ldb, C,
+              ldc, skip0, skip1, ow);
+  } else {  // small products: more, smaller tiles keep the device busy
+    dim3 grid(blocks_for(m, kGT), blocks_for(p, kGT));
+    LAUNCH_ON(h, s, "gemm_mfma", k_gemm_mfma, grid, 256, 0, m, p, k, alpha, A, lda, B, ldb, C,
+              ldc, skip0, skip1, ow);
+  }
 }
 
 // ---- in-place Gauss-Jordan inverse by blocks (no pivoting; SPD A_c) ---------
@@ -1034,17 +1089,85 @@ void lu_inverse(Handle* h, double* a, double* inv, int n) {
 
 // inv = A^{-1} by blocked Gauss-Jordan without pivoting; false (inv
 // undefined) if a pivot is not positive, i.e. A is not SPD
+namespace {
+
+// the 32-wide Gauss-Jordan steps on a contiguous n x n matrix (in place)
+void gje_inner(Handle* h, double* a, int n, int* info) {
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    const int nb = std::min(kNb, n - k0);
+    LAUNCH(h, "gje_block", k_gje_block, 1, 1024, 0, a, n, k0, nb, info);
+    if (n > nb) LAUNCH(h, "gje_col", k_gje_col, blocks_for(n - nb, 8), 256, 0, a, n, k0, nb);
+    gemm_mfma(h, n, n, nb, 1.0, a + static_cast<int64_t>(k0) * n, n, a + k0, n, a, n, k0,
+              k0 + nb);
+    if (n > nb) LAUNCH(h, "gje_row", k_gje_row, blocks_for(n - nb, 8), 256, 0, a, n, k0, nb);
+  }
+}
+
+// D (nb x nb, leading dimension nb) <- a[k0:k0+nb, k0:k0+nb]
+__global__ void k_block_get(const double* a, int n, int k0, int nb, double* D) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(nb) * nb) return;
+  const int i = static_cast<int>(e % nb), c = static_cast<int>(e / nb);
+  D[e] = a[static_cast<int64_t>(k0 + c) * n + k0 + i];
+}
+
+// column block and diagonal block back into a: a[r, k0 + c] = C1[r, c] for r
+// outside the block, D[r - k0, c] inside it
+__global__ void k_block_put_cols(double* a, int n, int k0, int nb, const double* C1,
+                                 const double* D) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * nb) return;
+  const int r = static_cast<int>(e % n), c = static_cast<int>(e / n);
+  a[static_cast<int64_t>(k0 + c) * n + r] =
+      (r >= k0 && r < k0 + nb) ? D[static_cast<int64_t>(c) * nb + (r - k0)] : C1[e];
+}
+
+// row block back into a: a[k0 + i, c] = R1[i, c] for columns c outside the block
+__global__ void k_block_put_rows(double* a, int n, int k0, int nb, const double* R1) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * nb) return;
+  const int i = static_cast<int>(e % nb), c = static_cast<int>(e / nb);
+  if (c < k0 || c >= k0 + nb) a[static_cast<int64_t>(c) * n + k0 + i] = R1[e];
+}
+
+}  // namespace
+
+// In-place Gauss-Jordan inverse in blocks of kOb = 256 (no pivoting; SPD
+// A_c).  Block step with D the diagonal block, B its row block, C its column
+// block and E the rest: D <- D^{-1} (by the 32-wide steps above), C <- -C
+// D^{-1}, E <- E + C B (old B), B <- D^{-1} B.  The three products are FP64
+// MFMA GEMMs of inner dimension 256, so the update of E (2 n^2 256 flops per
+// step, n/256 steps) reads and writes E once per 256 columns instead of once
+// per 32.
+constexpr int kOb = 256;
+
 bool spd_inverse(Handle* h, const double* a, double* inv, int n) {
   DBuf<int> info(&h->alloc, 1);
   HIPX(hipMemsetAsync(info, 0, sizeof(int), h->stream));
   HIPX(hipMemcpyAsync(inv, a, sizeof(double) * n * n, hipMemcpyDeviceToDevice, h->stream));
-  for (int k0 = 0; k0 < n; k0 += kNb) {
-    const int nb = std::min(kNb, n - k0);
-    LAUNCH(h, "gje_block", k_gje_block, 1, 1024, 0, inv, n, k0, nb, info.get());
-    if (n > nb) LAUNCH(h, "gje_col", k_gje_col, blocks_for(n - nb, 8), 256, 0, inv, n, k0, nb);
-    gemm_mfma(h, n, n, nb, 1.0, inv + static_cast<int64_t>(k0) * n, n, inv + k0, n, inv, n, k0,
-              k0 + nb);
-    if (n > nb) LAUNCH(h, "gje_row", k_gje_row, blocks_for(n - nb, 8), 256, 0, inv, n, k0, nb);
+  if (n <= kOb) {
+    gje_inner(h, inv, n, info.get());
+  } else {
+    DBuf<double> D(&h->alloc, static_cast<size_t>(kOb) * kOb);
+    DBuf<double> C1(&h->alloc, static_cast<size_t>(n) * kOb);
+    DBuf<double> R1(&h->alloc, static_cast<size_t>(n) * kOb);
+    for (int k0 = 0; k0 < n; k0 += kOb) {
+      const int nb = std::min(kOb, n - k0);
+      const int64_t nbb = static_cast<int64_t>(nb) * nb, nnb = static_cast<int64_t>(n) * nb;
+      LAUNCH(h, "gje_get", k_block_get, blocks_for(nbb, 256), 256, 0, inv, n, k0, nb, D.get());
+      gje_inner(h, D, nb, info.get());
+      // C1 = -C D^{-1} (rows inside the block are not used)
+      gemm_mfma(h, n, nb, nb, -1.0, inv + static_cast<int64_t>(k0) * n, n, D, nb, C1, n, 0, 0,
+                nullptr, true);
+      // E += C1 B
+      gemm_mfma(h, n, n, nb, 1.0, C1, n, inv + k0, n, inv, n, k0, k0 + nb);
+      // R1 = D^{-1} B (columns inside the block are not used)
+      gemm_mfma(h, nb, n, nb, 1.0, D, nb, inv + k0, n, R1, nb, 0, 0, nullptr, true);
+      LAUNCH(h, "gje_put", k_block_put_rows, blocks_for(nnb, 256), 256, 0, inv, n, k0, nb,
+             R1.get());
+      LAUNCH(h, "gje_put", k_block_put_cols, blocks_for(nnb, 256), 256, 0, inv, n, k0, nb,
+             C1.get(), D.get());
+    }
   }
   int hinfo = 0;
   HIPX(hipMemcpyAsync(&hinfo, info.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));

@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(256)
 k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const int* segbase,
                const int* ecol, const T* eval, const int* ecnt, const int* ep0, const T* ediag,
                const int* ci, const T* lu, const T* inp, T* out, T* arm, int* ticket, int* err,
-               unsigned long long limit, unsigned long long* trace) {
+               unsigned long long limit) {
   // dynamic LDS: the range's values (S entries of T), then its level
   // boundaries (max_segs + 1 ints; always in LDS, so every read of them is
   // an LDS read and never waits on the global loads in flight)
@@ -414,7 +414,6 @@ k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const
     const int c = s_c;
     if (c >= nranges) break;
     const int r = kUpper ? nranges - 1 - c : c;
-    if (trace && tid == 0) trace[4 * r] = wall_clock64();
     const int r0 = r * S, r1 = min(n, r0 + S);
     const int sb = segbase[r], ns = segbase[r + 1] - sb;
     for (int k = tid; k <= ns; k += nt) s_seg[k] = seg[sb + k];
@@ -440,7 +439,6 @@ k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const
         sweep_row<T, kUpper>(w, r0, r1, loc, out, arm, ep0, ci, lu, err, limit);
       }
       lds_barrier();  // the level's values in loc; global traffic stays in flight
-      if (trace && tid == 0 && lvl == 0) trace[4 * r + 2] = wall_clock64();
     };
     SweepRow<T> s0, s1, s2, s3;
     fst(s0, 0);
@@ -453,10 +451,6 @@ k_sweep_ranges(int n, int S, int nranges, const int* rows, const int* seg, const
       if (k + 1 < ns) step(k + 1, s1, s3, s0);
       if (k + 2 < ns) step(k + 2, s2, s0, s1);
       if (k + 3 < ns) step(k + 3, s3, s1, s2);
-    }
-    if (trace && tid == 0) {
-      trace[4 * r + 1] = wall_clock64();
-      trace[4 * r + 3] = static_cast<unsigned long long>(ns) | (static_cast<unsigned long long>(blockIdx.x) << 32);
     }
   }
 }
@@ -875,29 +869,6 @@ void range_table(Handle* h, const std::vector<int>& lev, int S, int upper, Range
   HIPX(hipStreamSynchronize(h->stream));
 }
 
-void print_sweep_trace(Handle* h, const unsigned long long* d, int nl, int nu) {
-  std::vector<unsigned long long> t(4 * static_cast<size_t>(nl + nu));
-  HIPX(hipMemcpyAsync(t.data(), d, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                      h->stream));
-  HIPX(hipStreamSynchronize(h->stream));
-  for (int part = 0; part < 2; ++part) {
-    const int base = part ? nl : 0, cnt = part ? nu : nl;
-    unsigned long long t0 = ~0ull, t1 = 0;
-    for (int r = 0; r < cnt; ++r) {
-      t0 = std::min(t0, t[4 * (base + r)]);
-      t1 = std::max(t1, t[4 * (base + r) + 1]);
-    }
-    std::fprintf(stderr, "[sweep %s] %d ranges, %.1f us total (ticks of 10 ns)\n",
-                 part ? "upper" : "lower", cnt, (t1 - t0) * 0.01);
-    for (int r = 0; r < cnt; r += std::max(1, cnt / 12)) {
-      const unsigned long long* q = &t[4 * (base + r)];
-      std::fprintf(stderr, "   range %3d: start %8.1f first-level %6.1f end %8.1f us, %4llu levels\n",
-                   r, (q[0] - t0) * 0.01, (q[2] - q[0]) * 0.01, (q[1] - t0) * 0.01,
-                   q[3] & 0xffffffffull);
-    }
-  }
-}
-
 // factor values of a range schedule in precision T (gathered once)
 template <class T>
 void ell_values(Handle* h, Ranges* R, const T* lu, DBuf<T>& ev, DBuf<T>& ed) {
@@ -1000,6 +971,25 @@ void build_ilu(Handle* h) {
     h->ilu32.reset(&h->alloc, h->nnz);
     LAUNCH(h, "d2f", k_d2f_ilu, blocks_for(h->nnz, kT), kT, 0, h->nnz, h->ilu.get(),
            h->ilu32.get());
+  }
+  // everything the sweeps keep in the handle, allocated now so that applying
+  // the smoother allocates nothing: work tickets, the wait error word, the
+  // sweep-order input and the factor values in the schedules' ELL form
+  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, 4);
+  if (!h->sweep_err.get()) {
+    h->sweep_err.reset(&h->alloc, 1);
+    HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
+  }
+  if (h->rng_lo.nranges > 0) {
+    if (h->precision == FAMS_PREC_MIXED) {
+      if (!h->sweep_in32.get()) h->sweep_in32.reset(&h->alloc, n);
+      ell_values<float>(h, &h->rng_lo, h->ilu32.get(), h->rng_lo.eval32, h->rng_lo.ediag32);
+      ell_values<float>(h, &h->rng_up, h->ilu32.get(), h->rng_up.eval32, h->rng_up.ediag32);
+    } else {
+      if (!h->sweep_in64.get()) h->sweep_in64.reset(&h->alloc, n);
+      ell_values<double>(h, &h->rng_lo, h->ilu.get(), h->rng_lo.eval64, h->rng_lo.ediag64);
+      ell_values<double>(h, &h->rng_up, h->ilu.get(), h->rng_up.eval64, h->rng_up.ediag64);
+    }
   }
 }
 
@@ -1112,23 +1102,16 @@ void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
       if (!h->sweep_in32.get()) h->sweep_in32.reset(&h->alloc, n);
       inp = h->sweep_in32.get();
     }
-    // FAMS_SWEEP_TRACE: per-range start / first level / end stamps of one
-    // application (diagnostics)
-    static const bool trace_on = std::getenv("FAMS_SWEEP_TRACE") != nullptr;
-    DBuf<unsigned long long> tr;
-    if (trace_on) tr.reset(&h->alloc, 4 * static_cast<size_t>(L.nranges + U.nranges));
     LAUNCH(h, "ilu_gather", k_gather<T>, blocks_for(n, kT), kT, 0, n, L.rows.get(), b, inp);
     LAUNCH(h, "ilu_lower", (k_sweep_ranges<T, false>), std::min(L.nranges, 2048), 256, lds, n,
            L.S, L.nranges, L.rows.get(), L.seg.get(), L.segbase.get(), L.ecol.get(), lv,
            L.ecnt.get(), L.ep0.get(), ld, h->ci.get(), lu, inp, y, x, h->ilu_ticket.get(),
-           h->sweep_err.get(), h->wait_ticks, tr.get());
+           h->sweep_err.get(), h->wait_ticks);
     LAUNCH(h, "ilu_gather", k_gather<T>, blocks_for(n, kT), kT, 0, n, U.rows.get(), y, inp);
     LAUNCH(h, "ilu_upper", (k_sweep_ranges<T, true>), std::min(U.nranges, 2048), 256, lds, n,
            U.S, U.nranges, U.rows.get(), U.seg.get(), U.segbase.get(), U.ecol.get(), uv,
            U.ecnt.get(), U.ep0.get(), ud, h->ci.get(), lu, inp, x, nullptr,
-           h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks,
-           tr.get() ? tr.get() + 4 * static_cast<size_t>(L.nranges) : nullptr);
-    if (trace_on) print_sweep_trace(h, tr.get(), L.nranges, U.nranges);
+           h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks);
     return;
   }
   // a window of ~kSweepGroups chunks in flight: enough to overlap tens of
@@ -1142,6 +1125,132 @@ void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
          h->lvl_up.chunk.get(), h->lvl_up.nchunks, h->rp.get(), h->ci.get(), h->diag.get(), lu,
          y, x, h->ilu_ticket.get() + 1, h->sweep_err.get(), h->wait_ticks);
 }
+
+namespace {
+
+// ---- sweeps of K right-hand sides in lock-step --------------------------------
+// Vectors hold K values per row (x[i * K + r], r = right-hand side).  The
+// schedule is the level order of the one-launch sweeps cut into chunks of at
+// most kBlkRows rows inside one level; a workgroup of kBlkRows x K threads
+// takes a chunk by ticket and gives each row K consecutive lanes, one per
+// right-hand side.  The K lanes of a row read the row's factor entries at the
+// same addresses (one transaction) and gather the K consecutive values of
+// each dependency (one contiguous stretch); lane r waits only for entry r of
+// the rows it depends on (value as ready flag, bounded waits).
+constexpr int kBlkRows = 64;
+
+template <class T, bool kUpper, int K>
+__global__ void __launch_bounds__(kBlkRows * K)
+k_bsweep(const int* rows, const int* chunk, int nchunks, const int* rp, const int* ci,
+         const int* diag, const T* lu, const T* in, T* out, T* arm, int* ticket, int* err,
+         unsigned long long limit) {
+  using U = typename Sentinel<T>::U;
+  __shared__ int s_c;
+  const int r = threadIdx.x % K, slot = threadIdx.x / K;
+  while (true) {
+    if (threadIdx.x == 0) s_c = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int c = s_c;
+    __syncthreads();
+    if (c >= nchunks) break;
+    const int t = chunk[c] + slot;
+    if (t < chunk[c + 1]) {
+      const int i = rows[t];
+      const int dg = diag[i];
+      const int p0 = kUpper ? dg + 1 : rp[i];
+      const int p1 = kUpper ? rp[i + 1] : dg;
+      const int64_t o = static_cast<int64_t>(i) * K + r;
+      T s = in[o];
+      for (int pb = p0; pb < p1; pb += kDeps) {
+        U u[kDeps];
+        int j[kDeps];
+        T l[kDeps];
+#pragma unroll
+        for (int k = 0; k < kDeps; ++k)
+          if (pb + k < p1) {
+            j[k] = ci[pb + k];
+            l[k] = lu[pb + k];
+          }
+#pragma unroll
+        for (int k = 0; k < kDeps; ++k)
+          if (pb + k < p1) u[k] = load_raw<T>(out + static_cast<int64_t>(j[k]) * K + r);
+#pragma unroll
+        for (int k = 0; k < kDeps; ++k)
+          if (pb + k < p1)
+            s -= l[k] * wait_ready<T>(out + static_cast<int64_t>(j[k]) * K + r, u[k], err, limit);
+      }
+      if constexpr (kUpper) {
+        s = s / lu[dg];
+      } else {
+        reinterpret_cast<U*>(arm)[o] = Sentinel<T>::bits;
+      }
+      store_ready<T>(out + o, s);
+    }
+  }
+}
+
+template <class T>
+__global__ void k_bfill_sentinel(int64_t n, T* x) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  using U = typename Sentinel<T>::U;
+  if (i < n) reinterpret_cast<U*>(x)[i] = Sentinel<T>::bits;
+}
+
+// chunks of at most kBlkRows rows inside one level (the lock-step sweeps)
+void block_chunk_table(Handle* h, Levels* L) {
+  if (L->bchunk.get()) return;
+  std::vector<int> cb;
+  for (int l = 0; l < L->count(); ++l)
+    for (int s = L->ptr[l]; s < L->ptr[l + 1]; s += kBlkRows) cb.push_back(s);
+  cb.push_back(L->ptr.empty() ? 0 : L->ptr.back());
+  L->nbchunks = static_cast<int>(cb.size()) - 1;
+  L->bchunk.reset(&h->alloc, cb.size());
+  HIPX(hipMemcpyAsync(L->bchunk, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+}
+
+}  // namespace
+
+// x = U^{-1} L^{-1} b for K right-hand sides in lock-step (x[i * K + r]);
+// y is scratch of n * K entries
+template <class T, int K>
+void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
+  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, 4);
+  if (!h->sweep_err.get()) {
+    h->sweep_err.reset(&h->alloc, 1);
+    HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
+  }
+  block_chunk_table(h, &h->lvl_lo);
+  block_chunk_table(h, &h->lvl_up);
+  HIPX(hipMemsetAsync(h->ilu_ticket, 0, 2 * sizeof(int), h->stream));
+  const int64_t nk = static_cast<int64_t>(h->n) * K;
+  LAUNCH(h, "bilu_arm", k_bfill_sentinel<T>, blocks_for(nk, kT), kT, 0, nk, y);
+  const unsigned long long lim = wait_limit(h);
+  // about 2048 threads per compute unit in flight
+  const int cap = 256 * 2048 / (kBlkRows * K);
+  const int groups_lo = std::min(h->lvl_lo.nbchunks, cap);
+  const int groups_up = std::min(h->lvl_up.nbchunks, cap);
+  LAUNCH(h, "bilu_lower", (k_bsweep<T, false, K>), groups_lo, kBlkRows * K, 0,
+         h->lvl_lo.rows.get(), h->lvl_lo.bchunk.get(), h->lvl_lo.nbchunks, h->rp.get(),
+         h->ci.get(), h->diag.get(), lu, b, y, x, h->ilu_ticket.get(), h->sweep_err.get(), lim);
+  LAUNCH(h, "bilu_upper", (k_bsweep<T, true, K>), groups_up, kBlkRows * K, 0,
+         h->lvl_up.rows.get(), h->lvl_up.bchunk.get(), h->lvl_up.nbchunks, h->rp.get(),
+         h->ci.get(), h->diag.get(), lu, static_cast<const T*>(y), x, static_cast<T*>(nullptr),
+         h->ilu_ticket.get() + 1, h->sweep_err.get(), lim);
+}
+
+#define FAMS_ILU_BLOCK(T, K) \
+  template void ilu_apply_block<T, K>(Handle*, const T*, const T*, T*, T*);
+FAMS_ILU_BLOCK(double, 2)
+FAMS_ILU_BLOCK(double, 4)
+FAMS_ILU_BLOCK(double, 8)
+FAMS_ILU_BLOCK(double, 16)
+FAMS_ILU_BLOCK(float, 2)
+FAMS_ILU_BLOCK(float, 4)
+FAMS_ILU_BLOCK(float, 8)
+FAMS_ILU_BLOCK(float, 16)
+#undef FAMS_ILU_BLOCK
 
 template void ilu_apply<double>(Handle*, const double*, const double*, double*, double*);
 template void ilu_apply<float>(Handle*, const float*, const float*, float*, float*);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <functional>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -141,6 +143,8 @@ struct Levels {
   DBuf<int> rows;        // device: rows grouped by level, ascending within level
   DBuf<int> chunk;       // device: chunk boundaries (<= 256 rows, inside one level)
   int nchunks = 0;
+  DBuf<int> bchunk;      // device: chunks of the lock-step sweeps (<= 64 rows, one level)
+  int nbchunks = 0;
   int count() const { return ptr.empty() ? 0 : static_cast<int>(ptr.size()) - 1; }
 };
 
@@ -245,6 +249,15 @@ struct Handle {
   DBuf<double> gpart;   // partial sums of the coarse matrix-vector product
   size_t wk_vectors = 0;
 
+  // lock-step solves of several right-hand sides (block.hip): K values per
+  // row in every block vector, m = the GMRES restart the space was sized for
+  DBuf<double> bwk;     // FP64 block vectors
+  DBuf<float> bwk32;    // FP32 block vectors of the precision-form stage
+  DBuf<double> bred;    // reduction partials
+  DBuf<double> bsmall;  // per-right-hand-side GMRES state and scalars
+  DBuf<double> bpart;   // partial sums of the coarse block product
+  int bK = 0, bm = 0;
+
   fams_setup_info_t info{};
 
   // per-medium smoothing stage (smoother 2): a handle of its own holding
@@ -272,6 +285,12 @@ class Fork {
   bool used_[kAuxStreams] = {};
   bool joined_ = false;
 };
+
+// api.hip: pointer checks of caller arrays, and the error mapping of the C ABI
+// (exceptions become a status and the thread's last error message)
+bool device_addressable(const void* p);
+bool all_addressable(std::initializer_list<const void*> ps);
+fams_status_t guarded(const std::function<fams_status_t()>& f);
 
 // dynamic LDS budget of one workgroup on this device (bytes, <= 160 KiB), and
 // raising a kernel's dynamic LDS limit to `bytes` (api.hip)
@@ -314,10 +333,23 @@ void build_ilu(Handle* h);
 void build_block_smoother(Handle* h);
 template <class T>
 void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y);
+// the same for K right-hand sides in lock-step, vectors interleaved x[i * K + r]
+template <class T, int K>
+void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y);
 // solve.hip
 fams_status_t solve_one(Handle* h, const double* q, double* p, const fams_solve_opts_t* o,
                         fams_info_t* info);
+// block.hip: nrhs right-hand sides (column-major) in lock-step groups
+fams_status_t solve_block(Handle* h, const double* q, double* p, int nrhs,
+                          const fams_solve_opts_t* o, fams_info_t* info);
 void apply_stage_fp64(Handle* h, const double* r, double* z);
+// the stage's scratch in a caller-provided region: bytes needed, and the
+// stage run with its scratch there (solve.hip)
+size_t stage_scratch_bytes(Handle* h);
+void apply_stage_in(Handle* h, void* base, const double* r, double* z);
+// noalloc.hip: the stage with its scratch in the library's static device array
+void apply_stage_noalloc(Handle* h, const double* r, double* z);
+size_t noalloc_scratch_capacity();
 void ensure_workspace(Handle* h, int restart);
 // flux.hip
 double reconstruct_flux(Handle* h, const double* q, const double* p, double* flux,

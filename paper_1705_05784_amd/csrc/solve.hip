@@ -215,6 +215,7 @@ __global__ void k_backsolve(GmresState s, int m, int k) {
 // ---- helpers ------------------------------------------------------------------
 struct Work {
   double *r, *w, *d1, *z, *rc, *xc, *part, *V, *Z;
+  double* gpart;  // partial sums of the coarse matrix-vector product
   float *r32, *d1_32, *rh32, *x32, *y32;
   double *rh, *x, *y;
   GmresState gs;
@@ -238,6 +239,7 @@ Work work_of(Handle* h) {
   k.Z = k.V + static_cast<int64_t>(m + 1) * n;
   double* s = h->red.get();
   k.part = s;
+  k.gpart = h->gpart.get();
   double* hs = h->hred.get();
   k.rc = hs;
   k.xc = hs + h->nc;
@@ -326,7 +328,7 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
   }
   LAUNCH(h, "restrict", (k_spmv_wave<T, T>), blocks_for(nc, 4), 256, 0, nc, h->r_rp.get(),
          h->r_ci.get(), rv, rT, k.rc);
-  coarse_apply(h, h->Ainv.get(), nc, k.rc, k.xc, h->gpart.get());
+  coarse_apply(h, h->Ainv.get(), nc, k.rc, k.xc, k.gpart);
   LAUNCH(h, "prolong", (k_spmv8<T, double, T>), blocks_for(n, kT / kSub), kT, 0, n,
          h->p_rp.get(), h->p_ci.get(), pv, k.xc, d1);
   if (h->smoother) {
@@ -499,6 +501,57 @@ fams_status_t solve_one(Handle* h, const double* q, double* p, const fams_solve_
 void apply_stage_fp64(Handle* h, const double* r, double* z) {
   ensure_workspace(h, 1);
   Work k = work_of(h);
+  stage_any(h, k, r, z);
+  HIPX(hipStreamSynchronize(h->stream));
+  check_sweeps(h);
+}
+
+// The stage's scratch inside one caller-provided region of device memory:
+// [rc | xc | gpart | d1 rh x y] (FP64 handles) or [rc | xc | gpart | r32 d1
+// rh x y] in float (precision form), each part 256-byte aligned.  Returns
+// the bytes needed; with `base` != null, also fills `k`.
+static size_t stage_scratch_layout(Handle* h, void* base, Work* k) {
+  const size_t n = h->n, nc = h->nc, nch = (nc + 63) / 64;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t o_xc = up(nc * sizeof(double));
+  const size_t o_gp = o_xc + up(nc * sizeof(double));
+  const size_t o_v = o_gp + up(nch * nc * sizeof(double));
+  const bool mixed = h->precision == FAMS_PREC_MIXED;
+  const size_t vb = up(n * (mixed ? sizeof(float) : sizeof(double)));
+  const size_t total = o_v + (mixed ? 5 : 4) * vb;
+  if (base && k) {
+    char* b = static_cast<char*>(base);
+    *k = Work{};
+    k->rc = reinterpret_cast<double*>(b);
+    k->xc = reinterpret_cast<double*>(b + o_xc);
+    k->gpart = reinterpret_cast<double*>(b + o_gp);
+    if (mixed) {
+      float* f[5];
+      for (int i = 0; i < 5; ++i) f[i] = reinterpret_cast<float*>(b + o_v + i * vb);
+      k->r32 = f[0];
+      k->d1_32 = f[1];
+      k->rh32 = f[2];
+      k->x32 = f[3];
+      k->y32 = f[4];
+    } else {
+      double* d[4];
+      for (int i = 0; i < 4; ++i) d[i] = reinterpret_cast<double*>(b + o_v + i * vb);
+      k->d1 = d[0];
+      k->rh = d[1];
+      k->x = d[2];
+      k->y = d[3];
+    }
+  }
+  return total;
+}
+
+size_t stage_scratch_bytes(Handle* h) { return stage_scratch_layout(h, nullptr, nullptr); }
+
+// the stage with its scratch in `base` (stage_scratch_bytes bytes); the
+// handle's own structures were all allocated by the setup
+void apply_stage_in(Handle* h, void* base, const double* r, double* z) {
+  Work k;
+  stage_scratch_layout(h, base, &k);
   stage_any(h, k, r, z);
   HIPX(hipStreamSynchronize(h->stream));
   check_sweeps(h);

@@ -64,13 +64,14 @@ class SetupInfo(C.Structure):
                 ("max_block", C.c_int64), ("fp32_fallback_blocks", C.c_int64),
                 ("ilu_levels_lower", C.c_int64), ("ilu_levels_upper", C.c_int64),
                 ("ms_setup", C.c_double), ("device_bytes", C.c_int64),
-                ("local_flops", C.c_double), ("local_subst_flops", C.c_double)]
+                ("local_flops", C.c_double), ("local_subst_flops", C.c_double),
+                ("peak_device_bytes", C.c_int64)]
 
 
 EXPORTS = {
     "fams_status_string": ([C.c_int], C.c_char_p),
     "fams_last_error": ([], C.c_char_p),
-    "fams_footprint": ([C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+    "fams_footprint": ([C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                         C.POINTER(C.c_size_t)], C.c_int),
     "fams_setup": ([C.POINTER(CSR), C.POINTER(Grid), C.POINTER(SetupOpts), C.c_void_p,
                     C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
@@ -143,9 +144,10 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def footprint(n, nnz, n_coarse, precision=FP64, restart=30) -> int:
+def footprint(n, nnz, n_coarse, precision=FP64, restart=30, max_nrhs=1) -> int:
     out = C.c_size_t()
-    _check(lib().fams_footprint(n, nnz, n_coarse, precision, restart, C.byref(out)), "footprint")
+    _check(lib().fams_footprint(n, nnz, n_coarse, precision, restart, max_nrhs, C.byref(out)),
+           "footprint")
     return int(out.value)
 
 
@@ -211,6 +213,10 @@ class Solver:
         if p is None:
             p = torch.zeros_like(q)
             use_initial_guess = False
+        else:  # the library reads and writes p on the device
+            p = torch.as_tensor(p).to(self.device, torch.float64).contiguous()
+            if p.shape != q.shape:
+                raise ValueError("solve: p must have the shape of q")
         if isinstance(outer, str):
             outer = {"richardson": RICHARDSON, "gmres": GMRES}[outer]
         opts = SolveOpts(int(outer), int(restart), float(rtol), int(max_iter),

@@ -18,6 +18,19 @@ import sqlite3
 import sys
 
 
+def source_digest() -> str:
+    """Hash of the library's HIP and C++ sources: a measured traffic figure is
+    only valid for the code it was measured on."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
 def short(name: str) -> str:
     n = name.replace("fams::(anonymous namespace)::", "").replace("void ", "")
     out = ""
@@ -111,6 +124,14 @@ LAUNCH_NAMES = {
     "k_local_solve<float, float>": "local_solve",
     "k_sweep_ranges<float, false>": "ilu_lower", "k_sweep_ranges<float, true>": "ilu_upper",
     "k_sweep_lower<float>": "ilu_lower", "k_sweep_upper<float>": "ilu_upper",
+    # lock-step kernels of the precision form with 16 right-hand sides
+    "k_bsweep<float, false, 16>": "bilu_lower", "k_bsweep<float, true, 16>": "bilu_upper",
+    "k_bspmv<double, double, double, double, 16, true>": "bresid_outer",
+    "k_bspmv<double, double, double, double, 16, false>": "bspmv",
+    "k_bspmv<float, float, float, float, 16, true>": "bspmv_resid",
+    "k_bspmv<float, double, float, float, 16, false>": "bprolong",
+    "k_brestrict<float, float, 16>": "brestrict", "k_bcoarse_part<16>": "bcoarse",
+    "k_gemm_mfma128": "gemm_mfma",
 }
 
 
@@ -120,9 +141,6 @@ def _main(argv):
         sys.stdout.write(trace_markdown(argv[1], argv[2], argv[3], top))
         return 0
     if len(argv) == 5 and argv[0] == "traffic":
-        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        sys.path.insert(0, root)
-        from bench import source_digest
         out = traffic(argv[1], argv[2], int(argv[3]), argv[4], source_digest(), LAUNCH_NAMES)
         print(json.dumps({k: round(v["traffic_bytes_per_launch"]) for k, v in
                           out["kernels"].items()}, indent=1))

@@ -67,12 +67,13 @@ def prepare(requests, coarse=(10, 10, 10), d_min=8, r_z=8):
 
 
 def request_footprint(req, precision: int, restart: int = 30) -> int:
-    """Device bytes a request may hold: the library's setup + workspace bound,
-    the borrowed inputs and the right-hand-side / pressure buffers."""
+    """Device bytes a request may hold: the library's setup + workspace bound
+    (lock-step work space for all of its right-hand sides), the borrowed
+    inputs and the right-hand-side / pressure buffers."""
     from . import fams
     s = req.system
     nc = int(req.meta["n_coarse"])
-    lib_bytes = fams.footprint(s.n, s.nnz, nc, precision, restart)
+    lib_bytes = fams.footprint(s.n, s.nnz, nc, precision, restart, int(req.rhs.shape[0]))
     inputs = 8 * (s.n + 1) + 12 * s.nnz + 13 * s.n + 8 * nc
     vectors = 2 * 8 * s.n * req.rhs.shape[0] + 2 * 8 * s.nnz
     return int(lib_bytes + inputs + vectors)
@@ -93,19 +94,19 @@ def _execute(system, grid, variant, rhs, precision, alpha, rtol, restart, flux, 
     try:
         out["setup_ms"] = (time.perf_counter() - t0) * 1e3
         q = torch.from_numpy(np.ascontiguousarray(rhs)).to("cuda")
-        ps = []
-        for k in range(q.shape[0]):
-            p, info = solver.solve(q[k], outer=fams.GMRES, restart=restart, rtol=rtol)
-            out["iterations"].append(info[0]["iterations"])
-            out["rel_residual"].append(info[0]["rel_residual"])
-            out["status"] = max(out["status"], info[0]["status"])
+        # every right-hand side of the request in one call: lock-step groups
+        P, infos = solver.solve(q if q.shape[0] > 1 else q[0], outer=fams.GMRES,
+                                restart=restart, rtol=rtol)
+        P = P.reshape(q.shape)
+        for k, info in enumerate(infos):
+            out["iterations"].append(info["iterations"])
+            out["rel_residual"].append(info["rel_residual"])
+            out["status"] = max(out["status"], info["status"])
             if flux:
-                _, _, imb = solver.reconstruct_flux(q[k], p)
+                _, _, imb = solver.reconstruct_flux(q[k], P[k])
                 out["imbalance"].append(imb)
-            if keep:
-                ps.append(p)
         if keep:
-            out["pressures"] = torch.stack(ps).cpu().numpy()
+            out["pressures"] = P.cpu().numpy()
         torch.cuda.current_stream().synchronize()
     finally:
         solver.close()
@@ -372,6 +373,11 @@ def _main(argv=None):
     ap = argparse.ArgumentParser(description="F-AMS serving run (continuous batching)")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--load", type=float, default=None,
+                    help="arrival rate as a fraction of the measured closed-loop capacity "
+                         "(overrides --rate): the first --probe requests are first run with "
+                         "all arrivals at t = 0, and their completions per second set mu")
+    ap.add_argument("--probe", type=int, default=48)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--pool", type=int, default=8, help="distinct systems in the stream")
     ap.add_argument("--side", type=int, nargs=2, default=(32, 128))
@@ -379,12 +385,29 @@ def _main(argv=None):
     ap.add_argument("--fp64", action="store_true", help="plain FP64 form instead of mixed")
     a = ap.parse_args(argv)
     prec = fams.FP64 if a.fp64 else fams.MIXED
-    reqs = prepare(make_stream(a.requests, a.rate, pool=a.pool, seed=a.seed, side=tuple(a.side)))
+    reqs = prepare(make_stream(a.requests, 1.0, pool=a.pool, seed=a.seed, side=tuple(a.side)))
+    gaps = np.diff([0.0] + [r.arrival for r in reqs])   # unit-rate Poisson gaps
     cells = {r.rid: r.system.n for r in reqs}
     print(f"[serving] {len(reqs)} requests ready", file=sys.stderr, flush=True)
+    mu = None
     with ProcessRunner(a.slots, prec, alpha=1e-2, rtol=1e-6) as run:
         srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec))
+        rate = a.rate
+        if a.load is not None:
+            probe = reqs[:max(1, min(a.probe, len(reqs)))]
+            pres = srv.run(probe, realtime=False)
+            span = max(r.t_done for r in pres)
+            mu = len(probe) / span
+            rate = a.load * mu
+            print(f"[serving] closed-loop capacity {mu:.2f} requests/s -> rate {rate:.2f}",
+                  file=sys.stderr, flush=True)
+        t = 0.0
+        for r, g in zip(reqs, gaps):
+            t += g / rate
+            r.arrival = t
+        srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec))
         res = srv.run(reqs, realtime=True)
+    a.rate = rate
     out = summarize(res, cells)
     errs = {}
     for r in res:
@@ -392,7 +415,8 @@ def _main(argv=None):
             key = r.error.split(":")[0] + ": " + r.error.split(":")[-1].strip()[:120]
             errs.setdefault(key, []).append((r.rid, cells[r.rid]))
     out["errors"] = {k: v for k, v in errs.items()}
-    out.update(slots=a.slots, rate=a.rate, precision="fp64" if a.fp64 else "mixed",
+    out.update(slots=a.slots, rate=a.rate, load=a.load, capacity_requests_per_s=mu,
+               precision="fp64" if a.fp64 else "mixed",
                peak_inflight=srv.peak_inflight, peak_reserved_gb=srv.peak_reserved / 2**30,
                mean_setup_ms=float(np.mean([r.setup_ms for r in res if r.status >= 0])),
                mean_iterations=float(np.mean([np.mean(r.iterations) for r in res if r.iterations])),

@@ -10,7 +10,7 @@ def _say(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("n", [1, 37, 64, 130, 600])
+@pytest.mark.parametrize("n", [1, 37, 64, 130, 600, 2000, 2049])
 def test_mfma_product(n):
     from paper_1705_05784_amd import fams
     _say(f"[dense] product n={n}")
@@ -20,7 +20,7 @@ def test_mfma_product(n):
     assert np.abs(c - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("n", [1, 37, 100, 700, 1855])
+@pytest.mark.parametrize("n", [1, 37, 100, 256, 257, 700, 1855, 4100])
 def test_spd_gauss_jordan(n):
     from paper_1705_05784_amd import fams
     _say(f"[dense] gauss-jordan n={n}")

@@ -90,6 +90,15 @@ class FracturedSystem:
         return m.hexdigest()
 
 
+def system_key(row_ptr, col, val, q) -> str:
+    """SHA-256 (24 hex digits) of a system and one right-hand side: the key
+    under which a reference pressure computed for exactly this input is kept."""
+    m = hashlib.sha256()
+    for a in (row_ptr, col, val, q):
+        m.update(np.ascontiguousarray(a).tobytes())
+    return m.hexdigest()[:24]
+
+
 def lnk_field(shape, std, corr, rng):
     """Gaussian random field: iid N(0,1), Gaussian filter, standardised, scaled."""
     z = rng.standard_normal(shape)
