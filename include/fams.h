@@ -238,9 +238,6 @@ fams_status_t fams_get_ilu(fams_handle_t h, double* lu_val);
 /* One application of Table 1 steps 5-7 to a residual r: z = dp_{1/2} +
  * dp_{2/2} (device [n] each). */
 fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
-/* Per-kernel timing with HIP events on the handle's stream: enable (1) or
- * disable (0); then read total milliseconds and launch counts per kernel
- * name (host strings valid until the handle is destroyed). */
 /* The dense kernels of the coarse system on an n x n column-major FP64
  * matrix a (device), result in out (device, n x n), on the default stream:
  *   op 0: out = a a          (the FP64 MFMA product used by the inverses)
@@ -255,6 +252,9 @@ fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
  * For tests of those kernels; blocking. */
 fams_status_t fams_dense_op(int32_t op, int32_t n, const double* a, double* out);
 
+/* Per-kernel timing with HIP events on the handle's stream: enable (1) or
+ * disable (0); then read total milliseconds and launch counts per kernel
+ * name (host strings valid until the handle is destroyed). */
 fams_status_t fams_set_profiling(fams_handle_t h, int32_t on);
 fams_status_t fams_get_kernel_stats(fams_handle_t h, int32_t max_entries, int32_t* n_entries,
                                     const char** names, double* total_ms, int64_t* launches);

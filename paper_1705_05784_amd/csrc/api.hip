@@ -223,11 +223,16 @@ __global__ void k_d2f_api(int64_t n, const double* a, float* b) {
 bool device_addressable(const void* p) {
   if (!p) return false;
   hipPointerAttribute_t a{};
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
+    g_last_error = std::string("an array argument is not memory the device can address "
+                               "(hipPointerGetAttributes: ") + hipGetErrorString(e) + ")";
     return false;
   }
-  return a.devicePointer != nullptr || a.isManaged != 0;
+  if (a.devicePointer != nullptr || a.isManaged != 0) return true;
+  g_last_error = "an array argument is host memory the device cannot address";
+  return false;
 }
 
 bool all_addressable(std::initializer_list<const void*> ps) {

@@ -217,23 +217,65 @@ __device__ void store_dots(const double* acc, int nb, int v0, double* part, int 
   }
 }
 
+// sum over the lanes of a workgroup of 256 that share tid % (K/2), i.e. the
+// same pair (2l, 2l + 1) of right-hand sides in the two-element kernels
+// below; valid in threads 0 .. K/2 - 1
+template <int K>
+__device__ double pair_sum(double v) {
+  constexpr int H = K / 2;
+  __shared__ double s[4][H];
+  for (int o = 32; o >= H; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l < H) s[w][l] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < H)
+    for (int q = 0; q < 4; ++q) t += s[q][threadIdx.x];
+  return t;
+}
+
+// the streaming Krylov kernels take two consecutive entries per thread (one
+// 16-byte load per vector; K is even, so both entries are of one row and of
+// right-hand sides 2l and 2l + 1)
+template <int K>
+__device__ void store_pair(double s0, double s1, int v, double* part, int pstride) {
+  s0 = pair_sum<K>(s0);
+  s1 = pair_sum<K>(s1);
+  if (threadIdx.x < K / 2) {
+    double* o = part + (static_cast<int64_t>(blockIdx.x) * pstride + v) * K + 2 * threadIdx.x;
+    o[0] = s0;
+    o[1] = s1;
+  }
+}
+
 template <int K>
 __global__ void __launch_bounds__(256)
 k_bmdot_part(int64_t nk, int nv, const double* V, int64_t ldv, const double* w, double* part,
              int pstride) {
+  const int64_t n2 = nk / 2;
+  const double2* w2 = reinterpret_cast<const double2*>(w);
   for (int v0 = 0; v0 < nv; v0 += kDotBatch) {
     const int nb = min(kDotBatch, nv - v0);
-    double acc[kDotBatch];
+    double a0[kDotBatch], a1[kDotBatch];
 #pragma unroll
-    for (int u = 0; u < kDotBatch; ++u) acc[u] = 0.0;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nk;
+    for (int u = 0; u < kDotBatch; ++u) a0[u] = a1[u] = 0.0;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n2;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-      const double we = w[e];
+      const double2 we = w2[e];
 #pragma unroll
       for (int u = 0; u < kDotBatch; ++u)
-        if (u < nb) acc[u] += V[(v0 + u) * ldv + e] * we;
+        if (u < nb) {
+          const double2 x = reinterpret_cast<const double2*>(V + (v0 + u) * ldv)[e];
+          a0[u] += x.x * we.x;
+          a1[u] += x.y * we.y;
+        }
     }
-    store_dots<K>(acc, nb, v0, part, pstride);
+#pragma unroll
+    for (int u = 0; u < kDotBatch; ++u) {
+      if (u >= nb) break;
+      store_pair<K>(a0[u], a1[u], v0 + u, part, pstride);
+    }
   }
 }
 
@@ -281,18 +323,28 @@ template <int K>
 __global__ void __launch_bounds__(256)
 k_bmaxpy_norm(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef, int cstride,
               double* w, double* part) {
-  double acc = 0.0;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nk;
+  const int64_t n2 = nk / 2;
+  double2* w2 = reinterpret_cast<double2*>(w);
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n2;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double* c = coef + static_cast<int64_t>(e % K) * cstride;
-    double s = 0.0;
-    for (int v = 0; v < nv; ++v) s += c[v] * V[v * ldv + e];
-    const double we = w[e] - s;
-    w[e] = we;
-    acc += we * we;
+    const int r = static_cast<int>((2 * e) % K);
+    const double* c0 = coef + static_cast<int64_t>(r) * cstride;
+    const double* c1 = c0 + cstride;
+    double s0 = 0.0, s1 = 0.0;
+    for (int v = 0; v < nv; ++v) {
+      const double2 x = reinterpret_cast<const double2*>(V + v * ldv)[e];
+      s0 += c0[v] * x.x;
+      s1 += c1[v] * x.y;
+    }
+    double2 we = w2[e];
+    we.x -= s0;
+    we.y -= s1;
+    w2[e] = we;
+    a0 += we.x * we.x;
+    a1 += we.y * we.y;
   }
-  const double t = group_sum<K>(acc);
-  if (threadIdx.x < K) part[static_cast<int64_t>(blockIdx.x) * K + threadIdx.x] = t;
+  store_pair<K>(a0, a1, 0, part, 1);
 }
 
 // out[r * ostride + v] = sum over blocks of the partials of (v, r): one

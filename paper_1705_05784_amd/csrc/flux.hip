@@ -28,7 +28,16 @@ namespace fams {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kFvRefine = 2;  // refinement steps of the FV coarse solve
+// refinement of the FV coarse solve against the fine-scale defect: at least
+// kFvRefine steps, then more while the largest primal-block defect still
+// halves, at most kFvRefineMax (a block pinned at its coarse node in the
+// Neumann problems carries its whole remaining defect at that cell)
+constexpr int kFvRefine = 2;
+constexpr int kFvRefineMax = 10;
+// refinement steps of each block's Neumann solve with its resident factors:
+// at a high permeability contrast a block's local matrix is ill conditioned
+// and every step gains about -log10(cond * eps) digits of the balance
+constexpr int kNeumannRefine = 3;
 constexpr double kSingularRowsum = 1e-10;  // s_i <= this * max A_ii counts as zero
 
 __global__ void k_rowsum_diag(int n, const int* rp, const int* ci, const double* av, double* s,
@@ -58,6 +67,20 @@ __global__ void k_max_reduce(int m, const double* part, double* out) {
   double v = 0.0;
   for (int k = threadIdx.x; k < m; k += blockDim.x) v = fmax(v, part[k]);
   red[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = kT / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// *out = max_k |v[k]| (one workgroup)
+__global__ void k_absmax(int m, const double* v, double* out) {
+  __shared__ double red[kT];
+  double a = 0.0;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) a = fmax(a, fabs(v[k]));
+  red[threadIdx.x] = a;
   __syncthreads();
   for (int k = kT / 2; k > 0; k >>= 1) {
     if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
@@ -169,8 +192,8 @@ struct PrimalEdge {
 // on the block, the right-hand side in flux form
 //   q_i - s_i p'_i + sum_{j != i} A_ij (p'_i - p'_j)   (s_i = row sum of A),
 // whose terms are of the size of the fluxes (not of A_ij p'_j, which at a
-// high permeability contrast are many orders larger), then one step of
-// iterative refinement with the resident factors.  A block without a
+// high permeability contrast are many orders larger), then kNeumannRefine
+// steps of iterative refinement with the resident factors.  A block without a
 // Dirichlet cell is pinned at its coarse node (d = 0 there).
 //
 // k_neumann assembles and factors block K (xs: the right-hand side, rs
@@ -210,11 +233,16 @@ __device__ void neumann_residual(int K, int beg, int n, int lv, const int* cells
 }
 
 __device__ void neumann_update(int beg, int n, const int* cells, const double* p1,
-                               const double* X, const double* R, double* p2, int t0, int dt) {
+                               const double* X, double* p2, int t0, int dt) {
   for (int l = t0; l < n; l += dt) {
     const int i = cells[beg + l];
-    p2[i] = p1[i] + (X[l] + R[l]);
+    p2[i] = p1[i] + X[l];
   }
+}
+
+// X += R (one refinement correction)
+__device__ void neumann_accumulate(int n, double* X, const double* R, int t0, int dt) {
+  for (int l = t0; l < n; l += dt) X[l] += R[l];
 }
 
 __global__ void __launch_bounds__(kT)
@@ -281,11 +309,17 @@ k_neumann(const int* ptr, const int* cells, const int* rp, const int* ci, const 
     if (mode == 0) band_export<double>(lds + band_panel_elems(b), G, n, b);
   } else {
     band_substitute<double, double>(B, n, b, X, 1, lds);
-    neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x,
-                     blockDim.x);
+    for (int it = 0; it < kNeumannRefine; ++it) {
+      __syncthreads();
+      neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x,
+                       blockDim.x);
+      __syncthreads();
+      band_substitute<double, double>(B, n, b, R, 1, lds);
+      __syncthreads();
+      neumann_accumulate(n, X, R, threadIdx.x, blockDim.x);
+    }
     __syncthreads();
-    band_substitute<double, double>(B, n, b, R, 1, lds);
-    neumann_update(beg, n, cells, p1, X, R, p2, threadIdx.x, blockDim.x);
+    neumann_update(beg, n, cells, p1, X, p2, threadIdx.x, blockDim.x);
   }
   if (bad && threadIdx.x == 0) atomicOr(err, 1);
   if (tk && threadIdx.x == 0) tk[4] = wall_clock64();
@@ -309,12 +343,16 @@ k_neumann_solve(const int* list, int nc, const int* ptr, const int* cells, const
   const double* Rq = rs + ptr[nc] + beg;
   const int lv = singular[K] != 0 ? local[vertex[K]] : -1;
   band_wave_columns<double, double, double, M, 1, 4>(G, Lt, 1, 0, n, b, X, 1, 0, X);
+  for (int it = 0; it < kNeumannRefine; ++it) {
+    __syncthreads();
+    neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x, 64);
+    __syncthreads();
+    band_wave_columns<double, double, double, M, 1, 4>(G, Lt, 1, 0, n, b, R, 1, 0, R);
+    __syncthreads();
+    neumann_accumulate(n, X, R, threadIdx.x, 64);
+  }
   __syncthreads();
-  neumann_residual(K, beg, n, lv, cells, rp, ci, av, primal, local, X, Rq, R, threadIdx.x, 64);
-  __syncthreads();
-  band_wave_columns<double, double, double, M, 1, 4>(G, Lt, 1, 0, n, b, R, 1, 0, R);
-  __syncthreads();
-  neumann_update(beg, n, cells, p1, X, R, p2, threadIdx.x, 64);
+  neumann_update(beg, n, cells, p1, X, p2, threadIdx.x, 64);
 }
 
 __global__ void k_flux(int n, const int* rp, const int* ci, const double* av, const int* primal,
@@ -360,7 +398,7 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   const unsigned g = blocks_for(n, kT);
   ensure_workspace(h, 1);
   // ---- lazy FV setup (kept in the handle) ----
-  DBuf<double> s(A, n), dpart(A, g), dmax(A, 1);
+  DBuf<double> s(A, n), dpart(A, g), dmax(A, 2);
   LAUNCH(h, "flux_rowsum", k_rowsum_diag, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(),
          s.get(), dpart.get());
   LAUNCH(h, "flux_max", k_max_reduce, 1, kT, 0, (int)g, dpart.get(), dmax.get());
@@ -431,13 +469,26 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   // iterative refinement against the fine-scale defect R^FV (q - A p'), with
   // p' = p + P x: it removes the coarse solve's error and the rounding of the
   // dense FV operator itself, which bounds the blocks' conservation
-  for (int it = 0; it < kFvRefine; ++it) {
+  double prev = 0.0;
+  for (int it = 0; it < kFvRefineMax; ++it) {
     LAUNCH(h, "flux_prolong", k_prolong_add, g, kT, 0, n, h->p_rp.get(), h->p_ci.get(),
            h->p_val.get(), x.get(), p, p1.get());
     LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(),
            p1.get(), q, r.get());
     LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
            h->fv_order.get(), r.get(), t.get());
+    if (it >= kFvRefine) {  // keep refining only while the block defects still halve
+      double m = 0.0;
+      LAUNCH(h, "flux_max", k_absmax, 1, kT, 0, nc, t.get(), dmax.get() + 1);
+      HIPX(hipMemcpyAsync(&m, dmax.get() + 1, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+      if (!(m < 0.5 * prev)) break;
+      prev = m;
+    } else if (it == kFvRefine - 1) {
+      LAUNCH(h, "flux_max", k_absmax, 1, kT, 0, nc, t.get(), dmax.get() + 1);
+      HIPX(hipMemcpyAsync(&prev, dmax.get() + 1, sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    }
     fv_solve(t, t2);
     LAUNCH(h, "flux_add", k_add_to, blocks_for(nc, kT), kT, 0, nc, t2.get(), x.get());
   }

@@ -150,7 +150,7 @@ extern "C" fams_status_t fams_grid_fracture(
     int64_t i = n_matrix + c;
     for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
       int64_t j = col_idx[q];
-      if (j >= n_matrix && j != i) fadj.push_back(j - n_matrix);
+      if (j >= n_matrix && j < n && j != i) fadj.push_back(j - n_matrix);  // fracture cells only
     }
     fptr[c + 1] = static_cast<int64_t>(fadj.size());
   }

@@ -1191,6 +1191,11 @@ void build_prolongation(Handle* h, const int8_t* wb) {
     pv64.reset(A, std::max<int64_t>(h_pval_off[ncomp], 1));
   }
   int64_t fallbacks = 0;
+  // FAMS_FORCE_FP64_BLOCKS=k (tests): in the precision form, blocks whose id
+  // is a multiple of k also take the FP64 re-solve, as if their FP32
+  // factorisation had met a non-positive pivot
+  int force_k = 0;
+  if (const char* e = std::getenv("FAMS_FORCE_FP64_BLOCKS")) force_k = std::max(0, std::atoi(e));
   for (auto [c0, c1] : levels) {
     HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
     std::vector<int> blocks(c1 - c0);
@@ -1205,7 +1210,7 @@ void build_prolongation(Handle* h, const int8_t* wb) {
                                    pv64.get(), h_comp_ptr, h_band, h_ncols, err, nullptr);
     }
     int ev = static_cast<int>(read1(h, err.get()));
-    if ((ev & E_PIVOT) && mixed) {
+    if (mixed && ((ev & E_PIVOT) || force_k > 0)) {
       // FP32 breakdown: re-solve the affected blocks of this level in FP64
       std::vector<int> hb(c1 - c0);
       HIPX(hipMemcpyAsync(hb.data(), bad_block.get() + c0, (c1 - c0) * sizeof(int),
@@ -1213,13 +1218,15 @@ void build_prolongation(Handle* h, const int8_t* wb) {
       HIPX(hipStreamSynchronize(h->stream));
       std::vector<int> redo;
       for (int k = 0; k < c1 - c0; ++k)
-        if (hb[k]) redo.push_back(c0 + k);
+        if (hb[k] || (force_k > 0 && (c0 + k) % force_k == 0)) redo.push_back(c0 + k);
       fallbacks += static_cast<int64_t>(redo.size());
-      HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
-      local_solves<float, double>(h, redo, true, comp_ptr, cells, ecls, wb, coarse_of, comp_of,
-                                  local_idx, col_ptr, cols, ncols, band, pval_off, pv32.get(),
-                                  h_comp_ptr, h_band, h_ncols, err, nullptr);
-      ev = static_cast<int>(read1(h, err.get()));
+      if (!redo.empty()) {
+        HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+        local_solves<float, double>(h, redo, true, comp_ptr, cells, ecls, wb, coarse_of, comp_of,
+                                    local_idx, col_ptr, cols, ncols, band, pval_off, pv32.get(),
+                                    h_comp_ptr, h_band, h_ncols, err, nullptr);
+        ev = static_cast<int>(read1(h, err.get()));
+      }
     }
     FAMS_REQUIRE(!(ev & E_PIVOT), FAMS_ERR_SINGULAR_LOCAL, "non-positive pivot in a local block");
     pt.mark("local solves (level)");

@@ -112,6 +112,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1705_05784_amd.build` (no fallback exists)")
+        # torch first: it ships its own HIP runtime under the same soname as
+        # the system's, and the library must bind to the runtime that owns
+        # the tensors it is handed
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in EXPORTS.items():
             f = getattr(L, name)
@@ -314,7 +321,7 @@ def grid_structured(nx, ny, nz, cx, cy, cz):
 
 def grid_fracture(sysm, n_coarse_matrix, d_min, r_z):
     """Fracture classes/primal/vertices for a workloads.FracturedSystem."""
-    nf = sysm.n - sysm.n_matrix
+    nf = sysm.n - sysm.n_matrix - getattr(sysm, "n_wells", 0)
     wb = np.empty(nf, dtype=np.int8)
     pr = np.empty(nf, dtype=np.int32)
     vx = np.empty(max(nf, 1), dtype=np.int64)
@@ -324,7 +331,8 @@ def grid_fracture(sysm, n_coarse_matrix, d_min, r_z):
     cc, cz = a(sysm.cell_col, np.int32), a(sysm.cell_z, np.int32)
     cp, cptr, cadj = a(sysm.col_plate, np.int32), a(sysm.col_ptr, np.int64), a(sysm.col_adj, np.int32)
     zlo, zhi = a(sysm.plate_zlo, np.int32), a(sysm.plate_zhi, np.int32)
-    _check(lib().fams_grid_fracture(sysm.n_matrix, sysm.n, rp.ctypes.data, ci.ctypes.data,
+    _check(lib().fams_grid_fracture(sysm.n_matrix, sysm.n_matrix + nf, rp.ctypes.data,
+                                    ci.ctypes.data,
                                     cc.ctypes.data, cz.ctypes.data, len(cp), cp.ctypes.data,
                                     cptr.ctypes.data, cadj.ctypes.data, len(zlo), zlo.ctypes.data,
                                     zhi.ctypes.data, int(d_min), int(r_z), int(n_coarse_matrix),
@@ -334,11 +342,18 @@ def grid_fracture(sysm, n_coarse_matrix, d_min, r_z):
 
 
 def full_grid(sysm, coarse, d_min, r_z):
-    """Matrix + fracture grid of a workloads.FracturedSystem through the library."""
+    """Matrix + fracture grid of a workloads.FracturedSystem through the
+    library's helpers; each well (the last sysm.n_wells unknowns) is a
+    coarse node of its own, appended after the fracture nodes."""
+    nw = getattr(sysm, "n_wells", 0)
     wbm, pm, vm = grid_structured(sysm.nx, sysm.ny, sysm.nz, *coarse)
     wbf, pf, vf = grid_fracture(sysm, len(vm), d_min, r_z)
-    return (np.concatenate([wbm, wbf]), np.concatenate([pm, pf]), np.concatenate([vm, vf]),
-            len(vm))
+    nc0 = len(vm) + len(vf)
+    wbw = np.full(nw, 3, dtype=np.int8)
+    pw = np.arange(nc0, nc0 + nw, dtype=np.int32)
+    vw = np.arange(sysm.n - nw, sysm.n, dtype=np.int64)
+    return (np.concatenate([wbm, wbf, wbw]), np.concatenate([pm, pf, pw]),
+            np.concatenate([vm, vf, vw]), len(vm))
 
 
 def setup(sysm, coarse, d_min, r_z, **kw) -> Solver:
