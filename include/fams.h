@@ -238,6 +238,19 @@ fams_status_t fams_get_ilu(fams_handle_t h, double* lu_val);
 /* One application of Table 1 steps 5-7 to a residual r: z = dp_{1/2} +
  * dp_{2/2} (device [n] each). */
 fams_status_t fams_apply_stage(fams_handle_t h, const double* r, double* z);
+/* fams_apply_stage without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and result as fams_apply_stage (the same
+ * kernels in the same order); the stage's scratch vectors live in one static
+ * device array of 128 MiB that every GPU the library runs on holds until the
+ * process ends, shared by all calls on that GPU: calls that overlap on one GPU
+ * race.  The scratch needs 32n + 8 n_c (2 + ceil(n_c / 64)) bytes (FP64) or
+ * 20n + the same coarse part (precision form), each part rounded up to 256
+ * bytes; a larger system is refused with FAMS_ERR_CAPACITY.  Kernel timing
+ * (fams_set_profiling) is not recorded for this call.  Synchronises the
+ * handle's stream. */
+fams_status_t fams_apply_stage_noalloc(fams_handle_t h, const double* r, double* z);
+
 /* The dense kernels of the coarse system on an n x n column-major FP64
  * matrix a (device), result in out (device, n x n), on the default stream:
  *   op 0: out = a a          (the FP64 MFMA product used by the inverses)

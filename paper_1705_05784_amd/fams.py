@@ -89,6 +89,7 @@ EXPORTS = {
     "fams_get_coarse_matrix": ([C.c_void_p, C.c_void_p], C.c_int),
     "fams_get_ilu": ([C.c_void_p, C.c_void_p], C.c_int),
     "fams_apply_stage": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "fams_apply_stage_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "fams_set_profiling": ([C.c_void_p, C.c_int32], C.c_int),
     "fams_get_kernel_stats": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                C.POINTER(C.c_char_p), C.POINTER(C.c_double),
