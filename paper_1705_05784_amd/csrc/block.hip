@@ -263,13 +263,15 @@ k_bmdot_part(int64_t nk, int nv, const double* V, int64_t ldv, const double* w, 
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n2;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
       const double2 we = w2[e];
+      // all loads of the batch unconditional (past nv they repeat the last
+      // vector and their sums are dropped), so they issue back to back
 #pragma unroll
-      for (int u = 0; u < kDotBatch; ++u)
-        if (u < nb) {
-          const double2 x = reinterpret_cast<const double2*>(V + (v0 + u) * ldv)[e];
-          a0[u] += x.x * we.x;
-          a1[u] += x.y * we.y;
-        }
+      for (int u = 0; u < kDotBatch; ++u) {
+        const double2 x =
+            reinterpret_cast<const double2*>(V + static_cast<int64_t>(min(v0 + u, nv - 1)) * ldv)[e];
+        a0[u] += x.x * we.x;
+        a1[u] += x.y * we.y;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kDotBatch; ++u) {
@@ -279,61 +281,222 @@ k_bmdot_part(int64_t nk, int nv, const double* V, int64_t ldv, const double* w, 
   }
 }
 
+// The two streaming passes below read up to kFuseMax basis vectors per
+// entry.  Every vector is addressed as a uniform base (scalar registers)
+// plus one byte offset shared by all of them (a 32-bit vector register):
+// left to itself, the compiler's loop strength reduction keeps one 64-bit
+// pointer per vector in vector registers, and the register pressure then
+// serialises the loads.  The empty asm statement hides the offset's
+// induction from that transformation.  Usable while a block vector is
+// under 4 GiB (checked on the host; larger ones take the general kernels).
+constexpr int kFuseMax = 4 * kDotBatch;
+
+// At most three waves per SIMD: lets the scheduler keep all of an entry's
+// loads in flight at once instead of trading them for occupancy (three
+// waves of 32 outstanding 16-byte loads per lane saturate HBM).
+#define FAMS_STREAM_WAVES __attribute__((amdgpu_waves_per_eu(1, 3)))
+
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <class T>
+__device__ __forceinline__ T load_at(const char* base, uint32_t off) {
+  return *reinterpret_cast<const T*>(base + off);
+}
+
 // the first Gram-Schmidt correction and the second pass's dots in one pass
 // over the rows: w <- w - sum_v coef[r, v] V_v, then the partial dots of the
 // new w with V_0..V_{nv-1}; each V value is loaded once and kept in a
-// register between the two uses (nv <= kFuseMax)
-constexpr int kFuseMax = 4 * kDotBatch;
-
-template <int K>
-__global__ void __launch_bounds__(256)
+// register between the two uses.  NV (a multiple of 4, nv <= NV <= kFuseMax)
+// fixes the register arrays at compile time, so the NV loads of an entry are
+// issued back to back with no branch between them: the vectors past nv
+// repeat V_{nv-1} (cache hits) with a zero coefficient, which leaves the sum
+// bit for bit what it is over nv vectors.  The grid stride is a multiple of
+// 256, so a thread keeps one right-hand side r = threadIdx.x % K and reads
+// its coefficients from LDS.
+template <int K, int NV>
+__global__ void __launch_bounds__(256) FAMS_STREAM_WAVES
 k_bmaxpy_mdot(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef, int cstride,
               double* w, double* part, int pstride) {
-  double acc[kFuseMax];
+  __shared__ double cs[K * NV];
+  for (int t = threadIdx.x; t < K * NV; t += blockDim.x) {
+    const int r = t / NV, v = t % NV;
+    cs[t] = v < nv ? coef[static_cast<int64_t>(r) * cstride + v] : 0.0;
+  }
+  __syncthreads();
+  const double* c = cs + (threadIdx.x % K) * NV;
+  const char* Vb = reinterpret_cast<const char*>(V);
+  char* wb = reinterpret_cast<char*>(w);
+  const int64_t ld8 = ldv * 8;
+  double acc[NV];
 #pragma unroll
-  for (int v = 0; v < kFuseMax; ++v) acc[v] = 0.0;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nk;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double* c = coef + static_cast<int64_t>(e % K) * cstride;
-    double vv[kFuseMax];
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const uint32_t end = static_cast<uint32_t>(nk * 8);
+  const uint32_t step = gridDim.x * blockDim.x * 8u;
+  for (uint32_t off0 = (blockIdx.x * blockDim.x + threadIdx.x) * 8u; off0 < end; off0 += step) {
+    const uint32_t off = opaque(off0);
+    double vv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vv[v] = load_at<double>(Vb + ld8 * min(v, nv - 1), off);
     double s = 0.0;
 #pragma unroll
-    for (int v = 0; v < kFuseMax; ++v)
-      if (v < nv) {
-        vv[v] = V[v * ldv + e];
-        s += c[v] * vv[v];
-      }
-    const double we = w[e] - s;
-    w[e] = we;
+    for (int v = 0; v < NV; ++v) s += c[v] * vv[v];
+    const double we = load_at<double>(wb, off) - s;
+    *reinterpret_cast<double*>(wb + off) = we;
 #pragma unroll
-    for (int v = 0; v < kFuseMax; ++v)
-      if (v < nv) acc[v] += vv[v] * we;
+    for (int v = 0; v < NV; ++v) acc[v] += vv[v] * we;
   }
 #pragma unroll
-  for (int a = 0; a < kFuseMax / kDotBatch; ++a) {
+  for (int a = 0; a < NV / kDotBatch + (NV % kDotBatch ? 1 : 0); ++a) {
     if (a * kDotBatch >= nv) break;
-    store_dots<K>(acc + a * kDotBatch, min(kDotBatch, nv - a * kDotBatch), a * kDotBatch, part,
-                  pstride);
+    double blk[kDotBatch];
+#pragma unroll
+    for (int u = 0; u < kDotBatch; ++u) blk[u] = a * kDotBatch + u < NV ? acc[a * kDotBatch + u] : 0.0;
+    store_dots<K>(blk, min(kDotBatch, nv - a * kDotBatch), a * kDotBatch, part, pstride);
   }
 }
 
-// the second correction and the norm: w <- w - sum_v coef[r, v] V_v, then
-// the partial sums of w^2 per right-hand side
+// block vectors of nk entries: can the offset-addressed passes take them?
+inline bool offset_addressable(int64_t nk, unsigned nb) {
+  return (nk * 8 + static_cast<int64_t>(nb) * kT * 16) < (int64_t(1) << 32);
+}
+
+// launch of the fused pass with NV = nv rounded up to a multiple of 4
 template <int K>
-__global__ void __launch_bounds__(256)
+void launch_bmaxpy_mdot(Handle* h, unsigned nb, int64_t nk, int nv, const double* V, int64_t ldv,
+                        const double* coef, int cstride, double* w, double* part, int pstride) {
+#define FAMS_MDOT(NV)                                                                          \
+  LAUNCH(h, "bmaxpy_mdot", (k_bmaxpy_mdot<K, NV>), nb, kT, 0, nk, nv, V, ldv, coef, cstride, w, \
+         part, pstride)
+  switch ((nv + 3) / 4) {
+    case 1: FAMS_MDOT(4); break;
+    case 2: FAMS_MDOT(8); break;
+    case 3: FAMS_MDOT(12); break;
+    case 4: FAMS_MDOT(16); break;
+    case 5: FAMS_MDOT(20); break;
+    case 6: FAMS_MDOT(24); break;
+    case 7: FAMS_MDOT(28); break;
+    case 8: FAMS_MDOT(32); break;
+    default: FAMS_REQUIRE(false, FAMS_ERR_CAPACITY, "fused Gram-Schmidt pass: too many vectors");
+  }
+#undef FAMS_MDOT
+}
+
+// the multi-dot h = V^T w of the first Gram-Schmidt pass, one entry per
+// thread with all NV loads in flight (as in the fused pass; vectors past nv
+// repeat the last one and their sums are dropped)
+template <int K, int NV>
+__global__ void __launch_bounds__(256) FAMS_STREAM_WAVES
+k_bmdot(int64_t nk, int nv, const double* V, int64_t ldv, const double* w, double* part,
+        int pstride) {
+  const char* Vb = reinterpret_cast<const char*>(V);
+  const char* wb = reinterpret_cast<const char*>(w);
+  const int64_t ld8 = ldv * 8;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const uint32_t end = static_cast<uint32_t>(nk * 8);
+  const uint32_t step = gridDim.x * blockDim.x * 8u;
+  for (uint32_t off0 = (blockIdx.x * blockDim.x + threadIdx.x) * 8u; off0 < end; off0 += step) {
+    const uint32_t off = opaque(off0);
+    const double we = load_at<double>(wb, off);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += load_at<double>(Vb + ld8 * min(v, nv - 1), off) * we;
+  }
+#pragma unroll
+  for (int a = 0; a < NV / kDotBatch + (NV % kDotBatch ? 1 : 0); ++a) {
+    if (a * kDotBatch >= nv) break;
+    double blk[kDotBatch];
+#pragma unroll
+    for (int u = 0; u < kDotBatch; ++u) blk[u] = a * kDotBatch + u < NV ? acc[a * kDotBatch + u] : 0.0;
+    store_dots<K>(blk, min(kDotBatch, nv - a * kDotBatch), a * kDotBatch, part, pstride);
+  }
+}
+
+template <int K>
+void launch_bmdot(Handle* h, const char* name, unsigned nb, int64_t nk, int nv, const double* V,
+                  int64_t ldv, const double* w, double* part, int pstride) {
+  if (nv > kFuseMax || !offset_addressable(nk, nb)) {
+    LAUNCH(h, name, k_bmdot_part<K>, nb, kT, 0, nk, nv, V, ldv, w, part, pstride);
+    return;
+  }
+#define FAMS_DOT(NV) \
+  LAUNCH(h, name, (k_bmdot<K, NV>), nb, kT, 0, nk, nv, V, ldv, w, part, pstride)
+  switch ((nv + 3) / 4) {
+    case 1: FAMS_DOT(4); break;
+    case 2: FAMS_DOT(8); break;
+    case 3: FAMS_DOT(12); break;
+    case 4: FAMS_DOT(16); break;
+    case 5: FAMS_DOT(20); break;
+    case 6: FAMS_DOT(24); break;
+    case 7: FAMS_DOT(28); break;
+    case 8: FAMS_DOT(32); break;
+  }
+#undef FAMS_DOT
+}
+
+// the second correction and the norm: w <- w - sum_v coef[r, v] V_v, then
+// the partial sums of w^2 per right-hand side, two entries per thread; NV as
+// in the fused pass above (loads past nv repeat the last vector with zero
+// coefficients)
+template <int K, int NV>
+__global__ void __launch_bounds__(256) FAMS_STREAM_WAVES
 k_bmaxpy_norm(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef, int cstride,
               double* w, double* part) {
+  __shared__ double cs[K * NV];
+  for (int t = threadIdx.x; t < K * NV; t += blockDim.x) {
+    const int r = t / NV, v = t % NV;
+    cs[t] = v < nv ? coef[static_cast<int64_t>(r) * cstride + v] : 0.0;
+  }
+  __syncthreads();
+  // the thread's pair of right-hand sides (2 e) % K is fixed: the grid
+  // stride is a multiple of 256 pairs
+  const double* c0 = cs + ((2 * threadIdx.x) % K) * NV;
+  const double* c1 = c0 + NV;
+  const char* Vb = reinterpret_cast<const char*>(V);
+  char* wb = reinterpret_cast<char*>(w);
+  const int64_t ld8 = ldv * 8;
+  double a0 = 0.0, a1 = 0.0;
+  const uint32_t end = static_cast<uint32_t>((nk / 2) * 16);
+  const uint32_t step = gridDim.x * blockDim.x * 16u;
+  for (uint32_t off0 = (blockIdx.x * blockDim.x + threadIdx.x) * 16u; off0 < end; off0 += step) {
+    const uint32_t off = opaque(off0);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double2 x = load_at<double2>(Vb + ld8 * min(v, nv - 1), off);
+      s0 += c0[v] * x.x;
+      s1 += c1[v] * x.y;
+    }
+    double2 we = load_at<double2>(wb, off);
+    we.x -= s0;
+    we.y -= s1;
+    *reinterpret_cast<double2*>(wb + off) = we;
+    a0 += we.x * we.x;
+    a1 += we.y * we.y;
+  }
+  store_pair<K>(a0, a1, 0, part, 1);
+}
+
+// the same for any nv and size (restart lengths above kFuseMax, block
+// vectors of 4 GiB or more): coefficients read from global memory inside
+// the loop over the basis
+template <int K>
+__global__ void __launch_bounds__(256)
+k_bmaxpy_norm_any(int64_t nk, int nv, const double* V, int64_t ldv, const double* coef,
+                  int cstride, double* w, double* part) {
   const int64_t n2 = nk / 2;
   double2* w2 = reinterpret_cast<double2*>(w);
+  const double* c0 = coef + static_cast<int64_t>((2 * threadIdx.x) % K) * cstride;
+  const double* c1 = c0 + cstride;
   double a0 = 0.0, a1 = 0.0;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n2;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int r = static_cast<int>((2 * e) % K);
-    const double* c0 = coef + static_cast<int64_t>(r) * cstride;
-    const double* c1 = c0 + cstride;
     double s0 = 0.0, s1 = 0.0;
     for (int v = 0; v < nv; ++v) {
-      const double2 x = reinterpret_cast<const double2*>(V + v * ldv)[e];
+      const double2 x = reinterpret_cast<const double2*>(V + static_cast<int64_t>(v) * ldv)[e];
       s0 += c0[v] * x.x;
       s1 += c1[v] * x.y;
     }
@@ -345,6 +508,30 @@ k_bmaxpy_norm(int64_t nk, int nv, const double* V, int64_t ldv, const double* co
     a1 += we.y * we.y;
   }
   store_pair<K>(a0, a1, 0, part, 1);
+}
+
+template <int K>
+void launch_bmaxpy_norm(Handle* h, unsigned nb, int64_t nk, int nv, const double* V, int64_t ldv,
+                        const double* coef, int cstride, double* w, double* part) {
+  if (nv > kFuseMax || !offset_addressable(nk, nb)) {
+    LAUNCH(h, "bmaxpy_norm", k_bmaxpy_norm_any<K>, nb, kT, 0, nk, nv, V, ldv, coef, cstride, w,
+           part);
+    return;
+  }
+#define FAMS_NORM(NV)                                                                          \
+  LAUNCH(h, "bmaxpy_norm", (k_bmaxpy_norm<K, NV>), nb, kT, 0, nk, nv, V, ldv, coef, cstride, w, \
+         part)
+  switch ((nv + 3) / 4) {
+    case 1: FAMS_NORM(4); break;
+    case 2: FAMS_NORM(8); break;
+    case 3: FAMS_NORM(12); break;
+    case 4: FAMS_NORM(16); break;
+    case 5: FAMS_NORM(20); break;
+    case 6: FAMS_NORM(24); break;
+    case 7: FAMS_NORM(28); break;
+    case 8: FAMS_NORM(32); break;
+  }
+#undef FAMS_NORM
 }
 
 // out[r * ostride + v] = sum over blocks of the partials of (v, r): one
@@ -647,7 +834,7 @@ void bstage_any(Handle* h, const BWork& k, const double* r, double* z) {
 // ||x_r|| of every right-hand side into S[r * stride + off]
 template <int K>
 void bnorms(Handle* h, const BWork& k, const double* x, int off) {
-  LAUNCH(h, "bdot", k_bmdot_part<K>, k.nb, kT, 0, k.nk, 1, x, k.nk, x, k.part, 1);
+  launch_bmdot<K>(h, "bdot", k.nb, k.nk, 1, x, k.nk, x, k.part, 1);
   LAUNCH(h, "breduce", k_breduce, dim3(1, K), 256, 0, k.nb, K, k.part, 1, k.small + off,
          k.st.stride);
   LAUNCH(h, "bsqrt", k_bsqrt, 1, 64, 0, K, k.small + off, k.st.stride);
@@ -730,12 +917,12 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
              static_cast<const double*>(nullptr), k.w);
       // CGS2 against V_0..V_j, per right-hand side: h = V^T w; w -= V h and
       // c = V^T w in one pass; w -= V c and ||w|| in one pass; h += c
-      LAUNCH(h, "bmdot", k_bmdot_part<K>, k.nb, kT, 0, nk, j + 1, k.V, nk, k.w, k.part, m + 2);
+      launch_bmdot<K>(h, "bmdot", k.nb, nk, j + 1, k.V, nk, k.w, k.part, m + 2);
       LAUNCH(h, "breduce", k_breduce, dim3(j + 1, K), 256, 0, k.nb, K, k.part, m + 2,
              k.small + S.hcol, S.stride);
-      if (j + 1 <= kFuseMax) {
-        LAUNCH(h, "bmaxpy_mdot", k_bmaxpy_mdot<K>, k.nb, kT, 0, nk, j + 1, k.V, nk,
-               k.small + S.hcol, S.stride, k.w, k.part, m + 2);
+      if (j + 1 <= kFuseMax && offset_addressable(nk, k.nb)) {
+        launch_bmaxpy_mdot<K>(h, k.nb, nk, j + 1, k.V, nk, k.small + S.hcol, S.stride, k.w,
+                              k.part, m + 2);
       } else {  // more basis vectors than the fused pass holds sums for
         LAUNCH(h, "bmaxpy", k_bmaxpy<K>, blocks_for(nk, kT), kT, 0, nk, j + 1, k.V, nk,
                k.small + S.hcol, S.stride, -1.0, k.w);
@@ -743,8 +930,7 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
       }
       LAUNCH(h, "breduce", k_breduce, dim3(j + 1, K), 256, 0, k.nb, K, k.part, m + 2,
              k.small + S.y, S.stride);
-      LAUNCH(h, "bmaxpy_norm", k_bmaxpy_norm<K>, k.nb, kT, 0, nk, j + 1, k.V, nk, k.small + S.y,
-             S.stride, k.w, k.part);
+      launch_bmaxpy_norm<K>(h, k.nb, nk, j + 1, k.V, nk, k.small + S.y, S.stride, k.w, k.part);
       LAUNCH(h, "breduce", k_breduce, dim3(1, K), 256, 0, k.nb, K, k.part, 1,
              k.small + S.hcol + j + 1, S.stride);
       LAUNCH(h, "bsqrt", k_bsqrt, 1, 64, 0, K, k.small + S.hcol + j + 1, S.stride);

@@ -116,3 +116,23 @@ def test_lockstep_media_smoothing_and_fv_restriction(precision):
         assert abs(info[r]["iterations"] - i1[0]["iterations"]) <= 1
         assert np.linalg.norm(P[r] - p1.cpu().numpy()) <= 1e-9 * np.linalg.norm(p1.cpu().numpy())
     g.close()
+
+
+@pytest.mark.parametrize("restart", [5, 40])
+def test_lockstep_restart_lengths(restart):
+    """Restart lengths on both sides of the fused Gram-Schmidt passes' basis
+    limit (32 vectors; longer bases take the general kernels): the columns
+    still equal their own single solves."""
+    say(f"[lockstep] restart={restart}")
+    s, _, g = solver("cfg2s", 3, 0)   # about 37 iterations at 1e-12: bases past 32 vectors
+    Q = rhs_set(s, 4, seed=restart)
+    P, info = g.solve(torch.from_numpy(Q), restart=restart, rtol=1e-12, max_iter=300)
+    P = P.cpu().numpy()
+    assert max(i["iterations"] for i in info) > 33
+    for r in range(4):
+        p1, i1 = g.solve(torch.from_numpy(Q[r]), restart=restart, rtol=1e-12, max_iter=300)
+        p1 = p1.cpu().numpy()
+        assert info[r]["status"] == 0 and i1[0]["status"] == 0
+        assert abs(info[r]["iterations"] - i1[0]["iterations"]) <= 1, (r, info[r], i1[0])
+        assert np.linalg.norm(P[r] - p1) <= 1e-9 * np.linalg.norm(p1), r
+    g.close()
