@@ -83,16 +83,31 @@ typedef enum { FAMS_RICHARDSON = 0, FAMS_GMRES = 1 } fams_outer_t;
 typedef enum { FAMS_RESTRICT_FE = 0, FAMS_RESTRICT_FV = 1, FAMS_RESTRICT_MIX = 2 } fams_restriction_t;
 
 /* Fine system A (Eq. A-dis-mf).  Rows/columns: matrix cells 0..n_matrix-1 in
- * natural grid order, then fracture cells.  CSR with columns sorted within
- * each row and the diagonal stored.  A must be symmetric positive definite
- * with non-positive off-diagonals (TPFA + EDFM connectivity). */
+ * natural grid order, then fracture cells, then (optionally) the last n_wells
+ * unknowns: one pressure per well (Sec. 3: each well is a single fine-scale
+ * unknown mapped to the coarse scale by the identity).  A well's row and
+ * column hold the Peaceman couplings of Sec. 2 (q^w = beta (p^w - p) in every
+ * perforated matrix or fracture cell).  CSR with columns sorted within each
+ * row and the diagonal stored.  A must be symmetric positive definite with
+ * non-positive off-diagonals (TPFA + EDFM connectivity + well indices). */
 typedef struct {
-  int64_t n;                  /* total fine cells (< 2^31) */
-  int64_t n_matrix;           /* matrix cells; rows >= n_matrix are fracture cells */
+  int64_t n;                  /* total fine unknowns (< 2^31) */
+  int64_t n_matrix;           /* matrix cells; rows >= n_matrix are fracture cells
+                                 (or wells) */
   int64_t nnz;                /* stored entries (< 2^31) */
   const int64_t* row_ptr;     /* device [n+1] */
   const int32_t* col_idx;     /* device [nnz] */
   const double* val;          /* device [nnz] */
+  int64_t n_wells;            /* wells: rows n - n_wells .. n - 1 (0 = none).  Each
+                                 is a coarse node of its own (class 3, in the
+                                 vertex list, a primal block of its own); its
+                                 basis function is computed like every other one,
+                                 with the well above every cell of both media in
+                                 the wirebasket order, so the perforated cells
+                                 take the well's value as Dirichlet data in all
+                                 four strategies (the beta term of the skeleton
+                                 equation, Sec. 3.1) and P^ww = I, P^wm = P^wf = 0
+                                 (Eq. prolongation_single) */
 } fams_csr_t;
 
 /* Coarse grids of both media (Sec. 3, Fig. 2).  wb_type is the wirebasket

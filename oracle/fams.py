@@ -24,7 +24,13 @@ formulas (Decoupled, Frac, Rock and Coupled-AMS) in one rule:
 * the local blocks are the connected components of the kept couplings (the
   dual edges, faces and interiors, merged across media in Coupled-AMS); they
   are solved from the highest rank down: P_K = A'_KK^{-1} B_K;
-* vertex rows are the Kronecker delta of Eq. (kronecker-basis).
+* vertex rows are the Kronecker delta of Eq. (kronecker-basis);
+* wells (the last n_wells unknowns, Sec. 3: one fine-scale unknown and one
+  coarse node per well, mapped by the identity) are vertices of a third
+  medium ranked above every cell (rho = 8): a perforated cell's coupling to
+  its well is never cut or lumped but taken as Dirichlet data, which is the
+  beta (Phi - Phi^w) term of the skeleton equation (Sec. 3.1) with
+  P^ww = I and P^wm = P^wf = 0 (Eq. prolongation_single).
 
 Readings where the paper is silent (listed in the design notes):
   * Coupled-AMS merging (Sec. 3.1: neighbouring dual blocks of one type join
@@ -68,15 +74,32 @@ OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
 RESTRICT_FE, RESTRICT_FV, RESTRICT_MIX = 0, 1, 2
 
 
-def ranks(wb_type, n_matrix, variant):
-    """rho(i) of every cell (see the module docstring)."""
+def media(n, n_matrix, n_wells=0):
+    """Medium of every unknown: 0 matrix, 1 fracture, 2 well (the last
+    n_wells unknowns are well pressures)."""
+    med = (np.arange(n) >= n_matrix).astype(np.int64)
+    if n_wells:
+        med[n - n_wells:] = 2
+    return med
+
+
+def ranks(wb_type, n_matrix, variant, n_wells=0):
+    """rho(i) of every cell (see the module docstring).  A well is a coarse
+    node of its own (Sec. 3: one coarse node per well, identity restriction)
+    above every cell of both media, so the cells it perforates take it as
+    Dirichlet data in every strategy (the well term of the skeleton equation
+    of Sec. 3.1)."""
     tau = np.asarray(wb_type, dtype=np.int64)
-    frac = np.arange(len(tau)) >= n_matrix
+    med = media(len(tau), n_matrix, n_wells)
+    frac = med == 1
     if variant == FRAC:
-        return tau + 4 * frac
-    if variant == ROCK:
-        return tau + 4 * (~frac)
-    return tau.copy()
+        rho = tau + 4 * frac
+    elif variant == ROCK:
+        rho = tau + 4 * (med == 0)
+    else:
+        rho = tau.copy()
+    rho[med == 2] = 8
+    return rho
 
 
 def _union_find_merge(rows, cols, base, sizes, cap):
@@ -102,20 +125,20 @@ def _union_find_merge(rows, cols, base, sizes, cap):
     return np.array([find(x) for x in range(len(sizes))])
 
 
-def classify(A: sp.csr_matrix, wb_type, n_matrix, variant, merge_cap=4096):
+def classify(A: sp.csr_matrix, wb_type, n_matrix, variant, merge_cap=4096, n_wells=0):
     """Class of every stored entry of A (0 for diagonals and vertex rows) and the
     local block (component) of every non-vertex cell (-1 for vertices)."""
     n = A.shape[0]
-    rho = ranks(wb_type, n_matrix, variant)
+    rho = ranks(wb_type, n_matrix, variant, n_wells)
     tau = np.asarray(wb_type, dtype=np.int64)
     is_v = tau == 3
-    med = (np.arange(n) >= n_matrix).astype(np.int64)
+    med = media(n, n_matrix, n_wells)
     r = np.repeat(np.arange(n), np.diff(A.indptr))
     c = A.indices.astype(np.int64)
     off = (r != c) & ~is_v[r]
     cut = np.zeros(len(c), dtype=bool)
-    if variant == DECOUPLED:
-        cut = med[r] != med[c]
+    if variant == DECOUPLED:   # matrix-fracture couplings only; wells are never cut
+        cut = (med[r] != med[c]) & (med[r] < 2) & (med[c] < 2)
     elif variant == COUPLED:
         # within-medium blocks first
         same = off & ~is_v[c] & (tau[r] == tau[c]) & (med[r] == med[c])
@@ -147,13 +170,15 @@ def _masked(A, mask):
 
 
 def prolongation(A, wb_type, vertex, n_matrix, variant, alpha=0.0, merge_cap=4096,
-                 return_blocks=False):
+                 return_blocks=False, n_wells=0):
     """The F-AMS prolongation P (N x n_c, CSR) for one coupling strategy."""
     A = sp.csr_matrix(A)
     A.sort_indices()
     n = A.shape[0]
     nc = len(vertex)
-    cls, comp, rho = classify(A, wb_type, n_matrix, variant, merge_cap)
+    if n_wells and np.any(np.asarray(wb_type)[n - n_wells:] != 3):
+        raise ValueError("every well is a coarse node (class 3)")
+    cls, comp, rho = classify(A, wb_type, n_matrix, variant, merge_cap, n_wells)
     is_v = np.asarray(wb_type) == 3
     coarse_of = np.full(n, -1, dtype=np.int64)
     coarse_of[np.asarray(vertex)] = np.arange(nc)
@@ -251,11 +276,13 @@ def restriction(P, primal, vertex, n_matrix, kind=RESTRICT_FE):
     return sp.csr_matrix(pick @ RFV + (sp.identity(nc) - pick) @ RT)
 
 
-def media_blocks(A, n_matrix):
+def media_blocks(A, n_matrix, n_wells=0):
     """diag(A^mm, A^ff) of Eq. (dis-mf): A without the couplings A^mf, A^fm
-    between matrix cells (rows [0, n_matrix)) and fracture cells."""
+    between matrix cells (rows [0, n_matrix)) and fracture cells (and, with
+    wells, without the couplings between wells and cells)."""
     A = sp.coo_matrix(A)
-    keep = (A.row < n_matrix) == (A.col < n_matrix)
+    med = media(A.shape[0], n_matrix, n_wells)
+    keep = med[A.row] == med[A.col]
     return sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
 
 
@@ -303,10 +330,11 @@ class FAMS:
 
     def __init__(self, A, wb_type, vertex, n_matrix, variant=DECOUPLED, alpha=0.0,
                  merge_cap=4096, smoothing=True, primal=None, restriction_kind=RESTRICT_FE,
-                 media_smoothing=False):
+                 media_smoothing=False, n_wells=0):
         self.A = sp.csr_matrix(A)
         self.A.sort_indices()
         self.n_matrix = n_matrix
+        self.n_wells = n_wells
         self.variant = variant
         if restriction_kind != RESTRICT_FE and primal is None:
             raise ValueError("the MSFV and MSMIX restrictions need the primal blocks")
@@ -320,7 +348,7 @@ class FAMS:
         wb_type, vertex, primal = self._grid
         alpha, merge_cap, kind = self._opts[:3]
         self.P = prolongation(self.A, wb_type, vertex, self.n_matrix, self.variant, alpha,
-                              merge_cap)
+                              merge_cap, n_wells=self.n_wells)
         self.R = restriction(self.P, primal, vertex, self.n_matrix, kind)
         self.A_basis = self.A.copy()
 
@@ -331,7 +359,7 @@ class FAMS:
         self.lu = sla.lu_factor(self.Ac)
         self.ilu = ILU0(self.A) if smoothing else None
         # the extra smoothing stage on the per-medium systems (Sec. 3.2)
-        self.ilu_media = (ILU0(media_blocks(self.A, self.n_matrix))
+        self.ilu_media = (ILU0(media_blocks(self.A, self.n_matrix, self.n_wells))
                           if smoothing and media_smoothing else None)
 
     def update_values(self, A_new, threshold=0.0):

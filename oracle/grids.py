@@ -27,7 +27,8 @@ Readings where the paper is silent (they are listed in the design notes):
     lower coarse index (for a 1D network this is Table 2's own primal
     assignment up to tie-breaking);
   * coarse ids: matrix blocks first (x fastest), then fracture V cells in
-    ascending fine index.
+    ascending fine index, then one per well (class V, a primal block of its
+    own) in well order.
 """
 from __future__ import annotations
 
@@ -183,7 +184,7 @@ def fracture_grid(n_matrix, row_ptr, col, cell_col, cell_z, col_plate, col_ptr, 
     for c in range(nf):
         i = n_matrix + c
         row = col[row_ptr[i]:row_ptr[i + 1]]
-        nbrs = [int(j) - n_matrix for j in row if j >= n_matrix and j != i]
+        nbrs = [int(j) - n_matrix for j in row if n_matrix <= j < n_matrix + nf and j != i]
         fadj.extend(nbrs)
         fptr[c + 1] = len(fadj)
     fadj = np.asarray(fadj, dtype=np.int64)
@@ -230,11 +231,18 @@ def fracture_grid(n_matrix, row_ptr, col, cell_col, cell_z, col_plate, col_ptr, 
 
 
 def full_grid(sysm, coarse, d_min, r_z):
-    """Matrix + fracture grid for a workloads.FracturedSystem."""
+    """Matrix + fracture (+ well) grid for a workloads.FracturedSystem: each
+    well is a coarse node of its own (class V, its own primal block; Sec. 3,
+    one coarse node per well with the identity restriction)."""
     cx, cy, cz = coarse
+    nw = getattr(sysm, "n_wells", 0)
     wbm, pm, vm = structured_grid(sysm.nx, sysm.ny, sysm.nz, cx, cy, cz)
     wbf, pf, vf = fracture_grid(sysm.n_matrix, sysm.row_ptr, sysm.col, sysm.cell_col,
                                 sysm.cell_z, sysm.col_plate, sysm.col_ptr, sysm.col_adj,
                                 sysm.plate_zlo, sysm.plate_zhi, d_min, r_z, len(vm))
-    return (np.concatenate([wbm, wbf]), np.concatenate([pm, pf]),
-            np.concatenate([vm, vf]), len(vm))
+    nc0 = len(vm) + len(vf)
+    wbw = np.full(nw, WB_V, dtype=np.int8)
+    pw = np.arange(nc0, nc0 + nw, dtype=np.int32)
+    vw = np.arange(sysm.n - nw, sysm.n, dtype=np.int64)
+    return (np.concatenate([wbm, wbf, wbw]), np.concatenate([pm, pf, pw]),
+            np.concatenate([vm, vf, vw]), len(vm))

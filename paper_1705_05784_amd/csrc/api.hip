@@ -465,7 +465,8 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
       !G->primal || !G->vertex)
     return FAMS_ERR_INVALID_ARG;
   if (A->n <= 0 || A->n >= (int64_t(1) << 31) || A->nnz < A->n || A->nnz >= (int64_t(1) << 31) ||
-      A->n_matrix < 0 || A->n_matrix > A->n || G->n_coarse <= 0 || G->n_coarse > A->n ||
+      A->n_matrix < 0 || A->n_matrix > A->n || A->n_wells < 0 ||
+      A->n_wells > A->n - A->n_matrix || G->n_coarse <= 0 || G->n_coarse > A->n ||
       G->n_coarse > 65536)
     return FAMS_ERR_INVALID_ARG;
   if (o->variant < 0 || o->variant > 3 || o->precision < 0 || o->precision > 1 ||
@@ -493,6 +494,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->prof.on = o->profile != 0;
     h->n = static_cast<int>(A->n);
     h->nm = static_cast<int>(A->n_matrix);
+    h->nw = static_cast<int>(A->n_wells);
     h->nnz = A->nnz;
     h->nc = static_cast<int>(G->n_coarse);
     fams::setup_impl(h.get(), A, G);

@@ -995,27 +995,27 @@ void build_ilu(Handle* h) {
 
 namespace {
 
-// the couplings of the per-medium systems A^mm and A^ff: both ends in the
-// matrix, or both in the fractures (rows [0, nm) are matrix cells)
-__global__ void k_media_count(int n, int nm, const int* rp, const int* ci, int* cnt) {
+// the couplings of the per-medium systems A^mm and A^ff (and, with wells,
+// the wells' own diagonal): both ends in one medium (medium_of)
+__global__ void k_media_count(int n, int nm, int nwb, const int* rp, const int* ci, int* cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
   int c = 0;
   if (i < n) {
-    const bool mi = i < nm;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) c += (ci[p] < nm) == mi;
+    const int mi = medium_of(i, nm, nwb);
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += medium_of(ci[p], nm, nwb) == mi;
   }
   cnt[i] = c;
 }
 
-__global__ void k_media_fill(int n, int nm, const int* rp, const int* ci, const double* val,
-                             const int* nrp, int* nci, double* nval) {
+__global__ void k_media_fill(int n, int nm, int nwb, const int* rp, const int* ci,
+                             const double* val, const int* nrp, int* nci, double* nval) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const bool mi = i < nm;
+  const int mi = medium_of(i, nm, nwb);
   int o = nrp[i];
   for (int p = rp[i]; p < rp[i + 1]; ++p)
-    if ((ci[p] < nm) == mi) {
+    if (medium_of(ci[p], nm, nwb) == mi) {
       nci[o] = ci[p];
       nval[o] = val[p];
       ++o;
@@ -1041,10 +1041,12 @@ void build_block_smoother(Handle* h) {
   b->smoother = 1;
   b->n = n;
   b->nm = h->nm;
+  b->nw = h->nw;
+  const int nwb = n - h->nw;
   {
     DBuf<int> cnt(&b->alloc, n + 1);
-    LAUNCH(h, "media_split", k_media_count, blocks_for(n + 1, kT), kT, 0, n, h->nm, h->rp.get(),
-           h->ci.get(), cnt.get());
+    LAUNCH(h, "media_split", k_media_count, blocks_for(n + 1, kT), kT, 0, n, h->nm, nwb,
+           h->rp.get(), h->ci.get(), cnt.get());
     b->rp.reset(&b->alloc, n + 1);
     exclusive_scan_i32(h, cnt, b->rp, n + 1);
     int nnz = 0;
@@ -1053,8 +1055,8 @@ void build_block_smoother(Handle* h) {
     b->nnz = nnz;
     b->ci.reset(&b->alloc, nnz);
     b->val.reset(&b->alloc, nnz);
-    LAUNCH(h, "media_split", k_media_fill, blocks_for(n, kT), kT, 0, n, h->nm, h->rp.get(),
-           h->ci.get(), h->val.get(), b->rp.get(), b->ci.get(), b->val.get());
+    LAUNCH(h, "media_split", k_media_fill, blocks_for(n, kT), kT, 0, n, h->nm, nwb,
+           h->rp.get(), h->ci.get(), h->val.get(), b->rp.get(), b->ci.get(), b->val.get());
   }
   build_ilu(b.get());
   if (h->precision == FAMS_PREC_MIXED) h->blk_x32.reset(&h->alloc, n);

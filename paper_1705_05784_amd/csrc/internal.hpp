@@ -131,6 +131,12 @@ struct AuxStreams {
   ~AuxStreams();
 };
 
+// Medium of unknown i: 0 matrix (i < nm), 1 fracture, 2 well (i >= nwb, the
+// first well row n - nw)
+__host__ __device__ __forceinline__ int medium_of(int i, int nm, int nwb) {
+  return i < nm ? 0 : (i < nwb ? 1 : 2);
+}
+
 inline unsigned blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -193,6 +199,7 @@ struct Handle {
 
   // sizes
   int n = 0, nm = 0, nc = 0;
+  int nw = 0;  // wells: the last nw unknowns (a third medium, always coarse nodes)
   int64_t nnz = 0;
 
   // fine system (int32 indices)

@@ -42,17 +42,23 @@ constexpr int kMaxCols = 2048;      // coarse columns per block (RHS count)
 enum ErrBits : int {
   E_VERTEX_RANGE = 1, E_VERTEX_CLASS = 2, E_VERTEX_DUP = 4, E_V_NOT_LISTED = 8,
   E_CLASS_RANGE = 16, E_FRAC_INTERIOR = 32, E_PRIMAL_RANGE = 64,
-  E_NO_HIGHER = 128, E_PIVOT = 256, E_SOURCES = 512, E_COLS = 2048,
+  E_NO_HIGHER = 128, E_PIVOT = 256, E_SOURCES = 512, E_COLS = 2048, E_WELL_CLASS = 4096,
 };
 
-__device__ __forceinline__ int rank_of(int wb, int i, int nm, int variant) {
-  bool frac = i >= nm;
-  if (variant == FAMS_FRAC) return wb + (frac ? 4 : 0);
-  if (variant == FAMS_ROCK) return wb + (frac ? 0 : 4);
+// rho(i): the wirebasket class lifted by 4 in the medium solved first (Frac-
+// AMS: fractures, App. A.2; Rock-AMS: the matrix, App. A.3); a well ranks
+// above every cell of both media, so its perforated cells take it as
+// Dirichlet data in all four strategies (the beta term of the skeleton
+// equation, Sec. 3.1)
+__device__ __forceinline__ int rank_of(int wb, int i, int nm, int nwb, int variant) {
+  const int med = medium_of(i, nm, nwb);
+  if (med == 2) return 8;
+  if (variant == FAMS_FRAC) return wb + (med == 1 ? 4 : 0);
+  if (variant == FAMS_ROCK) return wb + (med == 1 ? 0 : 4);
   return wb;
 }
 
-__global__ void k_validate(int n, int nm, int nc, const int8_t* wb, const int* primal,
+__global__ void k_validate(int n, int nm, int nwb, int nc, const int8_t* wb, const int* primal,
                            const int64_t* vertex, int* coarse_of, int8_t* rho, int variant,
                            int* err) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -69,8 +75,9 @@ __global__ void k_validate(int n, int nm, int nc, const int8_t* wb, const int* p
     int w = wb[i];
     if (w < 0 || w > 3) atomicOr(err, E_CLASS_RANGE);
     if (i >= nm && w == 0) atomicOr(err, E_FRAC_INTERIOR);
+    if (i >= nwb && w != 3) atomicOr(err, E_WELL_CLASS);
     if (primal[i] < 0 || primal[i] >= nc) atomicOr(err, E_PRIMAL_RANGE);
-    rho[i] = static_cast<int8_t>(rank_of(w, i, nm, variant));
+    rho[i] = static_cast<int8_t>(rank_of(w, i, nm, nwb, variant));
   }
 }
 
@@ -81,18 +88,20 @@ __global__ void k_check_vertices(int n, const int8_t* wb, const int* coarse_of, 
 
 // Class of every stored entry.  `mode` = the variant whose rule is applied;
 // `group` (Coupled only) = merged block label of each cell.
-__global__ void k_classify(int n, int nm, const int* rp, const int* ci, const int8_t* wb,
+// Couplings with a well are never cut (wells are neither medium).
+__global__ void k_classify(int n, int nm, int nwb, const int* rp, const int* ci, const int8_t* wb,
                            const int8_t* rho, int mode, const int* group, int8_t* ecls) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   bool vi = wb[i] == 3;
-  bool fi = i >= nm;
+  const int mi = medium_of(i, nm, nwb);
   int ri = rho[i];
   for (int p = rp[i]; p < rp[i + 1]; ++p) {
     int j = ci[p];
     int8_t c = C_NONE;
     if (!vi && j != i) {
-      bool cross = fi != (j >= nm);
+      const int mj = medium_of(j, nm, nwb);
+      bool cross = mi != mj && mi < 2 && mj < 2;
       bool cut = false;
       if (mode == FAMS_DECOUPLED) cut = cross;
       else if (mode == FAMS_COUPLED) cut = cross && wb[i] == wb[j] && group[i] != group[j];
@@ -637,6 +646,7 @@ std::string grid_error_text(int e) {
   if (e & E_V_NOT_LISTED) s += " a class-V cell missing from the vertex list;";
   if (e & E_CLASS_RANGE) s += " wirebasket class outside 0..3;";
   if (e & E_FRAC_INTERIOR) s += " fracture cell of class I;";
+  if (e & E_WELL_CLASS) s += " a well is not of class V (every well is a coarse node);";
   if (e & E_PRIMAL_RANGE) s += " primal id out of range;";
   return s;
 }
@@ -994,7 +1004,7 @@ void build_restriction(Handle* h) {
 }
 
 void build_prolongation(Handle* h, const int8_t* wb) {
-  const int n = h->n, nm = h->nm, nc = h->nc;
+  const int n = h->n, nm = h->nm, nc = h->nc, nwb = h->n - h->nw;
   unsigned g = blocks_for(n, kThreads);
   Allocator* A = &h->alloc;
   PhaseTimer pt(h->stream);
@@ -1016,8 +1026,9 @@ void build_prolongation(Handle* h, const int8_t* wb) {
     HIPX(hipMemcpyAsync(vtx64, hv64.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice,
                         h->stream));
   }
-  LAUNCH(h, "validate", k_validate, blocks_for(std::max(n, nc), kThreads), kThreads, 0, n, nm, nc,
-         wb, h->primal.get(), vtx64.get(), coarse_of.get(), rho.get(), h->variant, err.get());
+  LAUNCH(h, "validate", k_validate, blocks_for(std::max(n, nc), kThreads), kThreads, 0, n, nm,
+         nwb, nc, wb, h->primal.get(), vtx64.get(), coarse_of.get(), rho.get(), h->variant,
+         err.get());
   LAUNCH(h, "check_vertices", k_check_vertices, g, kThreads, 0, n, wb, coarse_of.get(), err.get());
   int e = static_cast<int>(read1(h, err.get()));
   FAMS_REQUIRE(e == 0, FAMS_ERR_BAD_GRID, grid_error_text(e));
@@ -1025,17 +1036,17 @@ void build_prolongation(Handle* h, const int8_t* wb) {
   // entry classes and local blocks
   DBuf<int> label(A, n);
   if (h->variant == FAMS_COUPLED) {
-    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, nwb, h->rp.get(), h->ci.get(), wb,
            rho.get(), static_cast<int>(FAMS_DECOUPLED), static_cast<const int*>(nullptr),
            ecls.get());
     DBuf<int> base(A, n);
     components(h, wb, ecls, base);
     coupled_groups(h, wb, base, label);
-    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, nwb, h->rp.get(), h->ci.get(), wb,
            rho.get(), static_cast<int>(FAMS_COUPLED), static_cast<const int*>(label.get()),
            ecls.get());
   } else {
-    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, h->rp.get(), h->ci.get(), wb,
+    LAUNCH(h, "classify", k_classify, g, kThreads, 0, n, nm, nwb, h->rp.get(), h->ci.get(), wb,
            rho.get(), h->variant, static_cast<const int*>(nullptr), ecls.get());
     components(h, wb, ecls, label);
   }

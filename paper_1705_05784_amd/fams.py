@@ -34,7 +34,8 @@ class FamsError(RuntimeError):
 
 class CSR(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_matrix", C.c_int64), ("nnz", C.c_int64),
-                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("n_wells", C.c_int64)]
 
 
 class Grid(C.Structure):
@@ -166,12 +167,14 @@ class Solver:
     its name); precision: FP64 or MIXED; alpha: truncation threshold of P;
     smoother: 0 none, 1 (or True) ILU(0), 2 ILU(0) plus the per-medium stage;
     restriction: RESTRICT_FE (P^T), RESTRICT_FV or RESTRICT_MIX (or "fe",
-    "fv", "mix").  Arrays may be numpy or torch; the handle copies them.
+    "fv", "mix"); n_wells: the last n_wells unknowns are well pressures (each
+    a coarse node of its own).  Arrays may be numpy or torch; the handle
+    copies them.
     """
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
                  precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False,
-                 restriction=0):
+                 restriction=0, n_wells=0):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -185,7 +188,8 @@ class Solver:
         self.nnz = int(ci.numel())
         self.n_matrix = int(n_matrix)
         self.n_coarse = int(vx.numel())
-        csr = CSR(self.n, self.n_matrix, self.nnz, _ptr(rp), _ptr(ci), _ptr(va))
+        self.n_wells = int(n_wells)
+        csr = CSR(self.n, self.n_matrix, self.nnz, _ptr(rp), _ptr(ci), _ptr(va), self.n_wells)
         grid = Grid(self.n_coarse, _ptr(wb), _ptr(pr), _ptr(vx))
         if isinstance(variant, str):
             variant = VARIANTS[variant]
@@ -359,7 +363,8 @@ def full_grid(sysm, coarse, d_min, r_z):
 
 def setup(sysm, coarse, d_min, r_z, **kw) -> Solver:
     wb, pr, vx, _ = full_grid(sysm, coarse, d_min, r_z)
-    return Solver(sysm.row_ptr, sysm.col, sysm.val, sysm.n_matrix, wb, pr, vx, **kw)
+    return Solver(sysm.row_ptr, sysm.col, sysm.val, sysm.n_matrix, wb, pr, vx,
+                  n_wells=getattr(sysm, "n_wells", 0), **kw)
 
 
 def dense_op(op: int, a):

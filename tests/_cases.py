@@ -1,7 +1,7 @@
 """Small seeded cases shared by the tests (inputs only)."""
 import numpy as np
 
-from workloads import Plate, build_system, make_small
+from workloads import Plate, Well, add_wells, build_system, make_small
 
 
 def homogeneous(nx, ny, nz, neumann=True, plates=()):
@@ -46,3 +46,23 @@ def small_case(name, seed=0, neumann=False, **kw):
         return s, spec
     s = make_small(spec["kind"], seed=seed, neumann=neumann, **kw)
     return s, spec
+
+
+def wells_case(name="3d", neumann=False, **kw):
+    """A small case with two wells: one through the matrix column of the first
+    fracture cell's host, perforating matrix cells only (so its cells are
+    connected to that fracture), and one through another fracture's host
+    column perforating the fracture cells there too."""
+    s, spec = small_case(name, neumann=neumann, **kw)
+    nx, ny, nz = s.nx, s.ny, s.nz
+
+    def col_of(m):
+        return m % nx, (m // nx) % ny, m // (nx * ny)
+
+    ix, iy, iz = col_of(int(s.host[0]))
+    w1 = Well(ix, iy, max(0, iz - 1), min(nz, iz + 2), rate=1.0, fractures=False)
+    far = [c for c in range(len(s.host)) if col_of(int(s.host[c]))[:2] != (ix, iy)
+           and abs(col_of(int(s.host[c]))[0] - ix) + abs(col_of(int(s.host[c]))[1] - iy) > 3]
+    jx, jy, _ = col_of(int(s.host[far[len(far) // 2]]))
+    w2 = Well(jx, jy, 0, nz, rate=-1.0, fractures=True)
+    return add_wells(s, [w1, w2]), spec

@@ -4,5 +4,5 @@ Only problem data lives here (permeability fields, the EDFM fine-scale system,
 fracture geometry, right-hand sides).  Nothing in this package implements any
 step of the multiscale solver.
 """
-from .edfm import FracturedSystem, Plate, build_system, lnk_field  # noqa: F401
+from .edfm import FracturedSystem, Plate, Well, add_wells, build_system, lnk_field  # noqa: F401
 from .configs import make_config, make_small, CONFIGS  # noqa: F401

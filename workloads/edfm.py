@@ -71,10 +71,11 @@ class FracturedSystem:
     host: np.ndarray             # int64 [n_f]: host matrix cell of each fracture cell
     t_ratio: float               # mean fracture T / mean matrix T (paper Eq. tratio)
     meta: dict
+    n_wells: int = 0             # the last n_wells unknowns are well pressures
 
     @property
     def n_frac(self) -> int:
-        return self.n - self.n_matrix
+        return self.n - self.n_matrix - self.n_wells
 
     @property
     def nnz(self) -> int:
@@ -412,3 +413,62 @@ def random_plates_3d(rng, n_frac, nx, ny, nz, len_cells, h_cells):
             continue
         plates.append(Plate(c[0], c[1], c[2], c[3], z0, z0 + H))
     return plates
+
+
+@dataclasses.dataclass
+class Well:
+    """A rate-controlled vertical well through matrix column (ix, iy), layers
+    [zlo, zhi); with ``fractures`` it also perforates the fracture cells
+    hosted in those matrix cells."""
+    ix: int
+    iy: int
+    zlo: int
+    zhi: int
+    rate: float
+    fractures: bool = False
+
+
+def add_wells(sysm: FracturedSystem, wells, kf=None, r_w=0.05) -> FracturedSystem:
+    """The system with rate-controlled wells as extra unknowns (the last rows).
+
+    Each perforated cell i couples to its well w through Peaceman's well
+    index WI_i = 2 pi k_i h_z / ln(r_e / r_w) with r_e = 0.2 h (square cells,
+    isotropic k), r_w in units of h and h_z = h in 3D (per unit thickness in
+    2D): the cell's row gains WI_i on the diagonal and -WI_i towards the well,
+    and the well's row reads sum_i WI_i (p_w - p_i) = rate (the well's total
+    rate).  Fracture perforations take k = kf (default: the contrast in the
+    system's meta times the geometric mean of the matrix k, else 1e3 times).
+    Row sums of the cell rows are unchanged, so a Neumann system stays one.
+    """
+    n0, nw = sysm.n, len(wells)
+    h = sysm.h
+    hz = h if sysm.nz > 1 else 1.0
+    k = np.exp(sysm.lnk)
+    if kf is None:
+        kf = float(sysm.meta.get("contrast", 1e3)) * float(np.exp(sysm.lnk.mean()))
+    geo = 2.0 * np.pi * hz / np.log(0.2 / r_w)
+    rows, cols, wi = [], [], []
+    for w, wl in enumerate(wells):
+        for z in range(wl.zlo, wl.zhi):
+            m = wl.ix + sysm.nx * (wl.iy + sysm.ny * z)
+            rows.append(m)
+            cols.append(w)
+            wi.append(geo * k[z, wl.iy, wl.ix])
+            if wl.fractures:
+                for c in np.nonzero(sysm.host == m)[0]:
+                    rows.append(sysm.n_matrix + int(c))
+                    cols.append(w)
+                    wi.append(geo * kf)
+    rows, cols, wi = np.asarray(rows), np.asarray(cols), np.asarray(wi)
+    A = sysm.csr()
+    B = sp.csr_matrix((-wi, (rows, cols)), shape=(n0, nw))
+    Ad = A + sp.diags(np.bincount(rows, weights=wi, minlength=n0))
+    D = sp.diags(np.bincount(cols, weights=wi, minlength=nw))
+    Aw = sp.bmat([[Ad, B], [B.T, D]], format="csr")
+    Aw.sort_indices()
+    Aw.sum_duplicates()
+    q = np.concatenate([sysm.q, [float(wl.rate) for wl in wells]])
+    return dataclasses.replace(
+        sysm, n=n0 + nw, row_ptr=Aw.indptr.astype(np.int64), col=Aw.indices.astype(np.int32),
+        val=Aw.data.astype(np.float64), q=q, n_wells=sysm.n_wells + nw,
+        meta=dict(sysm.meta, wells=[dataclasses.asdict(wl) for wl in wells]))
