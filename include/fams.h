@@ -144,6 +144,14 @@ typedef struct {
   int32_t restriction;        /* fams_restriction_t; MSFV and MSMIX make the coarse
                                  operator non-symmetric: its inverse then comes from LU
                                  with partial pivoting.  Other values: FAMS_ERR_INVALID_ARG */
+  int32_t nonsymmetric;       /* 0: A is symmetric (banded LDL^T local solves, SPD
+                                 coarse inverse).  1: A may be non-symmetric (a
+                                 linearised compressible system inside a Newton loop,
+                                 Eq. dis-mf and Table 1 steps 1-2): banded LU local
+                                 solves without pivoting, the coarse inverse from LU
+                                 with partial pivoting; the conservative flux
+                                 reconstruction (defined for the incompressible
+                                 system) is refused with FAMS_ERR_INVALID_ARG */
 } fams_setup_opts_t;
 
 typedef struct {

@@ -279,10 +279,10 @@ void coarse_setup(Handle* h) {
   build_coarse_operator(h, h->r_rp, h->r_ci, h->r_val, nc, h->Ac);
   {
     // A_c = P^T A P is SPD for SPD A: Gauss-Jordan without pivoting; if a
-    // pivot is not positive, or the restriction is not P^T, LU with partial
-    // pivoting
+    // pivot is not positive, the restriction is not P^T or A is not
+    // symmetric, LU with partial pivoting
     h->Ainv.reset(al, static_cast<size_t>(nc) * nc);
-    if (h->restriction != FAMS_RESTRICT_FE || !spd_inverse(h, h->Ac, h->Ainv, nc)) {
+    if (h->restriction != FAMS_RESTRICT_FE || h->nonsym || !spd_inverse(h, h->Ac, h->Ainv, nc)) {
       DBuf<double> lu(al, static_cast<size_t>(nc) * nc);
       HIPX(hipMemcpyAsync(lu, h->Ac.get(), sizeof(double) * nc * nc, hipMemcpyDeviceToDevice,
                           h->stream));
@@ -472,7 +472,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
   if (o->variant < 0 || o->variant > 3 || o->precision < 0 || o->precision > 1 ||
       !(o->trunc_alpha >= 0.0 && o->trunc_alpha < 1.0) || o->merge_cap < 1 ||
       o->restriction < FAMS_RESTRICT_FE || o->restriction > FAMS_RESTRICT_MIX ||
-      o->smoother < 0 || o->smoother > 2)
+      o->smoother < 0 || o->smoother > 2 || o->nonsymmetric < 0 || o->nonsymmetric > 1)
     return FAMS_ERR_INVALID_ARG;
   if (!fams::all_addressable({A->row_ptr, A->col_idx, A->val, G->wb_type, G->primal, G->vertex}))
     return FAMS_ERR_INVALID_ARG;
@@ -491,6 +491,7 @@ fams_status_t fams_setup(const fams_csr_t* A, const fams_grid_t* G, const fams_s
     h->merge_cap = o->merge_cap;
     h->smoother = o->smoother;
     h->restriction = o->restriction;
+    h->nonsym = o->nonsymmetric != 0;
     h->prof.on = o->profile != 0;
     h->n = static_cast<int>(A->n);
     h->nm = static_cast<int>(A->n_matrix);
@@ -566,6 +567,11 @@ fams_status_t fams_reconstruct_flux(fams_handle_t h, const double* q, const doub
   if (!h || !q || !p || !flux || !fams::all_addressable({q, p, flux}) ||
       (p_fv && !fams::device_addressable(p_fv)))
     return FAMS_ERR_INVALID_ARG;
+  if (h->nonsym) {
+    fams::g_last_error = "the conservative flux reconstruction needs a symmetric system "
+                         "(incompressible TPFA); this handle was set up as non-symmetric";
+    return FAMS_ERR_INVALID_ARG;
+  }
   return fams::guard([&]() -> fams_status_t {
     double imb = fams::reconstruct_flux(h, q, p, flux, p_fv);
     if (imbalance) *imbalance = imb;

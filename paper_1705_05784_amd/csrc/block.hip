@@ -46,21 +46,10 @@ __global__ void k_unpack(int n, int nr, const double* Q, double* q) {
 }
 
 // ---- operators on block vectors ------------------------------------------------
-// Workgroups are dealt to the eight XCDs in turn; for the row-wise kernels
-// the grid is padded to a multiple of eight and workgroup b takes the b/8-th
-// part of XCD (b % 8)'s contiguous eighth of the rows, so the neighbours a
-// row gathers (the previous and next rows, lines and planes) were mostly
-// brought into the same XCD's L2 by its own earlier workgroups.
-constexpr int kXcd = 8;
-
-__device__ __forceinline__ int64_t xcd_block() {
-  const int64_t per = gridDim.x / kXcd;
-  return static_cast<int64_t>(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
-}
-
-inline unsigned xcd_grid(int64_t blocks) {
-  return static_cast<unsigned>((blocks + kXcd - 1) / kXcd * kXcd);
-}
+// Row-wise kernels take their rows in XCD-contiguous ranges (xcd_block,
+// xcd_grid), so the neighbours a row gathers (the previous and next rows,
+// lines and planes) were mostly brought into the same XCD's L2 by its own
+// earlier workgroups.
 
 // Y = M X (kResid: Y = B - M X, B may be null or alias Y): one thread per
 // (row, right-hand side); the K threads of a row read its entries once
@@ -115,11 +104,15 @@ __device__ double group_sum(double v) {
 
 // Y[row * K + r] = sum_p M[row, p] X[col_p * K + r] for the fat rows of R =
 // P^T: one workgroup per row, 256 / K groups of K lanes stride over the
-// row's entries, then a fixed-order sum across the groups
+// row's entries, then a fixed-order sum across the groups.  Every fine cell
+// lies in the supports of several neighbouring coarse nodes, so rows are
+// dealt to the XCDs in contiguous ranges (xcd_block): neighbouring rows run
+// on one XCD at about the same time and gather the shared cells from its L2.
 template <class TV, class TX, int K>
 __global__ void __launch_bounds__(256)
 k_brestrict(int nrows, const int* rp, const int* ci, const TV* val, const TX* X, double* Y) {
-  const int row = blockIdx.x;
+  const int row = static_cast<int>(xcd_block());
+  if (row >= nrows) return;
   const int r = threadIdx.x % K, g = threadIdx.x / K;
   constexpr int G = 256 / K;
   double s = 0.0;
@@ -420,6 +413,10 @@ void launch_bmdot(Handle* h, const char* name, unsigned nb, int64_t nk, int nv, 
                   int64_t ldv, const double* w, double* part, int pstride) {
   if (nv > kFuseMax || !offset_addressable(nk, nb)) {
     LAUNCH(h, name, k_bmdot_part<K>, nb, kT, 0, nk, nv, V, ldv, w, part, pstride);
+    return;
+  }
+  if (nv == 1) {  // the norms of the outer iteration
+    LAUNCH(h, name, (k_bmdot<K, 1>), nb, kT, 0, nk, nv, V, ldv, w, part, pstride);
     return;
   }
 #define FAMS_DOT(NV) \
@@ -797,8 +794,8 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
     ysc = k.y32;
     xb = k.xb32;
   }
-  LAUNCH(h, "brestrict", (k_brestrict<T, T, K>), nc, 256, 0, nc, h->r_rp.get(), h->r_ci.get(),
-         rv, rT, k.rc);
+  LAUNCH(h, "brestrict", (k_brestrict<T, T, K>), xcd_grid(nc), 256, 0, nc, h->r_rp.get(),
+         h->r_ci.get(), rv, rT, k.rc);
   {
     dim3 grid(blocks_for(nc, 256), k.nch);
     LAUNCH(h, "bcoarse", k_bcoarse_part<K>, grid, 256, 0, nc, k.cw, h->Ainv.get(), k.rc, k.cpart);

@@ -137,6 +137,21 @@ __host__ __device__ __forceinline__ int medium_of(int i, int nm, int nwb) {
   return i < nm ? 0 : (i < nwb ? 1 : 2);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (each with its own L2).  A
+// grid padded to a multiple of eight (xcd_grid) and indexed by xcd_block
+// gives XCD x the contiguous x-th eighth of the work, taken in order: for
+// row-wise kernels whose rows share gathered data with nearby rows.
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t per = gridDim.x / kXcd;
+  return static_cast<int64_t>(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+}
+
+inline unsigned xcd_grid(int64_t blocks) {
+  return static_cast<unsigned>((blocks + kXcd - 1) / kXcd * kXcd);
+}
+
 inline unsigned blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -196,6 +211,7 @@ struct Handle {
   int64_t merge_cap = 4096;
   int smoother = 1;
   int restriction = 0;  // fams_restriction_t
+  bool nonsym = false;  // A may be non-symmetric: LU local solves, pivoted coarse inverse
 
   // sizes
   int n = 0, nm = 0, nc = 0;

@@ -511,6 +511,119 @@ k_local_subst(const int* groups, const int* list, int c0, const int* comp_ptr, c
   }
 }
 
+// ---- local solves of a non-symmetric A (LU without pivoting) ---------------
+// The same local problems as k_local_solve (A'_KK P_K = B_K) when A is not
+// symmetric (a linearised compressible system): the full band of A'_KK
+// (row l, columns l-b..l+b at B[l (2b+1) + b + (j - l)]) in global memory,
+// factored in place into unit-lower L and upper U by right-looking
+// elimination without pivoting (the local matrices are M-matrices), one
+// elimination step per pair of barriers; then every thread substitutes whole
+// columns of X (forward with L, backward with U), rows in order.  Plain, not
+// blocked: the general-matrix path, not the symmetric one the benchmarks use.
+template <class TS, class TC>
+__global__ void __launch_bounds__(kThreads)
+k_local_solve_lu(const int* list, const int* comp_ptr, const int* cells, const int* rp,
+                 const int* ci, const double* av, const int8_t* ecls, const int8_t* wb,
+                 const int* coarse_of, const int* comp_of, const int* local_idx,
+                 const int64_t* col_ptr, const int* cols, const int* ncols, const int* band,
+                 const int64_t* pval_off, TS* pvals, const int64_t* work_off, TC* band_glob,
+                 TC* xwork, int* err, int* bad_block) {
+  const int slot = blockIdx.x;
+  const int K = list[slot];
+  const int beg = comp_ptr[K], n = comp_ptr[K + 1] - beg;
+  const int b = band[K], w = 2 * b + 1;
+  const int nck = ncols[K];
+  const int* kcols = cols + col_ptr[K];
+  TC* X;
+  if constexpr (std::is_same<TS, TC>::value) X = xwork ? xwork + work_off[2 * slot + 1] : pvals + pval_off[K];
+  else X = xwork + work_off[2 * slot + 1];
+  TC* B = band_glob + work_off[2 * slot];
+  const int64_t bsz = static_cast<int64_t>(n) * w;
+  for (int64_t t = threadIdx.x; t < bsz; t += blockDim.x) B[t] = TC(0);
+  for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x) X[t] = TC(0);
+  __syncthreads();
+  // the band, both triangles: one thread per block row
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const int i = cells[beg + l];
+    double dg = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      const int j = ci[p];
+      const int8_t c = ecls[p];
+      if (j == i || c == C_LUMPED) dg += av[p];
+      else if (c == C_KEPT) B[static_cast<int64_t>(l) * w + b + (local_idx[j] - l)] = static_cast<TC>(av[p]);
+    }
+    B[static_cast<int64_t>(l) * w + b] = static_cast<TC>(dg);
+  }
+  // right-hand sides -A_ij P_j of the higher-rank neighbours (as k_local_solve)
+  {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+    for (int l = wave; l < n; l += nwaves) {
+      const int i = cells[beg + l];
+      TC* xl = X + static_cast<int64_t>(l) * nck;
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (ecls[p] != C_RHS) continue;
+        const int j = ci[p];
+        const TC a = static_cast<TC>(av[p]);
+        if (wb[j] == 3) {
+          if (lane == 0) xl[bsearch_i32(kcols, nck, coarse_of[j])] -= a;
+        } else {
+          const int cj = comp_of[j];
+          const int ncj = ncols[cj];
+          const TS* src = pvals + pval_off[cj] + static_cast<int64_t>(local_idx[j]) * ncj;
+          const int* cc = cols + col_ptr[cj];
+          for (int t = lane; t < ncj; t += 64)
+            xl[bsearch_i32(kcols, nck, cc[t])] -= a * static_cast<TC>(src[t]);
+        }
+        __threadfence_block();
+      }
+    }
+  }
+  __syncthreads();
+  // LU: step k scales column k below the pivot, then updates the trailing
+  // window of rows and columns k+1..k+b
+  bool bad = false;
+  for (int k = 0; k < n; ++k) {
+    const int e = min(n - 1, k + b);
+    const TC piv = B[static_cast<int64_t>(k) * w + b];
+    if (!(piv > TC(0))) bad = true;
+    for (int i = k + 1 + static_cast<int>(threadIdx.x); i <= e; i += blockDim.x)
+      B[static_cast<int64_t>(i) * w + b + (k - i)] /= piv;
+    __syncthreads();
+    const int m = e - k;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+      const int i = k + 1 + t / m, j = k + 1 + t % m;
+      B[static_cast<int64_t>(i) * w + b + (j - i)] -=
+          B[static_cast<int64_t>(i) * w + b + (k - i)] * B[static_cast<int64_t>(k) * w + b + (j - k)];
+    }
+    __syncthreads();
+  }
+  // substitution, one thread per column
+  for (int c = threadIdx.x; c < nck; c += blockDim.x) {
+    for (int l = 0; l < n; ++l) {
+      TC s = X[static_cast<int64_t>(l) * nck + c];
+      for (int t = max(0, l - b); t < l; ++t)
+        s -= B[static_cast<int64_t>(l) * w + b + (t - l)] * X[static_cast<int64_t>(t) * nck + c];
+      X[static_cast<int64_t>(l) * nck + c] = s;
+    }
+    for (int l = n - 1; l >= 0; --l) {
+      TC s = X[static_cast<int64_t>(l) * nck + c];
+      for (int t = l + 1; t <= min(n - 1, l + b); ++t)
+        s -= B[static_cast<int64_t>(l) * w + b + (t - l)] * X[static_cast<int64_t>(t) * nck + c];
+      X[static_cast<int64_t>(l) * nck + c] = s / B[static_cast<int64_t>(l) * w + b];
+    }
+  }
+  __syncthreads();
+  if (!std::is_same<TS, TC>::value || xwork) {
+    TS* out = pvals + pval_off[K];
+    for (int64_t t = threadIdx.x; t < static_cast<int64_t>(n) * nck; t += blockDim.x)
+      out[t] = static_cast<TS>(X[t]);
+  }
+  if (bad && threadIdx.x == 0) {
+    atomicOr(err, E_PIVOT);
+    if (bad_block) bad_block[K] = 1;
+  }
+}
+
 // ---- P in CSR (with the optional truncation of Sec. 4.3) -------------------
 template <class T>
 __global__ void k_p_count(int n, const int8_t* wb, const int* comp_of, const int* local_idx,
@@ -724,6 +837,36 @@ void local_solves(Handle* h, const std::vector<int>& blocks, bool use_list, cons
   if (nb == 0) return;
   (void)use_list;
   const bool separate_x = !std::is_same<TS, TC>::value;
+  if (h->nonsym) {  // the general path: full band in global memory, LU in place
+    std::vector<int64_t> off(2 * nb, 0);
+    int64_t band_total = 0, x_total = 0;
+    for (int k = 0; k < nb; ++k) {
+      const int K = blocks[k];
+      const int64_t nk = h_comp_ptr[K + 1] - h_comp_ptr[K];
+      off[2 * k] = band_total;
+      band_total += nk * (2 * h_band[K] + 1);
+      off[2 * k + 1] = x_total;
+      if (separate_x) x_total += nk * h_ncols[K];
+      const double bw = h_band[K], nn = static_cast<double>(nk);
+      h->info.local_flops += 2.0 * nn * bw * bw + 4.0 * nn * bw * h_ncols[K];
+    }
+    DBuf<int64_t> d_off(&h->alloc, 2 * nb);
+    HIPX(hipMemcpyAsync(d_off, off.data(), 2 * nb * sizeof(int64_t), hipMemcpyHostToDevice,
+                        h->stream));
+    DBuf<int> d_list(&h->alloc, nb);
+    HIPX(hipMemcpyAsync(d_list, blocks.data(), nb * sizeof(int), hipMemcpyHostToDevice,
+                        h->stream));
+    DBuf<TC> scratch(&h->alloc, std::max<int64_t>(band_total, 1));
+    DBuf<TC> xw;
+    if (separate_x) xw.reset(&h->alloc, std::max<int64_t>(x_total, 1));
+    LAUNCH(h, "local_solve_lu", (k_local_solve_lu<TS, TC>), nb, kThreads, 0,
+           static_cast<const int*>(d_list.get()), comp_ptr, cells, h->rp.get(), h->ci.get(),
+           h->val.get(), ecls, wb, coarse_of, comp_of, local_idx, col_ptr, cols, ncols, band,
+           pval_off, pvals, static_cast<const int64_t*>(d_off.get()), scratch.get(), xw.get(),
+           err, bad_block);
+    HIPX(hipStreamSynchronize(h->stream));  // scratch is freed on return
+    return;
+  }
   const int64_t lds_cap = lds_budget(h) / static_cast<int64_t>(sizeof(TC));
   // slots: the blocks whose band fits in LDS (in the given order), then the
   // others, longest first, which get a launch of their own with more waves

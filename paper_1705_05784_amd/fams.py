@@ -46,7 +46,7 @@ class Grid(C.Structure):
 class SetupOpts(C.Structure):
     _fields_ = [("variant", C.c_int32), ("precision", C.c_int32), ("trunc_alpha", C.c_double),
                 ("merge_cap", C.c_int64), ("smoother", C.c_int32), ("profile", C.c_int32),
-                ("restriction", C.c_int32)]
+                ("restriction", C.c_int32), ("nonsymmetric", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -168,13 +168,14 @@ class Solver:
     smoother: 0 none, 1 (or True) ILU(0), 2 ILU(0) plus the per-medium stage;
     restriction: RESTRICT_FE (P^T), RESTRICT_FV or RESTRICT_MIX (or "fe",
     "fv", "mix"); n_wells: the last n_wells unknowns are well pressures (each
-    a coarse node of its own).  Arrays may be numpy or torch; the handle
+    a coarse node of its own); nonsymmetric: A may be non-symmetric (LU local
+    solves and coarse inverse; no flux reconstruction).  Arrays may be numpy or torch; the handle
     copies them.
     """
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
                  precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False,
-                 restriction=0, n_wells=0):
+                 restriction=0, n_wells=0, nonsymmetric=False):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -196,7 +197,8 @@ class Solver:
         if isinstance(restriction, str):
             restriction = RESTRICTIONS[restriction]
         opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
-                         int(smoother), 1 if profile else 0, int(restriction))
+                         int(smoother), 1 if profile else 0, int(restriction),
+                         1 if nonsymmetric else 0)
         h = C.c_void_p()
         self._h = None
         _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, _stream(),

@@ -94,6 +94,20 @@ def _copy_kernel(per):
     return max(cands, key=lambda k: per[k][1])
 
 
+def launch_name(symbol, launch_names=None):
+    """The library's timer name of a kernel symbol: an exact entry of
+    `launch_names`, else the longest key ending in '*' that prefixes it (the
+    instantiations of one templated pass share one timer), else the symbol."""
+    names = launch_names or {}
+    if symbol in names:
+        return names[symbol]
+    best = None
+    for k, v in names.items():
+        if k.endswith("*") and symbol.startswith(k[:-1]) and (best is None or len(k) > len(best[0])):
+            best = (k, v)
+    return best[1] if best else symbol
+
+
 def traffic(fetch_db, write_db, copy_bytes, out_json, source_digest, launch_names=None):
     fetch = counter_per_kernel(fetch_db, "FETCH_SIZE")
     write = counter_per_kernel(write_db, "WRITE_SIZE")
@@ -105,12 +119,22 @@ def traffic(fetch_db, write_db, copy_bytes, out_json, source_digest, launch_name
     for k in fetch:
         if k not in write or k in (ck_f, ck_w):
             continue
-        name = (launch_names or {}).get(k, k)
-        fb = fetch[k][1] * f_scale
-        wb = write[k][1] * w_scale
-        kernels[name] = {"symbol": k, "dispatches": fetch[k][0], "fetch_kib_per_dispatch":
-                         fetch[k][1], "write_kib_per_dispatch": write[k][1],
-                         "traffic_bytes_per_launch": fb + wb}
+        name = launch_name(k, launch_names)
+        d = fetch[k][0]
+        e = kernels.setdefault(name, {"symbols": [], "dispatches": 0, "fetch_kib": 0.0,
+                                      "write_kib": 0.0, "bytes": 0.0})
+        e["symbols"].append(k)
+        e["dispatches"] += d
+        e["fetch_kib"] += fetch[k][1] * d
+        e["write_kib"] += write[k][1] * d
+        e["bytes"] += (fetch[k][1] * f_scale + write[k][1] * w_scale) * d
+    # per launch: averages over the dispatches of every symbol of one timer
+    for name, e in list(kernels.items()):
+        d = max(e["dispatches"], 1)
+        kernels[name] = {"symbols": e["symbols"], "dispatches": e["dispatches"],
+                         "fetch_kib_per_dispatch": e["fetch_kib"] / d,
+                         "write_kib_per_dispatch": e["write_kib"] / d,
+                         "traffic_bytes_per_launch": e["bytes"] / d}
     out = {"copy_kernel": ck_f, "copy_bytes": copy_bytes,
            "fetch_bytes_per_unit": f_scale, "write_bytes_per_unit": w_scale,
            "source_digest": source_digest, "kernels": kernels}
@@ -132,6 +156,9 @@ LAUNCH_NAMES = {
     "k_bspmv<float, double, float, float, 16, false>": "bprolong",
     "k_brestrict<float, float, 16>": "brestrict", "k_bcoarse_part<16>": "bcoarse",
     "k_gemm_mfma128": "gemm_mfma",
+    # the Gram-Schmidt passes, one instantiation per basis size bucket
+    "k_bmaxpy_mdot<16,*": "bmaxpy_mdot", "k_bmaxpy_norm<16,*": "bmaxpy_norm",
+    "k_bmdot<16,*": "bmdot", "k_bmdot<16, 1>": "bdot",
 }
 
 

@@ -97,7 +97,8 @@ def test_setup_options_validated_before_any_device_work():
                  fams.SetupOpts(0, 0, 0.0, 4096, -1, 0, 0),
                  fams.SetupOpts(4, 0, 0.0, 4096, 1, 0, 0),    # no such coupling strategy
                  fams.SetupOpts(0, 2, 0.0, 4096, 1, 0, 0),    # no such precision
-                 fams.SetupOpts(0, 0, 1.5, 4096, 1, 0, 0)):   # truncation threshold >= 1
+                 fams.SetupOpts(0, 0, 1.5, 4096, 1, 0, 0),    # truncation threshold >= 1
+                 fams.SetupOpts(0, 0, 0.0, 4096, 1, 0, 0, 2)):  # no such symmetry option
         assert L.fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, None,
                             C.byref(h)) == -1
     rec = C.c_int32()
