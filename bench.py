@@ -90,6 +90,7 @@ def block_bytes(name, z, K):
         "bilu_upper": (half + n) * (s + 4) + 12 * n + 2 * K * n * s,
         "bdot": K * n * 8,
         "bscale": 2 * K * n * 8,
+        "bpack": 2 * K * n * 8,
         "bcast_d2f": K * n * 12,
         "badd": K * n * (2 * s + 8),
     }.get(name)
@@ -110,12 +111,16 @@ def arnoldi_steps(its, group, restart):
 
 
 def krylov_bytes(name, z, K, jv):
-    """Algorithmic bytes of all launches of one orthogonalization kernel of
-    the lock-step FGMRES (CGS2), from the basis size of every step: the
+    """Algorithmic bytes of all launches of one Gram-Schmidt kernel of the
+    lock-step FGMRES, from the basis size j of every step (j = 1..30 in a
+    restart cycle).  Two-pass form: the dots read the j - 1 finished vectors,
+    the candidate and w; the update reads the same and writes the finished
+    vector and the next candidate.  CGS2 form (restarts above 32): the
     multi-dot reads V_0..V_j and w; the fused correction + dots and the
     correction + norm read V_0..V_j and read and write w."""
     vec = z["n"] * K * 8.0
-    extra = {"bmdot": 1, "bmaxpy_mdot": 2, "bmaxpy_norm": 2}.get(name)
+    extra = {"bgs_dots": 1, "bgs_update": 3, "bmdot": 1, "bmaxpy_mdot": 2,
+             "bmaxpy_norm": 2}.get(name)
     return None if extra is None else sum((j + extra) * vec for j in jv)
 
 
@@ -331,7 +336,7 @@ def headline(args, dev):
             if b is not None:
                 entries[name] = hbm_entry(name, st, b, "edfm3d_256x256x128")
         jv = arnoldi_steps(r["its"], GROUP, RESTART)
-        for name in ("bmdot", "bmaxpy_mdot", "bmaxpy_norm"):
+        for name in ("bgs_dots", "bgs_update", "bmdot", "bmaxpy_mdot", "bmaxpy_norm"):
             if name in st and st[name][1] == len(jv):
                 entries[name] = hbm_entry(name, st, krylov_bytes(name, z, GROUP, jv) / len(jv),
                                           "edfm3d_256x256x128")

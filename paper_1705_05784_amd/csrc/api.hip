@@ -451,7 +451,7 @@ fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t p
     while (K < 16 && K < max_nrhs) K *= 2;
     const double nk = static_cast<double>(n) * K;
     b += nk * 8 * (10 + 2 * restart + 1) + (mixed ? nk * 4 * 6 : 0.0);
-    b += (2 + 34) * nc * K * 8 + 512.0 * (restart + 2) * K * 8;
+    b += (2 + 34) * nc * K * 8 + 2048.0 * (2 * restart + 4) * K * 8;
   }
   b *= 1.10;
   *bytes = static_cast<size_t>(b) + (64u << 20);

@@ -28,21 +28,41 @@ constexpr int kT = 256;
 constexpr int kRedBlocks = 2048;  // workgroups of the multi-dot passes
 
 // ---- layout ------------------------------------------------------------------
-// Q[i * K + r] = q[r * n + i] for r < nr, 0 for the padding lanes
+// Q[i * K + r] = q[r * n + i] for r < nr, 0 for the padding lanes: a
+// transpose through LDS, a tile of kPackRows rows per workgroup, so that both
+// sides are read and written in contiguous runs
+constexpr int kPackRows = 256;
+
 template <int K>
-__global__ void k_pack(int n, int nr, const double* q, double* Q) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(n) * K) return;
-  const int i = static_cast<int>(e / K), r = static_cast<int>(e % K);
-  Q[e] = r < nr ? q[static_cast<int64_t>(r) * n + i] : 0.0;
+__global__ void __launch_bounds__(256) k_pack(int n, int nr, const double* q, double* Q) {
+  __shared__ double t[kPackRows * (K + 1)];  // row l at l (K + 1): padded against bank conflicts
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kPackRows;
+  for (int s = threadIdx.x; s < kPackRows * K; s += blockDim.x) {
+    const int r = s / kPackRows, l = s % kPackRows;
+    const int64_t i = i0 + l;
+    t[l * (K + 1) + r] = (r < nr && i < n) ? q[static_cast<int64_t>(r) * n + i] : 0.0;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < kPackRows * K; s += blockDim.x) {
+    const int l = s / K, r = s % K;
+    if (i0 + l < n) Q[(i0 + l) * K + r] = t[l * (K + 1) + r];
+  }
 }
 
 template <int K>
-__global__ void k_unpack(int n, int nr, const double* Q, double* q) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(n) * K) return;
-  const int i = static_cast<int>(e / K), r = static_cast<int>(e % K);
-  if (r < nr) q[static_cast<int64_t>(r) * n + i] = Q[e];
+__global__ void __launch_bounds__(256) k_unpack(int n, int nr, const double* Q, double* q) {
+  __shared__ double t[kPackRows * (K + 1)];
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kPackRows;
+  for (int s = threadIdx.x; s < kPackRows * K; s += blockDim.x) {
+    const int l = s / K, r = s % K;
+    if (i0 + l < n) t[l * (K + 1) + r] = Q[(i0 + l) * K + r];
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < kPackRows * K; s += blockDim.x) {
+    const int r = s / kPackRows, l = s % kPackRows;
+    const int64_t i = i0 + l;
+    if (r < nr && i < n) q[static_cast<int64_t>(r) * n + i] = t[l * (K + 1) + r];
+  }
 }
 
 // ---- operators on block vectors ------------------------------------------------
@@ -104,15 +124,11 @@ __device__ double group_sum(double v) {
 
 // Y[row * K + r] = sum_p M[row, p] X[col_p * K + r] for the fat rows of R =
 // P^T: one workgroup per row, 256 / K groups of K lanes stride over the
-// row's entries, then a fixed-order sum across the groups.  Every fine cell
-// lies in the supports of several neighbouring coarse nodes, so rows are
-// dealt to the XCDs in contiguous ranges (xcd_block): neighbouring rows run
-// on one XCD at about the same time and gather the shared cells from its L2.
+// row's entries, then a fixed-order sum across the groups
 template <class TV, class TX, int K>
 __global__ void __launch_bounds__(256)
 k_brestrict(int nrows, const int* rp, const int* ci, const TV* val, const TX* X, double* Y) {
-  const int row = static_cast<int>(xcd_block());
-  if (row >= nrows) return;
+  const int row = blockIdx.x;
   const int r = threadIdx.x % K, g = threadIdx.x / K;
   constexpr int G = 256 / K;
   double s = 0.0;
@@ -588,6 +604,7 @@ __global__ void k_bsqrt(int K, double* d, int stride) {
 struct BState {
   int m, stride;
   int H, cs, sn, g, y, hcol, out, beta;  // offsets inside one right-hand side's record
+  int dots, hp, c2, un;                   // the two-pass Gram-Schmidt (see block_gmres)
   static BState make(int m) {
     BState s{};
     s.m = m;
@@ -600,6 +617,10 @@ struct BState {
     s.hcol = o; o += m + 2;
     s.out = o; o += 2;
     s.beta = o; o += 2;
+    s.dots = o; o += 2 * m + 2;
+    s.hp = o; o += m + 1;
+    s.c2 = o; o += 2 * m + 3;
+    s.un = o; o += 2;
     s.stride = o;
     return s;
   }
@@ -671,6 +692,249 @@ __global__ void k_bbacksolve(int K, BState s, double* base, KK kk) {
     for (int c = i + 1; c < k; ++c) t -= S[s.H + static_cast<int64_t>(c) * (m + 1) + i] * y[c];
     y[i] = t / S[s.H + static_cast<int64_t>(i) * (m + 1) + i];
   }
+}
+
+// ---- Gram-Schmidt with the second pass delayed by one step ------------------------
+// Each Arnoldi step of block_gmres (two-pass form) reads the basis twice
+// instead of three times.  At step j the candidate u_j (V slot j) has been
+// orthogonalised once against q_0..q_{j-1} but neither re-orthogonalised nor
+// normalised, and w = A M u_j.  Pass one takes, in one sweep over q_0..q_{j-1},
+// u_j and w, the dots a = Q^T u_j, b = Q^T w, u_j.u_j and u_j.w.  Then
+// q_j = (u_j - Q a) / nu with nu^2 = u_j.u_j - |a|^2 (q_j is orthogonal to Q
+// after the second pass, so Pythagoras gives its norm), Hessenberg column
+// j - 1 is finished as h' + a with sub-diagonal nu (h' its first-pass
+// coefficients), and w's first-pass coefficients against [Q, q_j] are b and
+// (u_j.w - a.b) / nu.  Pass two writes q_j into slot j and the next candidate
+// u_{j+1} = w - Q b - h_j q_j into slot j + 1, summing |u_{j+1}|^2 for the
+// stopping test of column j (taken with the first-pass coefficients; the
+// column is finished at step j + 1, or as it stands when its right-hand side
+// stops or the cycle ends).  z_j = M u_j is a valid flexible-GMRES direction
+// for any u_j, so A Z = V H holds with the finished columns.
+
+// pass one: part[(blk * pstride + i) * K + r] for i < nq: q_i.u, nq + i:
+// q_i.w, 2 nq: u.u, 2 nq + 1: u.w (NV >= nq, a multiple of 4, or 0 for nq = 0)
+template <int K, int NV>
+__global__ void __launch_bounds__(256) FAMS_STREAM_WAVES
+k_dcgs_dots(int64_t nk, int nq, const double* V, int64_t ldv, const double* u, const double* w,
+            double* part, int pstride) {
+  const char* Vb = reinterpret_cast<const char*>(V);
+  const char* ub = reinterpret_cast<const char*>(u);
+  const char* wb = reinterpret_cast<const char*>(w);
+  const int64_t ld8 = ldv * 8;
+  double da[NV > 0 ? NV : 1], db[NV > 0 ? NV : 1];
+  double duu = 0.0, duw = 0.0;
+#pragma unroll
+  for (int v = 0; v < (NV > 0 ? NV : 1); ++v) da[v] = db[v] = 0.0;
+  const uint32_t end = static_cast<uint32_t>(nk * 8);
+  const uint32_t step = gridDim.x * blockDim.x * 8u;
+  for (uint32_t off0 = (blockIdx.x * blockDim.x + threadIdx.x) * 8u; off0 < end; off0 += step) {
+    const uint32_t off = opaque(off0);
+    const double ue = load_at<double>(ub, off);
+    const double we = load_at<double>(wb, off);
+    if constexpr (NV > 0) {
+      double q[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v] = load_at<double>(Vb + ld8 * min(v, nq - 1), off);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        da[v] += q[v] * ue;
+        db[v] += q[v] * we;
+      }
+    }
+    duu += ue * ue;
+    duw += ue * we;
+  }
+  // logical order: a (nq), b (nq), u.u, u.w; batches with constant indices
+  // so that the sums stay in registers
+  constexpr int NB = NV > 0 ? (NV + kDotBatch - 1) / kDotBatch : 0;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      if (a * kDotBatch >= nq) break;
+      double blk[kDotBatch];
+#pragma unroll
+      for (int u = 0; u < kDotBatch; ++u) {
+        const int v = a * kDotBatch + u;
+        blk[u] = v < NV ? (half ? db[v < NV ? v : 0] : da[v < NV ? v : 0]) : 0.0;
+      }
+      store_dots<K>(blk, min(kDotBatch, nq - a * kDotBatch), half * nq + a * kDotBatch, part,
+                    pstride);
+    }
+  }
+  double tail[kDotBatch] = {duu, duw};
+  store_dots<K>(tail, 2, 2 * nq, part, pstride);
+}
+
+// pass two, two entries per thread: q_j = (u - sum_i a_i q_i) inv_nu into
+// slot nq, u_next = wm w - sum_i b_i q_i - h_j q_j into slot nq + 1, and the
+// partial sums of u_next^2.  c2 per right-hand side: a (nq), b (nq), inv_nu,
+// h_j, wm (all zero for a right-hand side that has stopped).
+template <int K, int NV>
+__global__ void __launch_bounds__(256) FAMS_STREAM_WAVES
+k_dcgs_update(int64_t nk, int nq, double* V, int64_t ldv, const double* coef, int cstride,
+              const double* w, double* part) {
+  constexpr int NC = 2 * (NV > 0 ? NV : 0) + 3;
+  __shared__ double cs[K * NC];
+  for (int t = threadIdx.x; t < K * NC; t += blockDim.x) {
+    const int r = t / NC, v = t % NC;
+    double c = 0.0;
+    if (v < NV) c = v < nq ? coef[static_cast<int64_t>(r) * cstride + v] : 0.0;
+    else if (v < 2 * NV) c = v - NV < nq ? coef[static_cast<int64_t>(r) * cstride + nq + v - NV] : 0.0;
+    else c = coef[static_cast<int64_t>(r) * cstride + 2 * nq + (v - 2 * NV)];
+    cs[t] = c;
+  }
+  __syncthreads();
+  const int r0 = (2 * threadIdx.x) % K;
+  const double* c0 = cs + r0 * NC;
+  const double* c1 = c0 + NC;
+  char* Vb = reinterpret_cast<char*>(V);
+  const char* wb = reinterpret_cast<const char*>(w);
+  const int64_t ld8 = ldv * 8;
+  char* ub = Vb + ld8 * nq;
+  char* nb_ = Vb + ld8 * (nq + 1);
+  double a0 = 0.0, a1 = 0.0;
+  const uint32_t end = static_cast<uint32_t>((nk / 2) * 16);
+  const uint32_t step = gridDim.x * blockDim.x * 16u;
+  for (uint32_t off0 = (blockIdx.x * blockDim.x + threadIdx.x) * 16u; off0 < end; off0 += step) {
+    const uint32_t off = opaque(off0);
+    const double2 ue = load_at<double2>(ub, off);
+    const double2 we = load_at<double2>(wb, off);
+    double sa0 = 0.0, sa1 = 0.0, sb0 = 0.0, sb1 = 0.0;
+    if constexpr (NV > 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double2 x = load_at<double2>(Vb + ld8 * min(v, nq - 1), off);
+        sa0 += c0[v] * x.x;
+        sa1 += c1[v] * x.y;
+        sb0 += c0[NV + v] * x.x;
+        sb1 += c1[NV + v] * x.y;
+      }
+    }
+    double2 qv, un;
+    qv.x = (ue.x - sa0) * c0[2 * NV];
+    qv.y = (ue.y - sa1) * c1[2 * NV];
+    un.x = c0[2 * NV + 2] * we.x - sb0 - c0[2 * NV + 1] * qv.x;
+    un.y = c1[2 * NV + 2] * we.y - sb1 - c1[2 * NV + 1] * qv.y;
+    *reinterpret_cast<double2*>(ub + off) = qv;
+    *reinterpret_cast<double2*>(nb_ + off) = un;
+    a0 += un.x * un.x;
+    a1 += un.y * un.y;
+  }
+  store_pair<K>(a0, a1, 0, part, 1);
+}
+
+template <int K>
+void launch_dcgs(Handle* h, bool second, unsigned nb, int64_t nk, int nq, double* V, int64_t ldv,
+                 const double* w, const double* coef, int cstride, double* part, int pstride) {
+#define FAMS_DCGS(NV)                                                                          \
+  do {                                                                                         \
+    if (second)                                                                                \
+      LAUNCH(h, "bgs_update", (k_dcgs_update<K, NV>), nb, kT, 0, nk, nq, V, ldv, coef,         \
+             cstride, w, part);                                                                \
+    else                                                                                       \
+      LAUNCH(h, "bgs_dots", (k_dcgs_dots<K, NV>), nb, kT, 0, nk, nq, V, ldv,                   \
+             static_cast<const double*>(V + static_cast<int64_t>(nq) * ldv), w, part, pstride); \
+  } while (0)
+  switch ((nq + 3) / 4) {
+    case 0: FAMS_DCGS(0); break;
+    case 1: FAMS_DCGS(4); break;
+    case 2: FAMS_DCGS(8); break;
+    case 3: FAMS_DCGS(12); break;
+    case 4: FAMS_DCGS(16); break;
+    case 5: FAMS_DCGS(20); break;
+    case 6: FAMS_DCGS(24); break;
+    case 7: FAMS_DCGS(28); break;
+    case 8: FAMS_DCGS(32); break;
+    default: FAMS_REQUIRE(false, FAMS_ERR_CAPACITY, "two-pass Gram-Schmidt: too many vectors");
+  }
+#undef FAMS_DCGS
+}
+
+// per right-hand side in `mask` (one thread each): finish Hessenberg column
+// j - 1 from its first-pass coefficients and the dots of pass one (rotations
+// 0..j-2 applied, rotation j-1 formed, g updated), keep w's first-pass
+// coefficients for column j, and set pass two's coefficients; right-hand
+// sides outside the mask get zero coefficients.  A candidate without a part
+// orthogonal to Q (nu^2 <= 0) gets a zero q_j and is flagged (out[1] = 0).
+__global__ void k_dcgs_coef(int K, BState s, double* base, int j, unsigned mask) {
+  const int r = threadIdx.x;
+  if (r >= K) return;
+  double* S = base + static_cast<int64_t>(r) * s.stride;
+  double* c2 = S + s.c2;
+  if (!(mask >> r & 1u)) {
+    for (int i = 0; i < 2 * j + 3; ++i) c2[i] = 0.0;
+    return;
+  }
+  const int m = s.m;
+  const double* a = S + s.dots;
+  const double* b = a + j;
+  const double uu = a[2 * j], uw = a[2 * j + 1];
+  double na2 = 0.0, ab = 0.0;
+  for (int i = 0; i < j; ++i) {
+    na2 += a[i] * a[i];
+    ab += a[i] * b[i];
+  }
+  const double nu2 = uu - na2;
+  const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+  const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+  S[s.un + 1] = nu > 0.0 ? 1.0 : 0.0;
+  if (j >= 1) {
+    double* col = S + s.H + static_cast<int64_t>(j - 1) * (m + 1);
+    double* cs = S + s.cs;
+    double* sn = S + s.sn;
+    double* g = S + s.g;
+    const double* hp = S + s.hp;
+    for (int i = 0; i < j; ++i) col[i] = hp[i] + a[i];
+    col[j] = nu;
+    for (int i = 0; i < j - 1; ++i) {
+      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double den = hypot(col[j - 1], col[j]);
+    const double c = den == 0.0 ? 1.0 : col[j - 1] / den;
+    const double sg = den == 0.0 ? 0.0 : col[j] / den;
+    cs[j - 1] = c;
+    sn[j - 1] = sg;
+    col[j - 1] = c * col[j - 1] + sg * col[j];
+    col[j] = 0.0;
+    g[j] = -sg * g[j - 1];
+    g[j - 1] = c * g[j - 1];
+  }
+  double* hp = S + s.hp;
+  for (int i = 0; i < j; ++i) hp[i] = b[i];
+  const double hj = (uw - ab) * inv;
+  hp[j] = hj;
+  for (int i = 0; i < j; ++i) {
+    c2[i] = a[i];
+    c2[j + i] = b[i];
+  }
+  c2[2 * j] = inv;
+  c2[2 * j + 1] = hj;
+  c2[2 * j + 2] = 1.0;
+}
+
+// the stopping test of column j from its first-pass coefficients: hcol = [h',
+// |u_{j+1}|] (what k_bgivens commits when the column ends here), out[0] = the
+// residual estimate after the rotations, out[1] = |u_{j+1}| (0 if flagged)
+__global__ void k_dcgs_estimate(int K, BState s, double* base, int j, unsigned mask) {
+  const int r = threadIdx.x;
+  if (r >= K || !(mask >> r & 1u)) return;
+  double* S = base + static_cast<int64_t>(r) * s.stride;
+  const double t = sqrt(fmax(S[s.un], 0.0));
+  double* hcol = S + s.hcol;
+  for (int i = 0; i <= j; ++i) hcol[i] = S[s.hp + i];
+  hcol[j + 1] = t;
+  // entry j after rotations 0..j-1 (rotation i turns rows i and i + 1; the
+  // running value is row i + 1's after it)
+  double x = hcol[0];
+  for (int i = 0; i < j; ++i) x = -S[s.sn + i] * x + S[s.cs + i] * hcol[i + 1];
+  const double y = t;
+  const double den = hypot(x, y);
+  const double sg = den == 0.0 ? 0.0 : y / den;
+  S[s.out] = fabs(sg * S[s.g + j]);
+  S[s.out + 1] = S[s.un + 1] > 0.0 ? t : 0.0;
 }
 
 // ---- the lock-step iteration -----------------------------------------------------
@@ -746,7 +1010,7 @@ void ensure_block_workspace(Handle* h, int K, int m) {
   const int cw = coarse_chunk_width(h->nc);
   const size_t nch = (h->nc + cw - 1) / cw;
   h->bpart.reset(&h->alloc, (2 + nch) * static_cast<size_t>(h->nc) * K);
-  h->bred.reset(&h->alloc, static_cast<size_t>(kRedBlocks) * (m + 2) * K + 16);
+  h->bred.reset(&h->alloc, static_cast<size_t>(kRedBlocks) * (2 * m + 4) * K + 16);
   h->bsmall.reset(&h->alloc, static_cast<size_t>(BState::make(m).stride) * K + 16);
   h->bK = K;
   h->bm = m;
@@ -794,8 +1058,8 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
     ysc = k.y32;
     xb = k.xb32;
   }
-  LAUNCH(h, "brestrict", (k_brestrict<T, T, K>), xcd_grid(nc), 256, 0, nc, h->r_rp.get(),
-         h->r_ci.get(), rv, rT, k.rc);
+  LAUNCH(h, "brestrict", (k_brestrict<T, T, K>), nc, 256, 0, nc, h->r_rp.get(), h->r_ci.get(),
+         rv, rT, k.rc);
   {
     dim3 grid(blocks_for(nc, 256), k.nch);
     LAUNCH(h, "bcoarse", k_bcoarse_part<K>, grid, 256, 0, nc, k.cw, h->Ainv.get(), k.rc, k.cpart);
@@ -875,6 +1139,10 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
   const int64_t n = h->n, nk = k.nk;
   const int m = std::min(o->restart, k.m);
   const BState& S = k.st;
+  // Gram-Schmidt: the two-pass form (second pass of each candidate delayed to
+  // the next step) while its fused kernels can take the basis, else CGS2
+  // with three passes
+  const bool two_pass = m <= kFuseMax && offset_addressable(nk, k.nb);
   bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p, k.q,
                                               k.r, "bresid_outer");
   bnorms<K>(h, k, k.r, S.beta);
@@ -905,7 +1173,41 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
     KK kk{};
     unsigned cyc = mask;
     int jmax = 0;
-    for (int j = 0; j < m && cyc; ++j) {
+    if (two_pass) {
+      for (int j = 0; j < m && cyc; ++j) {
+        double* uj = k.V + j * nk;
+        double* zj = k.Z + j * nk;
+        bstage_any<K>(h, k, uj, zj);
+        LAUNCH(h, "bspmv", (k_bspmv<double, double, double, double, K, false>),
+               xcd_grid(blocks_for(nk, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(),
+               zj, static_cast<const double*>(nullptr), k.w);
+        launch_dcgs<K>(h, false, k.nb, nk, j, k.V, nk, k.w, nullptr, 0, k.part, 2 * m + 2);
+        LAUNCH(h, "breduce", k_breduce, dim3(2 * j + 2, K), 256, 0, k.nb, K, k.part, 2 * m + 2,
+               k.small + S.dots, S.stride);
+        LAUNCH(h, "bgs_coef", k_dcgs_coef, 1, 64, 0, K, S, k.small, j, cyc);
+        launch_dcgs<K>(h, true, k.nb, nk, j, k.V, nk, k.w, k.small + S.c2, S.stride, k.part, 1);
+        LAUNCH(h, "breduce", k_breduce, dim3(1, K), 256, 0, k.nb, K, k.part, 1, k.small + S.un,
+               S.stride);
+        LAUNCH(h, "bgs_estimate", k_dcgs_estimate, 1, 64, 0, K, S, k.small, j, cyc);
+        std::vector<double> est = read_field(h, k, S.out, 2);
+        unsigned next = 0;
+        for (int r = 0; r < K; ++r) {
+          if (!(cyc >> r & 1u)) continue;
+          ++rs[r].it;
+          kk.v[r] = j + 1;
+          const double e = est[2 * r], hn = est[2 * r + 1];
+          if (!(e <= rs[r].tol || rs[r].it >= o->max_iter || !(hn > 0.0) || !std::isfinite(e)))
+            next |= 1u << r;
+        }
+        jmax = j + 1;
+        // columns that end here (their right-hand side stops, or the cycle
+        // ends) are committed as they stand
+        const unsigned commit = j + 1 == m ? cyc : (cyc & ~next);
+        if (commit) LAUNCH(h, "bgivens", k_bgivens, 1, 64, 0, K, S, k.small, j, commit);
+        cyc = next;
+      }
+    }
+    for (int j = 0; j < m && cyc && !two_pass; ++j) {
       double* vj = k.V + j * nk;
       double* zj = k.Z + j * nk;
       bstage_any<K>(h, k, vj, zj);
@@ -1010,16 +1312,16 @@ void solve_group(Handle* h, const double* q, double* p, int nr, const fams_solve
   for (Handle* g : {h, h->blk.get()})
     if (g && g->sweep_err.get()) HIPX(hipMemsetAsync(g->sweep_err, 0, sizeof(int), h->stream));
   auto t0 = std::chrono::steady_clock::now();
-  LAUNCH(h, "bpack", k_pack<K>, blocks_for(nk, kT), kT, 0, n, nr, q, k.q);
+  LAUNCH(h, "bpack", k_pack<K>, blocks_for(n, kPackRows), kT, 0, n, nr, q, k.q);
   if (o->use_initial_guess)
-    LAUNCH(h, "bpack", k_pack<K>, blocks_for(nk, kT), kT, 0, n, nr, static_cast<const double*>(p),
+    LAUNCH(h, "bpack", k_pack<K>, blocks_for(n, kPackRows), kT, 0, n, nr, static_cast<const double*>(p),
            k.p);
   else
     HIPX(hipMemsetAsync(k.p, 0, nk * sizeof(double), h->stream));
   std::vector<RhsState> rs(K);
   if (o->outer == FAMS_GMRES) block_gmres<K>(h, k, nr, o, rs);
   else block_richardson<K>(h, k, nr, o, rs);
-  LAUNCH(h, "bunpack", k_unpack<K>, blocks_for(nk, kT), kT, 0, n, nr, k.p, p);
+  LAUNCH(h, "bunpack", k_unpack<K>, blocks_for(n, kPackRows), kT, 0, n, nr, k.p, p);
   HIPX(hipStreamSynchronize(h->stream));
   int e = 0;
   for (Handle* g : {h, h->blk.get()}) {

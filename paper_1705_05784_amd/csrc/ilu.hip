@@ -975,7 +975,7 @@ void build_ilu(Handle* h) {
   // everything the sweeps keep in the handle, allocated now so that applying
   // the smoother allocates nothing: work tickets, the wait error word, the
   // sweep-order input and the factor values in the schedules' ELL form
-  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, 4);
+  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
     h->sweep_err.reset(&h->alloc, 1);
     HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
@@ -1068,7 +1068,7 @@ void build_block_smoother(Handle* h) {
 // x = U^{-1} L^{-1} b.  `y` is scratch of n entries.
 template <class T>
 void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
-  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, 4);
+  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
     h->sweep_err.reset(&h->alloc, 1);
     HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
@@ -1139,18 +1139,28 @@ namespace {
 // same addresses (one transaction) and gather the K consecutive values of
 // each dependency (one contiguous stretch); lane r waits only for entry r of
 // the rows it depends on (value as ready flag, bounded waits).
+//
+// Chunks are handed out by ncls counters (one per XCD when the grid allows,
+// kTicketStride ints apart): workgroup b draws chunk cls + ncls t, t from
+// counter cls = b % ncls, so each class takes its chunks in increasing
+// order and no counter serves every workgroup of the device.  Waits stay
+// deadlock-free: the lowest chunk not yet drawn belongs to a class whose
+// workgroups all hold lower chunks, which wait only on lower chunks still,
+// so one of them finishes and draws it.
 constexpr int kBlkRows = 64;
 
 template <class T, bool kUpper, int K>
 __global__ void __launch_bounds__(kBlkRows * K)
 k_bsweep(const int* rows, const int* chunk, int nchunks, const int* rp, const int* ci,
-         const int* diag, const T* lu, const T* in, T* out, T* arm, int* ticket, int* err,
-         unsigned long long limit) {
+         const int* diag, const T* lu, const T* in, T* out, T* arm, int* ticket, int ncls,
+         int* err, unsigned long long limit) {
   using U = typename Sentinel<T>::U;
   __shared__ int s_c;
   const int r = threadIdx.x % K, slot = threadIdx.x / K;
+  const int cls = blockIdx.x % ncls;
+  int* my = ticket + kTicketStride * cls;
   while (true) {
-    if (threadIdx.x == 0) s_c = atomicAdd(ticket, 1);
+    if (threadIdx.x == 0) s_c = cls + ncls * atomicAdd(my, 1);
     __syncthreads();
     const int c = s_c;
     __syncthreads();
@@ -1218,14 +1228,16 @@ void block_chunk_table(Handle* h, Levels* L) {
 // y is scratch of n * K entries
 template <class T, int K>
 void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
-  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, 4);
+  if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
     h->sweep_err.reset(&h->alloc, 1);
     HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
   }
   block_chunk_table(h, &h->lvl_lo);
   block_chunk_table(h, &h->lvl_up);
-  HIPX(hipMemsetAsync(h->ilu_ticket, 0, 2 * sizeof(int), h->stream));
+  int* tlo = h->ilu_ticket.get() + kTicketBlock;
+  int* tup = tlo + kXcd * kTicketStride;
+  HIPX(hipMemsetAsync(tlo, 0, 2 * kXcd * kTicketStride * sizeof(int), h->stream));
   const int64_t nk = static_cast<int64_t>(h->n) * K;
   LAUNCH(h, "bilu_arm", k_bfill_sentinel<T>, blocks_for(nk, kT), kT, 0, nk, y);
   const unsigned long long lim = wait_limit(h);
@@ -1235,11 +1247,12 @@ void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
   const int groups_up = std::min(h->lvl_up.nbchunks, cap);
   LAUNCH(h, "bilu_lower", (k_bsweep<T, false, K>), groups_lo, kBlkRows * K, 0,
          h->lvl_lo.rows.get(), h->lvl_lo.bchunk.get(), h->lvl_lo.nbchunks, h->rp.get(),
-         h->ci.get(), h->diag.get(), lu, b, y, x, h->ilu_ticket.get(), h->sweep_err.get(), lim);
+         h->ci.get(), h->diag.get(), lu, b, y, x, tlo, std::min(groups_lo, kXcd),
+         h->sweep_err.get(), lim);
   LAUNCH(h, "bilu_upper", (k_bsweep<T, true, K>), groups_up, kBlkRows * K, 0,
          h->lvl_up.rows.get(), h->lvl_up.bchunk.get(), h->lvl_up.nbchunks, h->rp.get(),
          h->ci.get(), h->diag.get(), lu, static_cast<const T*>(y), x, static_cast<T*>(nullptr),
-         h->ilu_ticket.get() + 1, h->sweep_err.get(), lim);
+         tup, std::min(groups_up, kXcd), h->sweep_err.get(), lim);
 }
 
 #define FAMS_ILU_BLOCK(T, K) \

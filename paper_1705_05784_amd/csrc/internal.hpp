@@ -152,6 +152,13 @@ inline unsigned xcd_grid(int64_t blocks) {
   return static_cast<unsigned>((blocks + kXcd - 1) / kXcd * kXcd);
 }
 
+// the handle's work-ticket words: the one-launch sweeps use the first two;
+// the lock-step sweeps one counter per XCD class and direction, each on a
+// cache line of its own, from kTicketBlock on
+constexpr int kTicketStride = 32;
+constexpr int kTicketBlock = kTicketStride;
+constexpr int kTicketInts = kTicketBlock + 2 * kXcd * kTicketStride;
+
 inline unsigned blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;

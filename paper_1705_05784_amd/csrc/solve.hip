@@ -64,8 +64,7 @@ k_spmv8(int n, const int* rp, const int* ci, const TV* val, const TX* x, TY* y) 
 template <class TV, class TX>
 __global__ void __launch_bounds__(256)
 k_spmv_wave(int nrows, const int* rp, const int* ci, const TV* val, const TX* x, double* y) {
-  // rows in XCD-contiguous ranges: neighbouring fat rows of R share cells
-  int row = static_cast<int>(xcd_block()) * (blockDim.x / 64) + threadIdx.x / 64;
+  int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   int lane = threadIdx.x % 64;
   if (row >= nrows) return;
   double s = 0.0;
@@ -327,8 +326,8 @@ void stage(Handle* h, const Work& k, const double* r, double* z) {
     x = k.x32;
     ysc = k.y32;
   }
-  LAUNCH(h, "restrict", (k_spmv_wave<T, T>), xcd_grid(blocks_for(nc, 4)), 256, 0, nc,
-         h->r_rp.get(), h->r_ci.get(), rv, rT, k.rc);
+  LAUNCH(h, "restrict", (k_spmv_wave<T, T>), blocks_for(nc, 4), 256, 0, nc, h->r_rp.get(),
+         h->r_ci.get(), rv, rT, k.rc);
   coarse_apply(h, h->Ainv.get(), nc, k.rc, k.xc, k.gpart);
   LAUNCH(h, "prolong", (k_spmv8<T, double, T>), blocks_for(n, kT / kSub), kT, 0, n,
          h->p_rp.get(), h->p_ci.get(), pv, k.xc, d1);

@@ -159,6 +159,7 @@ LAUNCH_NAMES = {
     # the Gram-Schmidt passes, one instantiation per basis size bucket
     "k_bmaxpy_mdot<16,*": "bmaxpy_mdot", "k_bmaxpy_norm<16,*": "bmaxpy_norm",
     "k_bmdot<16,*": "bmdot", "k_bmdot<16, 1>": "bdot",
+    "k_dcgs_dots<16,*": "bgs_dots", "k_dcgs_update<16,*": "bgs_update",
 }
 
 
