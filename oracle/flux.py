@@ -9,7 +9,8 @@ mass conservative, but gives no algorithm.  The reconstruction here
 is the standard multiscale finite-volume one the paper cites:
 
 1. FV stage: A_FV = R^FV A P;  x = A_FV^{-1} R^FV (q - A p) (LU with partial
-   pivoting plus two steps of iterative refinement on the coarse system);
+   pivoting plus two steps of iterative refinement against the block
+   defects R^FV (q - A p'), the residual written with the fluxes);
    p' = p + P x, so that R^FV (q - A p') = 0: every primal block conserves mass.
 2. In each primal block K, a Neumann problem with the fluxes across the
    block boundary taken from p':
@@ -17,7 +18,11 @@ is the standard multiscale finite-volume one the paper cites:
            = q_i - sum_{j not in K} T_ij (p'_i - p'_j),   i in K,
    where T_ij = -A_ij and s_i = sum_j A_ij (the Dirichlet boundary term).
    If no cell of K has s_i > 0 the problem is singular but compatible, and
-   p'' is pinned to p' at K's coarse node.
+   p'' is pinned to p' at K's coarse node.  A row sum counts as zero when it
+   is rounding, |s_i| <= 1e-10 sum_{j != i} |A_ij| (measured against the
+   row's own couplings: a weakly coupled boundary cell next to
+   high-transmissibility fractures still has a real s_i > 0, and pinning its
+   block would leave s_i (p''_i - p'_i) unbalanced at the coarse node).
 3. Fluxes F_ij = T_ij (p''_i - p''_j) inside a block and T_ij (p'_i - p'_j)
    across blocks; exchange E_i = s_i p''_i - q_i (boundary flux and sources).
    Each cell then balances: sum_j F_ij + E_i = 0.
@@ -28,7 +33,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-SINGULAR_ROWSUM = 1e-10   # s_i <= this * max_i A_ii counts as zero
+SINGULAR_ROWSUM = 1e-10   # |s_i| <= this * sum_{j != i} |A_ij| counts as zero
 
 
 def fv_restriction(primal, n_coarse):
@@ -36,16 +41,42 @@ def fv_restriction(primal, n_coarse):
     return sp.csr_matrix((np.ones(n), (np.asarray(primal), np.arange(n))), shape=(n_coarse, n))
 
 
+def dirichlet_rows(A):
+    """Rows with a real (not rounding) row sum s_i: |s_i| > SINGULAR_ROWSUM
+    sum_{j != i} |A_ij|."""
+    A = sp.csr_matrix(A)
+    s = np.asarray(A.sum(axis=1)).ravel()
+    offsum = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(A.diagonal())
+    return s > SINGULAR_ROWSUM * offsum
+
+
+def flux_residual(A, q, p):
+    """q - A p written with the fluxes: q_i - s_i p_i + sum_{j != i} A_ij (p_i -
+    p_j) (s_i = sum_j A_ij).  Equal to q - A p; rounded relative to the fluxes
+    rather than to the products A_ij p_j, which at a high conductivity
+    contrast are many orders larger."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    r = np.repeat(np.arange(n), np.diff(A.indptr))
+    c = A.indices
+    off = r != c
+    s = np.asarray(A.sum(axis=1)).ravel()
+    terms = np.where(off, A.data * (p[r] - p[c]), 0.0)
+    return q - s * p + np.bincount(r, weights=terms, minlength=n)
+
+
 def fv_stage(A, P, primal, q, p, refine=2):
+    """p' = p + P x with R^FV A p' = R^FV q: x from the LU of A_FV = R^FV A P,
+    then `refine` steps of iterative refinement against the block defects
+    R^FV (q - A p') (flux form)."""
     A = sp.csr_matrix(A)
     nc = P.shape[1]
     Rfv = fv_restriction(primal, nc)
     Afv = np.asarray((Rfv @ (A @ P)).todense())
     lu = sla.lu_factor(Afv)
-    rc = Rfv @ (q - A @ p)
-    x = sla.lu_solve(lu, rc)
+    x = sla.lu_solve(lu, Rfv @ flux_residual(A, q, p))
     for _ in range(refine):
-        x = x + sla.lu_solve(lu, rc - Afv @ x)
+        x = x + sla.lu_solve(lu, Rfv @ flux_residual(A, q, p + P @ x))
     return p + P @ x
 
 
@@ -58,7 +89,7 @@ def reconstruct_flux(A, P, primal, vertex, q, p):
     p1 = fv_stage(A, P, primal, q, p)
     s = np.asarray(A.sum(axis=1)).ravel()
     diag = A.diagonal()
-    thr = SINGULAR_ROWSUM * diag.max()
+    has_s = dirichlet_rows(A)
     rp, ci, va = A.indptr, A.indices, A.data
     p2 = np.empty(n)
     order = np.argsort(primal, kind="stable")
@@ -83,7 +114,7 @@ def reconstruct_flux(A, P, primal, vertex, q, p):
                 else:
                     M[a, a] += va[pp]
                     b[a] += va[pp] * (p1[i] - p1[j])
-        if s[cells].max() <= thr:
+        if not has_s[cells].any():
             v = loc[int(vertex[K])]
             keep = np.array([a for a in range(m) if a != v], dtype=np.int64)
             sol = np.empty(m)

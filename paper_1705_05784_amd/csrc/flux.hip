@@ -38,7 +38,12 @@ constexpr int kFvRefineMax = 10;
 // at a high permeability contrast a block's local matrix is ill conditioned
 // and every step gains about -log10(cond * eps) digits of the balance
 constexpr int kNeumannRefine = 3;
-constexpr double kSingularRowsum = 1e-10;  // s_i <= this * max A_ii counts as zero
+// a row sum counts as zero (no Dirichlet coupling) when it is rounding:
+// |s_i| <= kSingularRowsum * sum_{j != i} |A_ij|, against the row's own
+// couplings (a weakly coupled boundary cell beside high-transmissibility
+// fractures has a real s_i > 0; pinning its block would leave s_i d_i
+// unbalanced at the coarse node)
+constexpr double kSingularRowsum = 1e-10;
 
 __global__ void k_rowsum_diag(int n, const int* rp, const int* ci, const double* av, double* s,
                               double* dmax_part) {
@@ -111,8 +116,8 @@ __global__ void k_block_local(int n, const int* cells, const int* primal, const 
 // per primal block: bandwidth of its within-block couplings and whether the
 // local Neumann problem is singular (no cell with a positive row sum)
 __global__ void k_fv_symbolic(const int* ptr, const int* cells, const int* rp, const int* ci,
-                              const int* primal, const int* local, const double* s,
-                              const double* dmax, int* band, int* singular) {
+                              const double* av, const int* primal, const int* local,
+                              const double* s, int* band, int* singular) {
   __shared__ int s_b, s_pos;
   int K = blockIdx.x;
   if (threadIdx.x == 0) {
@@ -121,15 +126,16 @@ __global__ void k_fv_symbolic(const int* ptr, const int* cells, const int* rp, c
   }
   __syncthreads();
   int beg = ptr[K], n = ptr[K + 1] - beg;
-  double thr = kSingularRowsum * *dmax;
   int bm = 0, pos = 0;
   for (int l = threadIdx.x; l < n; l += blockDim.x) {
     int i = cells[beg + l];
-    if (s[i] > thr) pos = 1;
+    double off = 0.0;
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
       int j = ci[p];
+      if (j != i) off += fabs(av[p]);
       if (j != i && primal[j] == K) bm = max(bm, abs(local[j] - l));
     }
+    if (s[i] > kSingularRowsum * off) pos = 1;
   }
   atomicMax(&s_b, bm);
   atomicOr(&s_pos, pos);
@@ -159,12 +165,20 @@ __global__ void k_add_to(int n, const double* a, double* y) {
   if (i < n) y[i] += a[i];
 }
 
-__global__ void k_resid_f(int n, const int* rp, const int* ci, const double* av, const double* x,
-                          const double* b, double* y) {
+// y = b - A x written with the fluxes: b_i - s_i x_i + sum_{j != i} A_ij (x_i -
+// x_j) (s = row sums of A); the same value, rounded relative to the fluxes
+// rather than to the products A_ij x_j (many orders larger beside
+// high-transmissibility fractures)
+__global__ void k_resid_f(int n, const int* rp, const int* ci, const double* av, const double* s,
+                          const double* x, const double* b, double* y) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double t = b[i];
-  for (int p = rp[i]; p < rp[i + 1]; ++p) t -= av[p] * x[ci[p]];
+  const double xi = x[i];
+  double t = b[i] - s[i] * xi;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    const int j = ci[p];
+    if (j != i) t += av[p] * (xi - x[j]);
+  }
   y[i] = t;
 }
 
@@ -446,8 +460,8 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   LAUNCH(h, "flux_block_local", k_block_local, g, kT, 0, n, h->fv_order.get(), h->primal.get(),
          h->fv_ptr.get(), local.get());
   LAUNCH(h, "flux_symbolic", k_fv_symbolic, nc, kT, 0, h->fv_ptr.get(), h->fv_order.get(),
-         h->rp.get(), h->ci.get(), h->primal.get(), local.get(), s.get(), dmax.get(), band.get(),
-         singular.get());
+         h->rp.get(), h->ci.get(), h->val.get(), h->primal.get(), local.get(), s.get(),
+         band.get(), singular.get());
   std::vector<int> hb(nc), hp(nc + 1);
   HIPX(hipMemcpyAsync(hb.data(), band.get(), nc * sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipMemcpyAsync(hp.data(), h->fv_ptr.get(), (nc + 1) * sizeof(int), hipMemcpyDeviceToHost,
@@ -457,8 +471,8 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
   // ---- FV stage ----
   DBuf<double> r(A, n), rc(A, nc), x(A, nc), t(A, nc), t2(A, nc), p1(A, n), p2(A, n), xs(A, n),
       rs(A, 2 * static_cast<size_t>(n));
-  LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(), p, q,
-         r.get());
+  LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(), s.get(),
+         p, q, r.get());
   LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
          h->fv_order.get(), r.get(), rc.get());
   auto fv_solve = [&](const double* in, double* out) {
@@ -474,7 +488,7 @@ double reconstruct_flux(Handle* h, const double* q, const double* p, double* flu
     LAUNCH(h, "flux_prolong", k_prolong_add, g, kT, 0, n, h->p_rp.get(), h->p_ci.get(),
            h->p_val.get(), x.get(), p, p1.get());
     LAUNCH(h, "flux_resid", k_resid_f, g, kT, 0, n, h->rp.get(), h->ci.get(), h->val.get(),
-           p1.get(), q, r.get());
+           s.get(), p1.get(), q, r.get());
     LAUNCH(h, "flux_restrict", k_block_sum, blocks_for(nc, kT), kT, 0, nc, h->fv_ptr.get(),
            h->fv_order.get(), r.get(), t.get());
     if (it >= kFvRefine) {  // keep refining only while the block defects still halve

@@ -384,3 +384,25 @@ def test_update_kept_basis(name, variant):
     assert abs(info[0]["iterations"] - oi["iterations"]) <= 1
     assert np.linalg.norm(p.cpu().numpy() - pr) <= 1e-8 * np.linalg.norm(pr)
     g.close()
+
+
+def test_flux_weakly_coupled_boundary():
+    """Low-permeability Dirichlet cells beside fractures 1e7 times more
+    conductive: their blocks have real (tiny) row sums and are not pinned,
+    on the GPU as in the oracle (whose reading is pinned in
+    test_oracle_solve.py): the balance stays at FP64's floor for the case
+    and the FV pressure matches the oracle's."""
+    from oracle import flux as oflux
+    from paper_1705_05784_amd import fams
+    from tests.test_oracle_solve import _weak_boundary_case
+    s, spec = _weak_boundary_case()
+    wb, pr, vx, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    say("[case] weak boundary, contrast 1e7")
+    gpu = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=3, alpha=1e-2)
+    ora = ofams.FAMS(s.csr(), wb, vx, s.n_matrix, 3, 1e-2)
+    p, _ = gpu.solve(torch.from_numpy(s.q), rtol=1e-4)
+    fl, pfv, imb = gpu.reconstruct_flux(torch.from_numpy(s.q), p)
+    _, p1, _, imr = oflux.reconstruct_flux(ora.A, ora.P, pr, vx, s.q, p.cpu().numpy())
+    assert imb <= 1e-8 and imr <= 1e-8
+    assert np.abs(pfv.cpu().numpy() - p1).max() <= 1e-9 * np.abs(p1).max()
+    gpu.close()

@@ -152,3 +152,41 @@ def test_solution_independent_of_strategy(name):
     ref = sols[0]
     for p in sols[1:]:
         assert np.linalg.norm(p - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def _weak_boundary_case():
+    """Low-permeability cells (k = 1e-3) on half of the x = 0 Dirichlet face
+    beside fractures 1e7 times more conductive than the matrix: their row
+    sums are real, but below 1e-10 of the largest diagonal of A."""
+    from tests._cases import SMALL
+    from workloads import make_small
+
+    def hook(lnk):
+        lnk = lnk.copy()
+        lnk[:, :7, :1] = np.log(1e-3)
+        return lnk
+    return make_small("3d", contrast=1e7, lnk_hook=hook), SMALL["3d"]
+
+
+def test_flux_balances_weakly_coupled_boundary_cells(monkeypatch):
+    """A block counts as pure Neumann (pinned at its coarse node) only when
+    none of its rows has a real row sum, judged against the row's own
+    couplings.  Judged against the largest diagonal of A instead (planted
+    here), the weakly coupled boundary blocks are pinned and their coarse
+    nodes keep s_i (p''_i - p'_i) unbalanced: the imbalance grows about
+    sixty-fold.  (The remaining ~5e-9 is FP64's floor for this case: pressures
+    equal to nine digits across fracture couplings of 1e6.)"""
+    s, spec = _weak_boundary_case()
+    A = s.csr()
+    s_row = np.asarray(A.sum(axis=1)).ravel()
+    weak = flux.dirichlet_rows(A) & (s_row <= 1e-10 * A.diagonal().max())
+    assert weak.sum() > 0                                  # the case bites
+    wb, primal, vertex, _ = grids.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    F = fams.FAMS(A, wb, vertex, s.n_matrix, fams.COUPLED, 1e-2)
+    p, _ = F.gmres(s.q, rtol=1e-4)
+    _, _, _, imb = flux.reconstruct_flux(A, F.P, primal, vertex, s.q, p)
+    assert imb <= 1e-8
+    monkeypatch.setattr(flux, "dirichlet_rows",
+                        lambda M: np.asarray(M.sum(axis=1)).ravel() > 1e-10 * M.diagonal().max())
+    _, _, _, imb_planted = flux.reconstruct_flux(A, F.P, primal, vertex, s.q, p)
+    assert imb_planted >= 20 * imb and imb_planted >= 1e-7

@@ -62,6 +62,8 @@ def make_small(kind: str, seed: int = 0, **kw):
     if kind == "3d":
         nx, ny, nz = kw.get("nx", 16), kw.get("ny", 14), kw.get("nz", 12)
         lnk = lnk_field((nz, ny, nx), kw.get("std", 1.5), (2, 3, 3), rng)
+        if "lnk_hook" in kw:    # tests: edit the field (same geometry and seeds)
+            lnk = kw["lnk_hook"](lnk)
         plates = random_plates_3d(rng, kw.get("n_frac", 5), nx, ny, nz,
                                   kw.get("len3d", (6, 12)), kw.get("h3d", (4, 9)))
         return build_system(nx, ny, nz, lnk, plates, kw.get("contrast", 1e3),
