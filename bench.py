@@ -275,6 +275,7 @@ def headline(args, dev):
                     cell_iterations_per_s=sysm.n * sum(its) / solve_s,
                     max_rel_residual=max(x for r in res for x in r["resid"]),
                     fp32_fallback_blocks=int(res[-1]["setup_info"]["fp32_fallback_blocks"]),
+                    long_waits=int(sum(r["setup_info"]["long_waits"] for r in res)),
                     steps=k, setup_info=res[-1]["setup_info"])
 
     say(f"config 5: mixed, {args.warmup} warm-up + {args.steps} timed steps")
@@ -437,6 +438,12 @@ def leg_config2(args, dev):
                          setup_ms_mean=float(np.mean([r["setup"] for r in rs]) * 1e3),
                          solve_ms_mean=float(np.mean([r["solve"] for r in rs]) * 1e3),
                          flux_ms_mean=float(np.mean([r["flux"] for r in rs]) * 1e3),
+                         slowest_request_ms={
+                             "setup": float(max(r["setup"] for r in rs) * 1e3),
+                             "solve": float(max(r["solve"] for r in rs) * 1e3),
+                             "flux": float(max(r["flux"] for r in rs) * 1e3),
+                             "total": float(max(r["total"] for r in rs) * 1e3)},
+                         long_waits=int(sum(r["si"]["long_waits"] for r in rs)),
                          iterations={VARIANT_NAMES[i]: rs[i]["info"]["iterations"]
                                      for i in range(4)},
                          max_flux_imbalance=max(r["imbalance"] for r in rs),

@@ -186,6 +186,12 @@ typedef struct {
                                  the wavefront solver, all levels */
   int64_t peak_device_bytes;  /* most device memory the handle has held at once
                                  (setup, solves and flux reconstructions so far) */
+  int64_t long_waits;         /* dependency waits of the dataflow ILU(0) sweeps and
+                                 LU solves that lasted over ~1 ms, all solves so far
+                                 (waits that long mean the workgroups holding the
+                                 dependencies were not running, e.g. another
+                                 process's work on the device; a wait gives up at
+                                 2 s with FAMS_ERR_DEVICE) */
 } fams_setup_info_t;
 
 /* ---- lifecycle -------------------------------------------------------- */

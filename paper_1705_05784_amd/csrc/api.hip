@@ -8,7 +8,9 @@
 #include <functional>
 #include <initializer_list>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -183,10 +185,19 @@ int64_t lds_hw_budget(Handle* h) {
   return h->lds_hw_bytes;
 }
 
+// The dynamic-LDS limit is process-wide state of the kernel: it is only ever
+// raised, under a lock, so that one handle's setting can never lower the
+// limit under another thread's launch of the same kernel.
 void allow_lds(const void* kernel, size_t bytes) {
-  if (bytes > 65536)
-    HIPX(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(bytes)));
+  if (bytes <= 65536) return;
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> limit;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = limit[kernel];
+  if (bytes <= cur) return;
+  HIPX(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           static_cast<int>(bytes)));
+  cur = bytes;
 }
 
 namespace {

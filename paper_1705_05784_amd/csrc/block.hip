@@ -1310,7 +1310,7 @@ void solve_group(Handle* h, const double* q, double* p, int nr, const fams_solve
   const int n = h->n;
   const int64_t nk = k.nk;
   for (Handle* g : {h, h->blk.get()})
-    if (g && g->sweep_err.get()) HIPX(hipMemsetAsync(g->sweep_err, 0, sizeof(int), h->stream));
+    if (g && g->sweep_err.get()) HIPX(hipMemsetAsync(g->sweep_err, 0, 2 * sizeof(int), h->stream));
   auto t0 = std::chrono::steady_clock::now();
   LAUNCH(h, "bpack", k_pack<K>, blocks_for(n, kPackRows), kT, 0, n, nr, q, k.q);
   if (o->use_initial_guess)
@@ -1326,10 +1326,11 @@ void solve_group(Handle* h, const double* q, double* p, int nr, const fams_solve
   int e = 0;
   for (Handle* g : {h, h->blk.get()}) {
     if (!g || !g->sweep_err.get()) continue;
-    int eg = 0;
-    HIPX(hipMemcpyAsync(&eg, g->sweep_err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    int eg[2] = {};
+    HIPX(hipMemcpyAsync(eg, g->sweep_err.get(), sizeof(eg), hipMemcpyDeviceToHost, h->stream));
     HIPX(hipStreamSynchronize(h->stream));
-    e |= eg;
+    e |= eg[0];
+    h->info.long_waits += eg[1];
   }
   FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "ILU(0) sweep: a dependency wait exceeded its bound");
   const double ms =

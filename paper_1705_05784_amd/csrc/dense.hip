@@ -868,10 +868,16 @@ __global__ void k_gather_perm(int n, const int* perm, const double* b, double* w
 template <bool kUpper>
 __global__ void __launch_bounds__(64)
 k_lu_df(int n, const double* lu, const double* w, double* x, int* flag, int epoch, int* err,
-        unsigned long long limit) {
+        int* ticket, unsigned long long limit) {
   const int lane = threadIdx.x;
   const int nch = (n + kLuB - 1) / kLuB;
-  const int ci = kUpper ? nch - 1 - static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x);
+  // chunks by ticket in solve order: every chunk this one waits for has been
+  // taken by a workgroup already running, whatever order the hardware
+  // dispatches the workgroups in
+  __shared__ int s_t;
+  if (lane == 0) s_t = atomicAdd(ticket, 1);
+  __syncthreads();
+  const int ci = kUpper ? nch - 1 - s_t : s_t;
   const int r0 = ci * kLuB, nbk = min(kLuB, n - r0), r = r0 + lane;
   const bool own = lane < nbk;
   double v = own ? w[r] : 0.0;
@@ -880,7 +886,11 @@ k_lu_df(int n, const double* lu, const double* w, double* x, int* flag, int epoc
     while (true) {
       int f = __hip_atomic_load(flag + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
       f = __builtin_amdgcn_readfirstlane(f);
-      if (f == epoch) break;
+      if (f == epoch) {
+        // waits beyond ~1 ms (limit / 2048) are counted in err[3]
+        if (lane == 0 && wall_clock64() - t0 > (limit >> 11)) atomicAdd(err + 3, 1);
+        break;
+      }
       int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       e = __builtin_amdgcn_readfirstlane(e);
       if (e != 0) break;
@@ -1192,20 +1202,25 @@ void lu_solve(Handle* h, const double* lu, const int* perm, int n, const double*
     h->lu_flag_n = 2 * nch;
     h->lu_epoch = 0;
   }
-  if (!h->lu_err.get()) h->lu_err.reset(&h->alloc, 1);
-  HIPX(hipMemsetAsync(h->lu_err, 0, sizeof(int), h->stream));
+  if (!h->lu_err.get()) {   // error word, two tickets, long waits
+    h->lu_err.reset(&h->alloc, 4);
+    HIPX(hipMemsetAsync(h->lu_err, 0, 4 * sizeof(int), h->stream));
+  }
+  HIPX(hipMemsetAsync(h->lu_err, 0, 3 * sizeof(int), h->stream));
   const int epoch = ++h->lu_epoch;
   const unsigned long long limit = wait_limit(h);
   DBuf<double> w1(&h->alloc, n), w2(&h->alloc, n);
   LAUNCH(h, "lu_solve", k_gather_perm, blocks_for(n, 256), 256, 0, n, perm, b, w1.get());
   LAUNCH(h, "lu_solve", k_lu_df<false>, nch, 64, 0, n, lu, static_cast<const double*>(w1.get()),
-         w2.get(), h->lu_flags.get(), epoch, h->lu_err.get(), limit);
+         w2.get(), h->lu_flags.get(), epoch, h->lu_err.get(), h->lu_err.get() + 1, limit);
   LAUNCH(h, "lu_solve", k_lu_df<true>, nch, 64, 0, n, lu, static_cast<const double*>(w2.get()), x,
-         h->lu_flags.get() + nch, epoch, h->lu_err.get(), limit);
-  int e = 0;
-  HIPX(hipMemcpyAsync(&e, h->lu_err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+         h->lu_flags.get() + nch, epoch, h->lu_err.get(), h->lu_err.get() + 2, limit);
+  int e[4] = {};
+  HIPX(hipMemcpyAsync(e, h->lu_err.get(), sizeof(e), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
-  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "LU solve: a dependency wait exceeded its bound");
+  h->info.long_waits += e[3];
+  HIPX(hipMemsetAsync(h->lu_err.get() + 3, 0, sizeof(int), h->stream));
+  FAMS_REQUIRE(e[0] == 0, FAMS_ERR_DEVICE, "LU solve: a dependency wait exceeded its bound");
 }
 
 // part: [ceil(nc / 64) * nc] partial sums

@@ -202,7 +202,10 @@ __device__ __forceinline__ typename Sentinel<T>::U load_raw(const T* p) {
 // Wait until *p is published, given a first read u of it.  Polls back off up
 // to ~0.4 us; the wait gives up after `limit` wall-clock ticks, or at once
 // when another wait has given up (err != 0), so a broken dependency order
-// ends the kernel quickly.
+// ends the kernel quickly.  A wait that ends after more than limit / 2048
+// ticks (about 1 ms) is counted in err[1]: waits that long mean the
+// workgroups holding the dependencies were not running (another process's
+// work on the device), the first sign before a wait runs out.
 template <class T>
 __device__ __forceinline__ T wait_ready(const T* p, typename Sentinel<T>::U u, int* err,
                                         unsigned long long limit) {
@@ -215,7 +218,10 @@ __device__ __forceinline__ T wait_ready(const T* p, typename Sentinel<T>::U u, i
       for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
       backoff = backoff < 16 ? 2 * backoff : 16;
       u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (u != Sentinel<T>::bits) break;
+      if (u != Sentinel<T>::bits) {
+        if (wall_clock64() - t0 > (limit >> 11)) atomicAdd(err + 1, 1);
+        break;
+      }
       if (wall_clock64() - t0 > limit ||
           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         atomicOr(err, 2);
@@ -977,8 +983,8 @@ void build_ilu(Handle* h) {
   // sweep-order input and the factor values in the schedules' ELL form
   if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
-    h->sweep_err.reset(&h->alloc, 1);
-    HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
+    h->sweep_err.reset(&h->alloc, 2);   // error bits, long waits
+    HIPX(hipMemsetAsync(h->sweep_err, 0, 2 * sizeof(int), h->stream));
   }
   if (h->rng_lo.nranges > 0) {
     if (h->precision == FAMS_PREC_MIXED) {
@@ -1070,8 +1076,8 @@ template <class T>
 void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y) {
   if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
-    h->sweep_err.reset(&h->alloc, 1);
-    HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
+    h->sweep_err.reset(&h->alloc, 2);   // error bits, long waits
+    HIPX(hipMemsetAsync(h->sweep_err, 0, 2 * sizeof(int), h->stream));
   }
   HIPX(hipMemsetAsync(h->ilu_ticket, 0, 2 * sizeof(int), h->stream));
   const int n = h->n;
@@ -1230,8 +1236,8 @@ template <class T, int K>
 void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
   if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
-    h->sweep_err.reset(&h->alloc, 1);
-    HIPX(hipMemsetAsync(h->sweep_err, 0, sizeof(int), h->stream));
+    h->sweep_err.reset(&h->alloc, 2);   // error bits, long waits
+    HIPX(hipMemsetAsync(h->sweep_err, 0, 2 * sizeof(int), h->stream));
   }
   block_chunk_table(h, &h->lvl_lo);
   block_chunk_table(h, &h->lvl_up);

@@ -459,10 +459,12 @@ fams_status_t gmres(Handle* h, const Work& k, const double* q, double* p,
 // a bounded wait that gave up means the sweep's dependency order was broken
 void check_sweeps(Handle* h) {
   if (!h->sweep_err.get()) return;
-  int e = 0;
-  HIPX(hipMemcpyAsync(&e, h->sweep_err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  int e[2] = {};
+  HIPX(hipMemcpyAsync(e, h->sweep_err.get(), sizeof(e), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
-  FAMS_REQUIRE(e == 0, FAMS_ERR_DEVICE, "ILU(0) sweep: a dependency wait exceeded its bound");
+  h->info.long_waits += e[1];
+  HIPX(hipMemsetAsync(h->sweep_err.get() + 1, 0, sizeof(int), h->stream));
+  FAMS_REQUIRE(e[0] == 0, FAMS_ERR_DEVICE, "ILU(0) sweep: a dependency wait exceeded its bound");
 }
 
 }  // namespace

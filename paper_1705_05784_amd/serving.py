@@ -43,6 +43,7 @@ class ServedResult:
     t_admit: float = 0.0
     t_done: float = 0.0
     setup_ms: float = 0.0
+    long_waits: int = 0     # dependency waits over ~1 ms in the request's sweeps/LU solves
     slot: int = -1
 
     @property
@@ -108,6 +109,7 @@ def _execute(system, grid, variant, rhs, precision, alpha, rtol, restart, flux, 
         if keep:
             out["pressures"] = P.cpu().numpy()
         torch.cuda.current_stream().synchronize()
+        out["long_waits"] = int(solver.setup_info()["long_waits"])
     finally:
         solver.close()
     return out
@@ -126,6 +128,7 @@ def _fill(res: ServedResult, out: dict):
     res.imbalance = out["imbalance"]
     res.pressures = out["pressures"]
     res.setup_ms = out["setup_ms"]
+    res.long_waits = out.get("long_waits", 0)
 
 
 class GpuRunner:
@@ -419,6 +422,9 @@ def _main(argv=None):
                precision="fp64" if a.fp64 else "mixed",
                peak_inflight=srv.peak_inflight, peak_reserved_gb=srv.peak_reserved / 2**30,
                mean_setup_ms=float(np.mean([r.setup_ms for r in res if r.status >= 0])),
+               max_setup_ms=float(max(r.setup_ms for r in res if r.status >= 0)),
+               max_latency_s=float(max(r.latency for r in res if r.status >= 0)),
+               long_waits=int(sum(r.long_waits for r in res)),
                mean_iterations=float(np.mean([np.mean(r.iterations) for r in res if r.iterations])),
                cells_range=[min(cells.values()), max(cells.values())])
     print(json.dumps(out))
