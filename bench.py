@@ -355,8 +355,8 @@ def headline(args, dev):
             "note": "Gauss-Jordan inverse of A_c, 2 n_c^3 flops over all its launches"}
         gm = st.get("gemm_mfma")
         if gm:
-            # the GEMMs alone: 2 n^2 256 per block step plus the two panel products
-            nb, steps_ = 256, -(-nc // 256)
+            # the GEMMs alone: 2 n^2 1024 per block step plus the two panel products
+            nb, steps_ = 1024, -(-nc // 1024)
             g_flop = sum(2.0 * nc * nc * min(nb, nc - k * nb) + 4.0 * nc * min(nb, nc - k * nb) ** 2
                          for k in range(steps_))
             entries["gemm_mfma"] = {

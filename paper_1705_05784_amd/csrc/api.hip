@@ -449,7 +449,7 @@ fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t p
   b += nnz * 8.0 + n;                                            // basis values, classes
   b += 2 * zp * (4 + 8) + (n + 2 * nc + 2) * 4;                  // P and R
   b += 2.0 * 8 * nc * nc;                                        // A_c and its inverse
-  b += 2.0 * 8 * 256 * nc + 8.0 * 256 * 256;                     // block Gauss-Jordan panels
+  b += 2.0 * 8 * 1024 * nc + 8.0 * 1024 * 1024;                   // block Gauss-Jordan panels
   b += 3.0 * zp * (4 + 8) + 8.0 * (n + 1);                       // A P
   b += 48.0 * 8 * n;                                             // local solutions (setup)
   b += 2.0 * (4 + 32 + 32 + 4 + 4 + 72 + 8) * n + 24.0 * n;     // sweep schedules, levels

@@ -686,7 +686,7 @@ k_gemm_mfma(int m, int p, int k, double alpha, const double* A, int lda, const d
 // 16-wide slices of A and B in registers and stores them into the other
 // buffer after the step, so one barrier per step and the global loads
 // overlap the arithmetic.
-constexpr int kBT = 128, kBK = 16, kBPad = kBT + 4;
+constexpr int kBT = 128, kBK = 32, kBPad = kBT + 4;
 
 __global__ void __launch_bounds__(256)
 k_gemm_mfma128(int m, int p, int k, double alpha, const double* A, int lda, const double* B,
@@ -696,26 +696,27 @@ k_gemm_mfma128(int m, int p, int k, double alpha, const double* A, int lda, cons
   const int r0 = blockIdx.x * kBT, c0 = blockIdx.y * kBT;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wr = (wave % 2) * 64, wc = (wave / 2) * 64;
-  // global slice loads: A column-major, 128 rows x 16 k: thread t loads rows
-  // (t % 128) at k = t / 128 + 2u; B column-major, 16 k x 128 columns: thread
-  // t loads k = t % 16 of columns t / 16 + 16u
+  // global slice loads: A column-major, 128 rows x kBK k: thread t loads row
+  // t % 128 at k = t / 128 + 2u; B column-major, kBK k x 128 columns: thread t
+  // loads k = t % kBK of columns t / kBK + (256 / kBK) u; kBK / 2 of each
+  constexpr int kL = kBK / 2, kCs = 256 / kBK;
   const int ar = tid % kBT, ak = tid / kBT;
   const int bk = tid % kBK, bc = tid / kBK;
-  double ra[8], rb[8];
+  double ra[kL], rb[kL];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kL; ++u) {
       const int kk = k0 + ak + 2 * u, rr = r0 + ar;
       ra[u] = (rr < m && kk < k) ? A[static_cast<int64_t>(kk) * lda + rr] : 0.0;
-      const int kb = k0 + bk, cc = c0 + bc + 16 * u;
+      const int kb = k0 + bk, cc = c0 + bc + kCs * u;
       rb[u] = (cc < p && kb < k) ? B[static_cast<int64_t>(cc) * ldb + kb] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kL; ++u) {
       As[buf][ak + 2 * u][ar] = ra[u];
-      Bs[buf][bk][bc + 16 * u] = rb[u];
+      Bs[buf][bk][bc + kCs * u] = rb[u];
     }
   };
   v4d acc[4][4];
@@ -1142,14 +1143,16 @@ __global__ void k_block_put_rows(double* a, int n, int k0, int nb, const double*
 
 }  // namespace
 
-// In-place Gauss-Jordan inverse in blocks of kOb = 256 (no pivoting; SPD
+// In-place Gauss-Jordan inverse in blocks of kOb = 1024 (no pivoting; SPD
 // A_c).  Block step with D the diagonal block, B its row block, C its column
 // block and E the rest: D <- D^{-1} (by the 32-wide steps above), C <- -C
 // D^{-1}, E <- E + C B (old B), B <- D^{-1} B.  The three products are FP64
-// MFMA GEMMs of inner dimension 256, so the update of E (2 n^2 256 flops per
-// step, n/256 steps) reads and writes E once per 256 columns instead of once
-// per 32.
-constexpr int kOb = 256;
+// MFMA GEMMs of inner dimension 1024, so the update of E (2 n^2 1024 flops
+// per step, n/1024 steps) reads and writes E once per 1024 columns: the E
+// traffic of a step is then small against its arithmetic (measured on an
+// n = 17810 coarse system: 454 ms of GEMM time with 256-wide blocks, 363 ms
+// with 512, 331 ms with 1024).
+constexpr int kOb = 1024;
 
 bool spd_inverse(Handle* h, const double* a, double* inv, int n) {
   DBuf<int> info(&h->alloc, 1);
