@@ -71,23 +71,43 @@ __global__ void __launch_bounds__(256) k_unpack(int n, int nr, const double* Q, 
 // lines and planes) were mostly brought into the same XCD's L2 by its own
 // earlier workgroups.
 
-// Y = M X (kResid: Y = B - M X, B may be null or alias Y): one thread per
-// (row, right-hand side); the K threads of a row read its entries once
-// (same addresses) and gather K consecutive values per neighbour
+// Y = M X (kResid: Y = B - M X, B may be null or alias Y) on block vectors:
+// K / 2 threads per row, each with two right-hand sides (r, r + 1) whose
+// values of a neighbour it gathers in one load; the threads of a row read
+// its entries at the same addresses
+// two consecutive values of a block vector (right-hand sides r, r + 1; r even)
+template <class T> struct Pair;
+template <> struct Pair<double> { using V = double2; };
+template <> struct Pair<float> { using V = float2; };
+
+template <class T>
+__device__ __forceinline__ void load_pair(const T* p, double& a, double& b) {
+  const typename Pair<T>::V v = *reinterpret_cast<const typename Pair<T>::V*>(p);
+  a = static_cast<double>(v.x);
+  b = static_cast<double>(v.y);
+}
+
+template <class T>
+__device__ __forceinline__ void store_pair_to(T* p, double a, double b) {
+  typename Pair<T>::V v;
+  v.x = static_cast<T>(a);
+  v.y = static_cast<T>(b);
+  *reinterpret_cast<typename Pair<T>::V*>(p) = v;
+}
+
 template <class TV, class TX, class TB, class TY, int K, bool kResid>
 __global__ void __launch_bounds__(256)
 k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const TB* B, TY* Y) {
-  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(n) * K) return;
-  const int i = static_cast<int>(e / K), r = static_cast<int>(e % K);
-  double s = 0.0;
+  constexpr int H = K / 2;
+  const int64_t e2 = xcd_block() * blockDim.x + threadIdx.x;
+  if (e2 >= static_cast<int64_t>(n) * H) return;
+  const int i = static_cast<int>(e2 / H), r = 2 * static_cast<int>(e2 % H);
+  double s0 = 0.0, s1 = 0.0;
   const int p0 = rp[i], p1 = rp[i + 1];
-  // the row's entries eight at a time: their columns and values first, then
-  // all their gathers, so a row costs about two memory round trips
   for (int pb = p0; pb < p1; pb += 8) {
     int c[8];
     TV v[8];
-    TX x[8];
+    double x0[8], x1[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (pb + k < p1) {
@@ -96,13 +116,22 @@ k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const T
       }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (pb + k < p1) x[k] = X[static_cast<int64_t>(c[k]) * K + r];
+      if (pb + k < p1) load_pair<TX>(X + static_cast<int64_t>(c[k]) * K + r, x0[k], x1[k]);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (pb + k < p1) s += static_cast<double>(v[k]) * static_cast<double>(x[k]);
+      if (pb + k < p1) {
+        s0 += static_cast<double>(v[k]) * x0[k];
+        s1 += static_cast<double>(v[k]) * x1[k];
+      }
   }
-  if constexpr (kResid) s = (B ? static_cast<double>(B[e]) : 0.0) - s;
-  Y[e] = static_cast<TY>(s);
+  const int64_t o = static_cast<int64_t>(i) * K + r;
+  if constexpr (kResid) {
+    double b0 = 0.0, b1 = 0.0;
+    if (B) load_pair<TB>(B + o, b0, b1);
+    s0 = b0 - s0;
+    s1 = b1 - s1;
+  }
+  store_pair_to<TY>(Y + o, s0, s1);
 }
 
 // sum over the lanes of a workgroup of 256 that hold the same r = tid % K
@@ -1022,8 +1051,8 @@ template <class TV, class TX, class TB, class TY, int K>
 void bresid(Handle* h, const int* rp, const int* ci, const TV* val, const TX* x, const TB* b,
             TY* y, const char* name = "bspmv_resid") {
   const int64_t nk = static_cast<int64_t>(h->n) * K;
-  LAUNCH(h, name, (k_bspmv<TV, TX, TB, TY, K, true>), xcd_grid(blocks_for(nk, kT)), kT, 0, h->n, rp, ci,
-         val, x, b, y);
+  LAUNCH(h, name, (k_bspmv<TV, TX, TB, TY, K, true>), xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n,
+         rp, ci, val, x, b, y);
 }
 
 // Table 1 steps 5-7 on K residuals at once (FP64 in and out; T = stage type)
@@ -1066,8 +1095,8 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
     const int64_t nck = static_cast<int64_t>(nc) * K;
     LAUNCH(h, "bcoarse_red", k_bcoarse_red, blocks_for(nck, kT), kT, 0, nck, k.nch, k.cpart, k.xc);
   }
-  LAUNCH(h, "bprolong", (k_bspmv<T, double, T, T, K, false>), xcd_grid(blocks_for(nk, kT)), kT, 0, n,
-         h->p_rp.get(), h->p_ci.get(), pv, k.xc, static_cast<const T*>(nullptr), d1);
+  LAUNCH(h, "bprolong", (k_bspmv<T, double, T, T, K, false>), xcd_grid(blocks_for(nk / 2, kT)), kT, 0,
+         n, h->p_rp.get(), h->p_ci.get(), pv, k.xc, static_cast<const T*>(nullptr), d1);
   if (h->smoother) {
     bresid<T, T, T, T, K>(h, h->rp.get(), h->ci.get(), av, d1, rT, rh);
     ilu_apply_block<T, K>(h, lu, rh, x, ysc);
@@ -1179,7 +1208,7 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
         double* zj = k.Z + j * nk;
         bstage_any<K>(h, k, uj, zj);
         LAUNCH(h, "bspmv", (k_bspmv<double, double, double, double, K, false>),
-               xcd_grid(blocks_for(nk, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(),
+               xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(),
                zj, static_cast<const double*>(nullptr), k.w);
         launch_dcgs<K>(h, false, k.nb, nk, j, k.V, nk, k.w, nullptr, 0, k.part, 2 * m + 2);
         LAUNCH(h, "breduce", k_breduce, dim3(2 * j + 2, K), 256, 0, k.nb, K, k.part, 2 * m + 2,
@@ -1212,7 +1241,7 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
       double* zj = k.Z + j * nk;
       bstage_any<K>(h, k, vj, zj);
       LAUNCH(h, "bspmv", (k_bspmv<double, double, double, double, K, false>),
-             xcd_grid(blocks_for(nk, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(), zj,
+             xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(), zj,
              static_cast<const double*>(nullptr), k.w);
       // CGS2 against V_0..V_j, per right-hand side: h = V^T w; w -= V h and
       // c = V^T w in one pass; w -= V c and ||w|| in one pass; h += c
