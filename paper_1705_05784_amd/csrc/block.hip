@@ -151,21 +151,40 @@ __device__ double group_sum(double v) {
   return t;
 }
 
+// sum over the lanes of a workgroup of 256 that share tid % (K/2), i.e. the
+// same pair (2l, 2l + 1) of right-hand sides in the two-element kernels
+// below; valid in threads 0 .. K/2 - 1
+template <int K>
+__device__ double pair_sum(double v) {
+  constexpr int H = K / 2;
+  __shared__ double s[4][H];
+  for (int o = 32; o >= H; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l < H) s[w][l] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < H)
+    for (int q = 0; q < 4; ++q) t += s[q][threadIdx.x];
+  return t;
+}
+
 // Y[row * K + r] = sum_p M[row, p] X[col_p * K + r] for the fat rows of R =
-// P^T: one workgroup per row, 256 / K groups of K lanes stride over the
-// row's entries, then a fixed-order sum across the groups
+// P^T: one workgroup per row, 512 / K groups of K / 2 lanes (two right-hand
+// sides each) stride over the row's entries, then a fixed-order sum across
+// the groups
 template <class TV, class TX, int K>
 __global__ void __launch_bounds__(256)
 k_brestrict(int nrows, const int* rp, const int* ci, const TV* val, const TX* X, double* Y) {
+  constexpr int H = K / 2, G = 256 / H;
   const int row = blockIdx.x;
-  const int r = threadIdx.x % K, g = threadIdx.x / K;
-  constexpr int G = 256 / K;
-  double s = 0.0;
+  const int r = 2 * (threadIdx.x % H), g = threadIdx.x / H;
+  double s0 = 0.0, s1 = 0.0;
   const int p1 = rp[row + 1];
   for (int pb = rp[row] + g; pb < p1; pb += 4 * G) {
     int c[4];
     TV v[4];
-    TX x[4];
+    double x0[4], x1[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (pb + k * G < p1) {
@@ -174,13 +193,20 @@ k_brestrict(int nrows, const int* rp, const int* ci, const TV* val, const TX* X,
       }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (pb + k * G < p1) x[k] = X[static_cast<int64_t>(c[k]) * K + r];
+      if (pb + k * G < p1) load_pair<TX>(X + static_cast<int64_t>(c[k]) * K + r, x0[k], x1[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (pb + k * G < p1) s += static_cast<double>(v[k]) * static_cast<double>(x[k]);
+      if (pb + k * G < p1) {
+        s0 += static_cast<double>(v[k]) * x0[k];
+        s1 += static_cast<double>(v[k]) * x1[k];
+      }
   }
-  s = group_sum<K>(s);
-  if (threadIdx.x < K) Y[static_cast<int64_t>(row) * K + threadIdx.x] = s;
+  s0 = pair_sum<K>(s0);
+  s1 = pair_sum<K>(s1);
+  if (threadIdx.x < H) {
+    Y[static_cast<int64_t>(row) * K + 2 * threadIdx.x] = s0;
+    Y[static_cast<int64_t>(row) * K + 2 * threadIdx.x + 1] = s1;
+  }
 }
 
 // coarse solve X = A_c^{-1} Y with the dense inverse (column-major nc x nc):
@@ -255,23 +281,6 @@ __device__ void store_dots(const double* acc, int nb, int v0, double* part, int 
   }
 }
 
-// sum over the lanes of a workgroup of 256 that share tid % (K/2), i.e. the
-// same pair (2l, 2l + 1) of right-hand sides in the two-element kernels
-// below; valid in threads 0 .. K/2 - 1
-template <int K>
-__device__ double pair_sum(double v) {
-  constexpr int H = K / 2;
-  __shared__ double s[4][H];
-  for (int o = 32; o >= H; o >>= 1) v += __shfl_down(v, o, 64);
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  __syncthreads();
-  if (l < H) s[w][l] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x < H)
-    for (int q = 0; q < 4; ++q) t += s[q][threadIdx.x];
-  return t;
-}
 
 // the streaming Krylov kernels take two consecutive entries per thread (one
 // 16-byte load per vector; K is even, so both entries are of one row and of
