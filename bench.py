@@ -10,7 +10,7 @@ coarsening 10x10x10 in the matrix and d_min = r_z = 10 in the fractures
 1e-2; 64 right-hand sides (the Dirichlet boundary term plus 2-8 zero-sum
 point sources each) reusing one setup, each solved by GMRES(30) with the
 F-AMS two-stage preconditioner (multiscale stage + ILU(0)) to a relative
-residual of 1e-6, in lock-step groups of 16.  The fine system is resident in
+residual of 1e-6, in lock-step groups of 32.  The fine system is resident in
 HBM before the clock starts.
 
 One step = setup (basis functions, R, A_c and its inverse, ILU(0)) + the 64
@@ -47,7 +47,7 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 RTOL = 1e-6
 ALPHA = 1e-2
 HEADLINE_NRHS = 64
-GROUP = 16
+GROUP = 32
 RESTART = 30
 VARIANT_NAMES = ["decoupled", "frac", "rock", "coupled"]
 # coarse grid of each workload: (cx, cy, cz), d_min, r_z
@@ -187,7 +187,8 @@ def load_system(config, dev, contrast=None):
 def solver(sysm, A, variant, precision, profile=False):
     from paper_1705_05784_amd import fams
     return fams.Solver(A["row_ptr"], A["col"], A["val"], sysm.n_matrix, A["wb"], A["pr"], A["vx"],
-                       variant=variant, precision=precision, alpha=ALPHA, profile=profile)
+                       variant=variant, precision=precision, alpha=ALPHA, profile=profile,
+                       allocator="torch")
 
 
 PREF_DIR = os.path.join(ROOT, "oracle", "_pref")
@@ -378,7 +379,7 @@ def headline(args, dev):
                                   sorted(st.items(), key=lambda kv: -kv[1][0])[:16]}}
     cfg = {"workload": ("EDFM 3D 256x256x128 + 2000 plates (contrast 1e6, ln k std 4), "
                         "Coupled-AMS, coarsening 10^3 / d_min=r_z=10, alpha 1e-2, 64 right-hand "
-                        "sides per setup in lock-step groups of 16, FGMRES(30) to 1e-6; "
+                        "sides per setup in lock-step groups of 32, FGMRES(30) to 1e-6; "
                         "step = setup + 64 solves"),
            "n": int(sysm.n), "n_matrix": int(sysm.n_matrix), "nnz": int(sysm.nnz),
            "n_coarse": int(m_si["n_coarse"]), "nnz_P": int(m_si["nnz_P"]),

@@ -123,7 +123,16 @@ typedef struct {
 } fams_grid_t;
 
 /* Optional device-memory hook (e.g. a framework's caching allocator).  NULL
- * in fams_setup = hipMalloc/hipFree. */
+ * in fams_setup = hipMallocAsync/hipFreeAsync on the handle's stream.  Every
+ * device buffer of the handle comes from `alloc` (called with the handle's
+ * stream) and goes back through `free`, the last ones in fams_destroy; alloc
+ * returns NULL when it cannot serve the size (the call then fails with
+ * FAMS_ERR_OOM, except while fams_solve picks its lock-step group width).  A
+ * caching hook lets handles created one after another reuse memory instead of
+ * allocating it afresh (on MI355X a 140 GB lock-step work space allocated
+ * anew after an earlier handle released its memory cost ~4 s of host time on
+ * its first solve; taken from a cache, nothing).  The hook must stay valid
+ * until fams_destroy returns. */
 typedef struct {
   void* ctx;
   void* (*alloc)(void* ctx, size_t bytes, void* stream);
@@ -200,7 +209,7 @@ typedef struct {
  * through its setup and its solves (host-only estimate from sizes; used for
  * admission): `restart` sizes the GMRES work space and `max_nrhs` the
  * lock-step work space of fams_solve with several right-hand sides (groups of
- * up to 16).  Both smoother settings are covered.  Not covered: the flux
+ * up to 32).  Both smoother settings are covered.  Not covered: the flux
  * reconstruction's work space (two dense n_coarse^2 FP64 matrices and the
  * primal blocks' banded factors).  Errors: FAMS_ERR_INVALID_ARG for
  * non-positive sizes, restart or max_nrhs. */
@@ -231,8 +240,10 @@ fams_status_t fams_update_values(fams_handle_t h, const double* val, double thre
 
 /* Solve A p = q for nrhs right-hand sides (device, column-major [n x nrhs];
  * pageable host memory is refused with FAMS_ERR_INVALID_ARG).  Several
- * right-hand sides reuse the setup in lock-step groups of up to 16 (as many
- * as the free device memory holds): every pass over A, P, R, the ILU(0)
+ * right-hand sides reuse the setup in lock-step groups of up to 32 (as many
+ * as the free device memory holds, with 10% left to the caller; with an
+ * allocation hook, the widest group whose work space the hook grants, halving
+ * while it returns NULL): every pass over A, P, R, the ILU(0)
  * factors and A_c^{-1} serves the whole group, while each right-hand side
  * keeps its own outer iteration and stopping test (Sec. 4.6 reuses one setup
  * for a sequence of solves).  info (host, [nrhs], may be NULL).  Returns the

@@ -459,7 +459,7 @@ fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t p
   if (mixed) b += nnz * 8.0 + 2 * zp * 4 + 16.0 * n;
   if (max_nrhs > 1) {  // lock-step groups of K right-hand sides
     int K = 2;
-    while (K < 16 && K < max_nrhs) K *= 2;
+    while (K < 32 && K < max_nrhs) K *= 2;
     const double nk = static_cast<double>(n) * K;
     b += nk * 8 * (10 + 2 * restart + 1) + (mixed ? nk * 4 * 6 : 0.0);
     b += (2 + 34) * nc * K * 8 + 2048.0 * (2 * restart + 4) * K * 8;

@@ -713,7 +713,7 @@ __global__ void k_bgivens(int K, BState s, double* base, int j, unsigned mask) {
 }
 
 struct KK {
-  int v[16];
+  int v[32];
 };
 
 // y = H(0:k, 0:k)^{-1} g(0:k) with each right-hand side's own k; y beyond k
@@ -1037,19 +1037,32 @@ size_t block_bytes(Handle* h, int K, int m) {
   return b;
 }
 
-void ensure_block_workspace(Handle* h, int K, int m) {
-  if (h->bK == K && h->bm >= m && h->bwk.get()) return;
+void free_block_workspace(Handle* h) {
+  h->bK = 0;
   h->bwk.free();
   h->bwk32.free();
   h->bpart.free();
-  const size_t nk = static_cast<size_t>(h->n) * K;
-  h->bwk.reset(&h->alloc, block_vectors(m) * nk);
-  if (h->precision == FAMS_PREC_MIXED) h->bwk32.reset(&h->alloc, 6 * nk);
-  const int cw = coarse_chunk_width(h->nc);
-  const size_t nch = (h->nc + cw - 1) / cw;
-  h->bpart.reset(&h->alloc, (2 + nch) * static_cast<size_t>(h->nc) * K);
-  h->bred.reset(&h->alloc, static_cast<size_t>(kRedBlocks) * (2 * m + 4) * K + 16);
-  h->bsmall.reset(&h->alloc, static_cast<size_t>(BState::make(m).stride) * K + 16);
+  h->bred.free();
+  h->bsmall.free();
+}
+
+// all or nothing: a failed allocation leaves no work space (bK = 0)
+void ensure_block_workspace(Handle* h, int K, int m) {
+  if (h->bK == K && h->bm >= m && h->bwk.get()) return;
+  free_block_workspace(h);
+  try {
+    const size_t nk = static_cast<size_t>(h->n) * K;
+    h->bwk.reset(&h->alloc, block_vectors(m) * nk);
+    if (h->precision == FAMS_PREC_MIXED) h->bwk32.reset(&h->alloc, 6 * nk);
+    const int cw = coarse_chunk_width(h->nc);
+    const size_t nch = (h->nc + cw - 1) / cw;
+    h->bpart.reset(&h->alloc, (2 + nch) * static_cast<size_t>(h->nc) * K);
+    h->bred.reset(&h->alloc, static_cast<size_t>(kRedBlocks) * (2 * m + 4) * K + 16);
+    h->bsmall.reset(&h->alloc, static_cast<size_t>(BState::make(m).stride) * K + 16);
+  } catch (...) {
+    free_block_workspace(h);
+    throw;
+  }
   h->bK = K;
   h->bm = m;
 }
@@ -1386,15 +1399,33 @@ void solve_group(Handle* h, const double* q, double* p, int nr, const fams_solve
 fams_status_t solve_block(Handle* h, const double* q, double* p, int nrhs,
                           const fams_solve_opts_t* o, fams_info_t* info) {
   const int m = o->outer == FAMS_GMRES ? o->restart : 1;
-  // the widest group (up to 16 right-hand sides) whose work space fits in
-  // the free device memory with a margin
+  // the widest group (up to 32 right-hand sides, no wider than nrhs needs)
+  // whose work space fits in the device memory
+  int K = 32;
+  while (K > 2 && K / 2 >= nrhs) K /= 2;
   size_t free_b = 0, total_b = 0;
   HIPX(hipMemGetInfo(&free_b, &total_b));
-  const size_t held = h->bwk.get() ? block_bytes(h, h->bK, h->bm) : 0;
-  int K = 16;
-  while (K > 2 && (K / 2 >= nrhs || block_bytes(h, K, m) > (free_b + held) / 10 * 9)) K /= 2;
-  FAMS_REQUIRE(block_bytes(h, K, m) <= free_b + held, FAMS_ERR_OOM,
-               "no room for the lock-step work space of two right-hand sides");
+  if (!h->alloc.has_hook) {
+    // the free device memory, with a margin for the caller
+    const size_t held = h->bwk.get() ? block_bytes(h, h->bK, h->bm) : 0;
+    while (K > 2 && block_bytes(h, K, m) > (free_b + held) / 10 * 9) K /= 2;
+    FAMS_REQUIRE(block_bytes(h, K, m) <= free_b + held, FAMS_ERR_OOM,
+                 "no room for the lock-step work space of two right-hand sides");
+  } else {
+    // an allocation hook may hold memory that the device does not count as
+    // free (a caching allocator): ask the hook for the widest work space and
+    // halve the group while it refuses
+    while (K > 2 && block_bytes(h, K, m) > total_b) K /= 2;
+    for (;;) {
+      try {
+        ensure_block_workspace(h, K, m);
+        break;
+      } catch (const Error& e) {
+        if (e.status != FAMS_ERR_OOM || K == 2) throw;
+        K /= 2;
+      }
+    }
+  }
   const int64_t n = h->n;
   fams_status_t worst = FAMS_OK;
   for (int r0 = 0; r0 < nrhs; r0 += K) {
@@ -1406,7 +1437,8 @@ fams_status_t solve_block(Handle* h, const double* q, double* p, int nrhs,
       case 2: solve_group<2>(h, qg, pg, nr, o, inf); break;
       case 4: solve_group<4>(h, qg, pg, nr, o, inf); break;
       case 8: solve_group<8>(h, qg, pg, nr, o, inf); break;
-      default: solve_group<16>(h, qg, pg, nr, o, inf); break;
+      case 16: solve_group<16>(h, qg, pg, nr, o, inf); break;
+      default: solve_group<32>(h, qg, pg, nr, o, inf); break;
     }
     for (int r = 0; r < nr; ++r)
       if (inf[r].status > worst) worst = static_cast<fams_status_t>(inf[r].status);

@@ -1154,9 +1154,12 @@ namespace {
 // workgroups all hold lower chunks, which wait only on lower chunks still,
 // so one of them finishes and draws it.
 constexpr int kBlkRows = 64;
+// rows per chunk for K lanes per row: workgroups of at most 1024 threads
+template <int K>
+constexpr int blk_rows() { return K <= 16 ? kBlkRows : 1024 / K; }
 
 template <class T, bool kUpper, int K>
-__global__ void __launch_bounds__(kBlkRows * K)
+__global__ void __launch_bounds__(blk_rows<K>() * K)
 k_bsweep(const int* rows, const int* chunk, int nchunks, const int* rp, const int* ci,
          const int* diag, const T* lu, const T* in, T* out, T* arm, int* ticket, int ncls,
          int* err, unsigned long long limit) {
@@ -1214,16 +1217,19 @@ __global__ void k_bfill_sentinel(int64_t n, T* x) {
   if (i < n) reinterpret_cast<U*>(x)[i] = Sentinel<T>::bits;
 }
 
-// chunks of at most kBlkRows rows inside one level (the lock-step sweeps)
-void block_chunk_table(Handle* h, Levels* L) {
-  if (L->bchunk.get()) return;
+// chunks of at most `rows` rows inside one level (the lock-step sweeps; 64
+// rows, or 32 for groups of 32 right-hand sides), kept in the level structure
+void block_chunk_table(Handle* h, Levels* L, int rows) {
+  DBuf<int>& tab = rows == kBlkRows ? L->bchunk : L->bchunk32;
+  int& count = rows == kBlkRows ? L->nbchunks : L->nbchunks32;
+  if (tab.get()) return;
   std::vector<int> cb;
   for (int l = 0; l < L->count(); ++l)
-    for (int s = L->ptr[l]; s < L->ptr[l + 1]; s += kBlkRows) cb.push_back(s);
+    for (int s = L->ptr[l]; s < L->ptr[l + 1]; s += rows) cb.push_back(s);
   cb.push_back(L->ptr.empty() ? 0 : L->ptr.back());
-  L->nbchunks = static_cast<int>(cb.size()) - 1;
-  L->bchunk.reset(&h->alloc, cb.size());
-  HIPX(hipMemcpyAsync(L->bchunk, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice,
+  count = static_cast<int>(cb.size()) - 1;
+  tab.reset(&h->alloc, cb.size());
+  HIPX(hipMemcpyAsync(tab, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice,
                       h->stream));
   HIPX(hipStreamSynchronize(h->stream));
 }
@@ -1239,8 +1245,13 @@ void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
     h->sweep_err.reset(&h->alloc, 2);   // error bits, long waits
     HIPX(hipMemsetAsync(h->sweep_err, 0, 2 * sizeof(int), h->stream));
   }
-  block_chunk_table(h, &h->lvl_lo);
-  block_chunk_table(h, &h->lvl_up);
+  constexpr int rows = blk_rows<K>();
+  block_chunk_table(h, &h->lvl_lo, rows);
+  block_chunk_table(h, &h->lvl_up, rows);
+  const int nlo = rows == kBlkRows ? h->lvl_lo.nbchunks : h->lvl_lo.nbchunks32;
+  const int nup = rows == kBlkRows ? h->lvl_up.nbchunks : h->lvl_up.nbchunks32;
+  const int* clo = rows == kBlkRows ? h->lvl_lo.bchunk.get() : h->lvl_lo.bchunk32.get();
+  const int* cup = rows == kBlkRows ? h->lvl_up.bchunk.get() : h->lvl_up.bchunk32.get();
   int* tlo = h->ilu_ticket.get() + kTicketBlock;
   int* tup = tlo + kXcd * kTicketStride;
   HIPX(hipMemsetAsync(tlo, 0, 2 * kXcd * kTicketStride * sizeof(int), h->stream));
@@ -1248,17 +1259,16 @@ void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
   LAUNCH(h, "bilu_arm", k_bfill_sentinel<T>, blocks_for(nk, kT), kT, 0, nk, y);
   const unsigned long long lim = wait_limit(h);
   // about 2048 threads per compute unit in flight
-  const int cap = 256 * 2048 / (kBlkRows * K);
-  const int groups_lo = std::min(h->lvl_lo.nbchunks, cap);
-  const int groups_up = std::min(h->lvl_up.nbchunks, cap);
-  LAUNCH(h, "bilu_lower", (k_bsweep<T, false, K>), groups_lo, kBlkRows * K, 0,
-         h->lvl_lo.rows.get(), h->lvl_lo.bchunk.get(), h->lvl_lo.nbchunks, h->rp.get(),
-         h->ci.get(), h->diag.get(), lu, b, y, x, tlo, std::min(groups_lo, kXcd),
+  const int cap = 256 * 2048 / (rows * K);
+  const int groups_lo = std::min(nlo, cap);
+  const int groups_up = std::min(nup, cap);
+  LAUNCH(h, "bilu_lower", (k_bsweep<T, false, K>), groups_lo, rows * K, 0,
+         h->lvl_lo.rows.get(), clo, nlo, h->rp.get(), h->ci.get(), h->diag.get(), lu, b, y, x,
+         tlo, std::min(groups_lo, kXcd), h->sweep_err.get(), lim);
+  LAUNCH(h, "bilu_upper", (k_bsweep<T, true, K>), groups_up, rows * K, 0,
+         h->lvl_up.rows.get(), cup, nup, h->rp.get(), h->ci.get(), h->diag.get(), lu,
+         static_cast<const T*>(y), x, static_cast<T*>(nullptr), tup, std::min(groups_up, kXcd),
          h->sweep_err.get(), lim);
-  LAUNCH(h, "bilu_upper", (k_bsweep<T, true, K>), groups_up, kBlkRows * K, 0,
-         h->lvl_up.rows.get(), h->lvl_up.bchunk.get(), h->lvl_up.nbchunks, h->rp.get(),
-         h->ci.get(), h->diag.get(), lu, static_cast<const T*>(y), x, static_cast<T*>(nullptr),
-         tup, std::min(groups_up, kXcd), h->sweep_err.get(), lim);
 }
 
 #define FAMS_ILU_BLOCK(T, K) \
@@ -1267,10 +1277,12 @@ FAMS_ILU_BLOCK(double, 2)
 FAMS_ILU_BLOCK(double, 4)
 FAMS_ILU_BLOCK(double, 8)
 FAMS_ILU_BLOCK(double, 16)
+FAMS_ILU_BLOCK(double, 32)
 FAMS_ILU_BLOCK(float, 2)
 FAMS_ILU_BLOCK(float, 4)
 FAMS_ILU_BLOCK(float, 8)
 FAMS_ILU_BLOCK(float, 16)
+FAMS_ILU_BLOCK(float, 32)
 #undef FAMS_ILU_BLOCK
 
 template void ilu_apply<double>(Handle*, const double*, const double*, double*, double*);

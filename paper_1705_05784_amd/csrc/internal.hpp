@@ -173,6 +173,8 @@ struct Levels {
   int nchunks = 0;
   DBuf<int> bchunk;      // device: chunks of the lock-step sweeps (<= 64 rows, one level)
   int nbchunks = 0;
+  DBuf<int> bchunk32;    // the same with <= 32 rows (groups of 32 right-hand sides)
+  int nbchunks32 = 0;
   int count() const { return ptr.empty() ? 0 : static_cast<int>(ptr.size()) - 1; }
 };
 

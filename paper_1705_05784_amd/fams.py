@@ -49,6 +49,38 @@ class SetupOpts(C.Structure):
                 ("restriction", C.c_int32), ("nonsymmetric", C.c_int32)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class AllocatorHook(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  int(stream or 0))
+    except Exception:   # NULL: the library reports FAMS_ERR_OOM
+        return None
+
+
+def _torch_free(ctx, ptr, stream):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:   # interpreter shutdown: the process returns the memory
+        pass
+
+
+# torch's caching allocator behind the library's allocation hook: a handle's
+# buffers go back to torch's cache when it is destroyed and the next handle of
+# the same shape takes them from there, instead of fresh device memory that
+# the driver clears first (seconds for ~100 GB of work space)
+TORCH_ALLOCATOR = AllocatorHook(None, _ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("outer", C.c_int32), ("restart", C.c_int32), ("rtol", C.c_double),
                 ("max_iter", C.c_int32), ("use_initial_guess", C.c_int32)]
@@ -74,8 +106,8 @@ EXPORTS = {
     "fams_last_error": ([], C.c_char_p),
     "fams_footprint": ([C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                         C.POINTER(C.c_size_t)], C.c_int),
-    "fams_setup": ([C.POINTER(CSR), C.POINTER(Grid), C.POINTER(SetupOpts), C.c_void_p,
-                    C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "fams_setup": ([C.POINTER(CSR), C.POINTER(Grid), C.POINTER(SetupOpts),
+                    C.POINTER(AllocatorHook), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "fams_update_values": ([C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_int32)],
                            C.c_int),
     "fams_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(SolveOpts),
@@ -169,13 +201,15 @@ class Solver:
     restriction: RESTRICT_FE (P^T), RESTRICT_FV or RESTRICT_MIX (or "fe",
     "fv", "mix"); n_wells: the last n_wells unknowns are well pressures (each
     a coarse node of its own); nonsymmetric: A may be non-symmetric (LU local
-    solves and coarse inverse; no flux reconstruction).  Arrays may be numpy or torch; the handle
-    copies them.
+    solves and coarse inverse; no flux reconstruction); allocator: None
+    (hipMallocAsync / hipFreeAsync on the handle's stream) or "torch" (torch's
+    caching allocator, so that handles created one after another reuse the
+    same device memory).  Arrays may be numpy or torch; the handle copies them.
     """
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
                  precision=FP64, alpha=0.0, merge_cap=4096, smoother=True, profile=False,
-                 restriction=0, n_wells=0, nonsymmetric=False):
+                 restriction=0, n_wells=0, nonsymmetric=False, allocator=None):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -199,9 +233,12 @@ class Solver:
         opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
                          int(smoother), 1 if profile else 0, int(restriction),
                          1 if nonsymmetric else 0)
+        if allocator not in (None, "torch"):
+            raise ValueError(f"allocator must be None or 'torch', not {allocator!r}")
+        hook = C.byref(TORCH_ALLOCATOR) if allocator == "torch" else None
         h = C.c_void_p()
         self._h = None
-        _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), None, _stream(),
+        _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), hook, _stream(),
                                 C.byref(h)), "fams_setup")
         self._h = h
         self._keep = None   # the handle owns copies of everything it needs

@@ -56,10 +56,10 @@ def test_grid_helpers_config2_shape():
 
 def test_footprint_grows_with_lockstep_rhs():
     """Several right-hand sides add the lock-step work space (groups of up
-    to 16): the bound grows with max_nrhs up to 16 and stays there."""
+    to 32): the bound grows with max_nrhs up to 32 and stays there."""
     from paper_1705_05784_amd import fams
-    b = [fams.footprint(100000, 700000, 500, 1, 30, k) for k in (1, 2, 3, 16, 64)]
-    assert b[0] < b[1] < b[2] < b[3] == b[4]
+    b = [fams.footprint(100000, 700000, 500, 1, 30, k) for k in (1, 2, 3, 16, 32, 64)]
+    assert b[0] < b[1] < b[2] < b[3] < b[4] == b[5]
     with pytest.raises(fams.FamsError):
         fams.footprint(100000, 700000, 500, 1, 30, 0)
 

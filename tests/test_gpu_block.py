@@ -136,3 +136,22 @@ def test_lockstep_restart_lengths(restart):
         assert abs(info[r]["iterations"] - i1[0]["iterations"]) <= 1, (r, info[r], i1[0])
         assert np.linalg.norm(P[r] - p1) <= 1e-9 * np.linalg.norm(p1), r
     g.close()
+
+
+@pytest.mark.parametrize("outer", ["gmres", "richardson"])
+def test_lockstep_group_of_32(outer):
+    """33 right-hand sides: one group of 32 (32 rows per sweep chunk) and one
+    padded group; every column equals its own single solve."""
+    say(f"[lockstep] nrhs=33 outer={outer}")
+    s, _, g = solver("3d", 3, 1)
+    Q = rhs_set(s, 33, seed=33)
+    it_max = 400 if outer == "richardson" else 300
+    P, info = g.solve(torch.from_numpy(Q), outer=outer, rtol=1e-10, max_iter=it_max)
+    P = P.cpu().numpy()
+    for r in range(33):
+        p1, i1 = g.solve(torch.from_numpy(Q[r]), outer=outer, rtol=1e-10, max_iter=it_max)
+        p1 = p1.cpu().numpy()
+        assert info[r]["status"] == 0 and i1[0]["status"] == 0
+        assert abs(info[r]["iterations"] - i1[0]["iterations"]) <= 1, (r, info[r], i1[0])
+        assert np.linalg.norm(P[r] - p1) <= 1e-9 * np.linalg.norm(p1), r
+    g.close()
