@@ -76,7 +76,9 @@ def block_bytes(name, z, K):
     """Algorithmic bytes of one launch of a lock-step kernel: every matrix
     entry and every vector entry once (gathered neighbours counted as cache
     hits).  z: sizes; K: right-hand sides per group; s: bytes per stage value
-    (4 in the precision form)."""
+    (4 in the precision form).  The upper sweep also reads the prolongated
+    coarse correction and writes the FP64 sum of the two stages (ILU(0)
+    smoother without the per-medium stage, as in every lock-step leg here)."""
     n, nnz, zp, nc, s = z["n"], z["nnz"], z["nnz_P"], z["n_coarse"], z["s"]
     half = (nnz - n) / 2.0
     return {
@@ -87,7 +89,7 @@ def block_bytes(name, z, K):
         "bcoarse": 8.0 * nc * nc + 2 * K * nc * 8,
         "bprolong": zp * (s + 4) + 4 * (n + 1) + K * nc * 8 + K * n * s,
         "bilu_lower": half * (s + 4) + 12 * n + 3 * K * n * s,
-        "bilu_upper": (half + n) * (s + 4) + 12 * n + 2 * K * n * s,
+        "bilu_upper": (half + n) * (s + 4) + 12 * n + 2 * K * n * s + K * n * (s + 8),
         "bdot": K * n * 8,
         "bscale": 2 * K * n * 8,
         "bpack": 2 * K * n * 8,

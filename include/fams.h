@@ -201,6 +201,12 @@ typedef struct {
                                  dependencies were not running, e.g. another
                                  process's work on the device; a wait gives up at
                                  2 s with FAMS_ERR_DEVICE) */
+  int64_t tiled_rows;         /* rows that the lock-step products with A visit in
+                                 slabs of grid lines marched along z (the first
+                                 n_matrix rows when they form a 3D grid in natural
+                                 order, found at the first lock-step solve; 0
+                                 before it or otherwise); an order for cache reuse
+                                 only, the results do not depend on it */
 } fams_setup_info_t;
 
 /* ---- lifecycle -------------------------------------------------------- */

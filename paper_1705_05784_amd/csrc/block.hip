@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <map>
 #include <type_traits>
 #include <vector>
 
@@ -97,11 +98,12 @@ __device__ __forceinline__ void store_pair_to(T* p, double a, double b) {
 
 template <class TV, class TX, class TB, class TY, int K, bool kResid>
 __global__ void __launch_bounds__(256)
-k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const TB* B, TY* Y) {
+k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const TB* B, TY* Y,
+        RowTiling tl) {
   constexpr int H = K / 2;
   const int64_t e2 = xcd_block() * blockDim.x + threadIdx.x;
   if (e2 >= static_cast<int64_t>(n) * H) return;
-  const int i = static_cast<int>(e2 / H), r = 2 * static_cast<int>(e2 % H);
+  const int i = tiled_row(tl, static_cast<int>(e2 / H)), r = 2 * static_cast<int>(e2 % H);
   double s0 = 0.0, s1 = 0.0;
   const int p0 = rp[i], p1 = rp[i + 1];
   for (int pb = p0; pb < p1; pb += 8) {
@@ -132,6 +134,101 @@ k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const T
     s1 = b1 - s1;
   }
   store_pair_to<TY>(Y + o, s0, s1);
+}
+
+// The products with A in the lock-step solves read A in a fixed-width form:
+// kEll (column, value) slots per row in CSR order, padded with (row, 0),
+// and per row the CSR position and count of the entries beyond kEll.  A
+// row's slots sit at a position computed from the row alone, so the index
+// and value loads need no row-pointer load before them: one dependent
+// memory step less per row than CSR, and wide loads.  Same terms in the
+// same order as the CSR product (padding adds +0).
+constexpr int kEll = 8;
+
+template <class TV>
+__device__ __forceinline__ void load_ell_vals(const TV* p, TV* v);
+template <>
+__device__ __forceinline__ void load_ell_vals<double>(const double* p, double* v) {
+#pragma unroll
+  for (int k = 0; k < kEll; k += 2) {
+    const double2 t = reinterpret_cast<const double2*>(p)[k / 2];
+    v[k] = t.x;
+    v[k + 1] = t.y;
+  }
+}
+template <>
+__device__ __forceinline__ void load_ell_vals<float>(const float* p, float* v) {
+#pragma unroll
+  for (int k = 0; k < kEll; k += 4) {
+    const float4 t = reinterpret_cast<const float4*>(p)[k / 4];
+    v[k] = t.x;
+    v[k + 1] = t.y;
+    v[k + 2] = t.z;
+    v[k + 3] = t.w;
+  }
+}
+
+template <class TV, class TX, class TB, class TY, int K, bool kResid>
+__global__ void __launch_bounds__(256)
+k_bspmv_ell(int n, const int* ecol, const TV* eval, const int* ovf, const int* ci, const TV* val,
+            const TX* X, const TB* B, TY* Y, RowTiling tl) {
+  constexpr int H = K / 2;
+  const int64_t e2 = xcd_block() * blockDim.x + threadIdx.x;
+  if (e2 >= static_cast<int64_t>(n) * H) return;
+  const int i = tiled_row(tl, static_cast<int>(e2 / H)), r = 2 * static_cast<int>(e2 % H);
+  const int64_t o = static_cast<int64_t>(i) * K + r;
+  int c[kEll];
+  TV v[kEll];
+#pragma unroll
+  for (int k = 0; k < kEll; k += 4) {
+    const int4 t = reinterpret_cast<const int4*>(ecol + static_cast<int64_t>(i) * kEll)[k / 4];
+    c[k] = t.x;
+    c[k + 1] = t.y;
+    c[k + 2] = t.z;
+    c[k + 3] = t.w;
+  }
+  load_ell_vals<TV>(eval + static_cast<int64_t>(i) * kEll, v);
+  const int2 ov = reinterpret_cast<const int2*>(ovf)[i];
+  double b0 = 0.0, b1 = 0.0;
+  if (kResid && B) load_pair<TB>(B + o, b0, b1);
+  double x0[kEll], x1[kEll];
+#pragma unroll
+  for (int k = 0; k < kEll; ++k) load_pair<TX>(X + static_cast<int64_t>(c[k]) * K + r, x0[k], x1[k]);
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < kEll; ++k) {
+    s0 += static_cast<double>(v[k]) * x0[k];
+    s1 += static_cast<double>(v[k]) * x1[k];
+  }
+  for (int p = ov.x; p < ov.x + ov.y; ++p) {
+    double a0, a1;
+    load_pair<TX>(X + static_cast<int64_t>(ci[p]) * K + r, a0, a1);
+    s0 += static_cast<double>(val[p]) * a0;
+    s1 += static_cast<double>(val[p]) * a1;
+  }
+  if constexpr (kResid) {
+    s0 = b0 - s0;
+    s1 = b1 - s1;
+  }
+  store_pair_to<TY>(Y + o, s0, s1);
+}
+
+// columns and overflow ranges of the fixed-width form (one thread per row)
+__global__ void k_ell_cols(int n, const int* rp, const int* ci, int* ecol, int* ovf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = rp[i], d = rp[i + 1] - p0;
+  for (int k = 0; k < kEll; ++k) ecol[static_cast<int64_t>(i) * kEll + k] = k < d ? ci[p0 + k] : i;
+  ovf[2 * i] = p0 + kEll;
+  ovf[2 * i + 1] = d > kEll ? d - kEll : 0;
+}
+
+template <class TV>
+__global__ void k_ell_vals(int n, const int* rp, const TV* val, TV* eval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = rp[i], d = rp[i + 1] - p0;
+  for (int k = 0; k < kEll; ++k) eval[static_cast<int64_t>(i) * kEll + k] = k < d ? val[p0 + k] : TV(0);
 }
 
 // sum over the lanes of a workgroup of 256 that hold the same r = tid % K
@@ -1037,6 +1134,64 @@ size_t block_bytes(Handle* h, int K, int m) {
   return b;
 }
 
+// forward column offsets (j - i, j in the first nm rows) of up to 8 entries
+// of each of S rows spread evenly over the first nm rows; 0 fills the rest
+constexpr int kTileSample = 4096;
+__global__ void k_offset_sample(int nm, const int* rp, const int* ci, int* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= kTileSample) return;
+  const int i = static_cast<int>(static_cast<int64_t>(s) * nm / kTileSample);
+  int k = 0;
+  for (int p = rp[i]; p < rp[i + 1] && k < 8; ++p) {
+    const int j = ci[p];
+    if (j > i && j < nm) out[s * 8 + k++] = j - i;
+  }
+  for (; k < 8; ++k) out[s * 8 + k] = 0;
+}
+
+// The grid behind the first nm rows, read off the sample: offset 1 and two
+// larger offsets sy < sz, each in at least half of the sampled rows, with
+// sz a multiple of sy and nm a multiple of sz (then the slab order is a
+// permutation of the nm rows whatever the matrix is).  Anything else, or a
+// grid too small to gain, keeps natural order.
+RowTiling infer_tiling(Handle* h) {
+  RowTiling t;
+  const int nm = h->nm;
+  if (nm < 4096) return t;
+  DBuf<int> d(&h->alloc, kTileSample * 8);
+  LAUNCH(h, "btiling", k_offset_sample, blocks_for(kTileSample, 256), 256, 0, nm, h->rp.get(),
+         h->ci.get(), d.get());
+  std::vector<int> off(kTileSample * 8);
+  HIPX(hipMemcpyAsync(off.data(), d.get(), off.size() * sizeof(int), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
+  std::map<int, int> hist;
+  for (int v : off)
+    if (v > 0) ++hist[v];
+  int sy = 0, sz = 0, cy = 0, cz = 0;  // the two most frequent offsets above 1
+  for (const auto& [v, c] : hist) {
+    if (v == 1) continue;
+    if (c > cy) {
+      sz = sy; cz = cy;
+      sy = v; cy = c;
+    } else if (c > cz) {
+      sz = v; cz = c;
+    }
+  }
+  if (sy > sz) std::swap(sy, sz), std::swap(cy, cz);
+  const int half = kTileSample / 2;
+  if (hist.count(1) == 0 || hist[1] < half || cy < half || cz < half || sy < 2 || sz % sy != 0 ||
+      nm % sz != 0)
+    return t;
+  t.nm = nm;
+  t.sy = sy;
+  t.ny = sz / sy;
+  t.nz = nm / sz;
+  t.yb = std::max(1, std::min(t.ny, 4096 / sy));  // a slab plane of ~4096 rows
+  if (t.nz < 2) t = RowTiling{};
+  return t;
+}
+
 void free_block_workspace(Handle* h) {
   h->bK = 0;
   h->bwk.free();
@@ -1048,6 +1203,17 @@ void free_block_workspace(Handle* h) {
 
 // all or nothing: a failed allocation leaves no work space (bK = 0)
 void ensure_block_workspace(Handle* h, int K, int m) {
+  if (!h->tiling_known) {
+    h->tiling = infer_tiling(h);
+    h->tiling_known = true;
+    h->info.tiled_rows = h->tiling.sy ? h->tiling.nm : 0;
+  }
+  if (!h->ell_col.get()) {
+    h->ell_col.reset(&h->alloc, static_cast<size_t>(h->n) * kEll);
+    h->ell_ovf.reset(&h->alloc, 2 * static_cast<size_t>(h->n));
+    LAUNCH(h, "bell", k_ell_cols, blocks_for(h->n, 256), 256, 0, h->n, h->rp.get(), h->ci.get(),
+           h->ell_col.get(), h->ell_ovf.get());
+  }
   if (h->bK == K && h->bm >= m && h->bwk.get()) return;
   free_block_workspace(h);
   try {
@@ -1067,14 +1233,49 @@ void ensure_block_workspace(Handle* h, int K, int m) {
   h->bm = m;
 }
 
-// y = b - A x on block vectors ("bspmv_resid" inside the stage, "bresid_outer"
-// for the FP64 residual of the outer iteration)
-template <class TV, class TX, class TB, class TY, int K>
-void bresid(Handle* h, const int* rp, const int* ci, const TV* val, const TX* x, const TB* b,
-            TY* y, const char* name = "bspmv_resid") {
+// A's fixed-width form with values of type TV (FP64, or FP32 in the
+// precision form), built from the CSR arrays on first use
+template <class TV>
+const TV* ell_values(Handle* h);
+template <>
+const double* ell_values<double>(Handle* h) {
+  if (!h->ell_val.get()) {
+    h->ell_val.reset(&h->alloc, static_cast<size_t>(h->n) * kEll);
+    LAUNCH(h, "bell", k_ell_vals<double>, blocks_for(h->n, 256), 256, 0, h->n, h->rp.get(),
+           h->val.get(), h->ell_val.get());
+  }
+  return h->ell_val.get();
+}
+template <>
+const float* ell_values<float>(Handle* h) {
+  if (!h->ell_val32.get()) {
+    h->ell_val32.reset(&h->alloc, static_cast<size_t>(h->n) * kEll);
+    LAUNCH(h, "bell", k_ell_vals<float>, blocks_for(h->n, 256), 256, 0, h->n, h->rp.get(),
+           h->val32.get(), h->ell_val32.get());
+  }
+  return h->ell_val32.get();
+}
+
+template <class TV>
+const TV* csr_values(Handle* h) {
+  if constexpr (std::is_same<TV, double>::value) return h->val.get();
+  else return h->val32.get();
+}
+
+// y = b - A x (kResid; "bspmv_resid" inside the stage, "bresid_outer" for the
+// FP64 residual of the outer iteration) or y = A x ("bspmv") on block vectors
+template <class TV, class TX, class TB, class TY, int K, bool kResid>
+void aprod(Handle* h, const TX* x, const TB* b, TY* y, const char* name) {
   const int64_t nk = static_cast<int64_t>(h->n) * K;
-  LAUNCH(h, name, (k_bspmv<TV, TX, TB, TY, K, true>), xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n,
-         rp, ci, val, x, b, y);
+  const TV* ev = ell_values<TV>(h);
+  LAUNCH(h, name, (k_bspmv_ell<TV, TX, TB, TY, K, kResid>), xcd_grid(blocks_for(nk / 2, kT)), kT,
+         0, h->n, h->ell_col.get(), ev, h->ell_ovf.get(), h->ci.get(), csr_values<TV>(h), x, b, y,
+         h->tiling);
+}
+
+template <class TV, class TX, class TB, class TY, int K>
+void bresid(Handle* h, const TX* x, const TB* b, TY* y, const char* name = "bspmv_resid") {
+  aprod<TV, TX, TB, TY, K, true>(h, x, b, y, name);
 }
 
 // Table 1 steps 5-7 on K residuals at once (FP64 in and out; T = stage type)
@@ -1082,13 +1283,12 @@ template <class T, int K>
 void bstage(Handle* h, const BWork& k, const double* r, double* z) {
   const int n = h->n, nc = h->nc;
   const int64_t nk = k.nk;
-  const T *pv, *rv, *av, *lu;
+  const T *pv, *rv, *lu;
   const T* rT;
   T *d1, *rh, *x, *ysc, *xb;
   if constexpr (std::is_same<T, double>::value) {
     pv = h->p_val.get();
     rv = h->r_val.get();
-    av = h->val.get();
     lu = h->ilu.get();
     rT = r;
     d1 = k.d1;
@@ -1099,7 +1299,6 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
   } else {
     pv = h->p_val32.get();
     rv = h->r_val32.get();
-    av = h->val32.get();
     lu = h->ilu32.get();
     LAUNCH(h, "bcast_d2f", (k_bcast<double, float>), blocks_for(nk, kT), kT, 0, nk, r, k.r32);
     rT = k.r32;
@@ -1118,16 +1317,21 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
     LAUNCH(h, "bcoarse_red", k_bcoarse_red, blocks_for(nck, kT), kT, 0, nck, k.nch, k.cpart, k.xc);
   }
   LAUNCH(h, "bprolong", (k_bspmv<T, double, T, T, K, false>), xcd_grid(blocks_for(nk / 2, kT)), kT, 0,
-         n, h->p_rp.get(), h->p_ci.get(), pv, k.xc, static_cast<const T*>(nullptr), d1);
+         n, h->p_rp.get(), h->p_ci.get(), pv, k.xc, static_cast<const T*>(nullptr), d1,
+         RowTiling{});
   if (h->smoother) {
-    bresid<T, T, T, T, K>(h, h->rp.get(), h->ci.get(), av, d1, rT, rh);
+    bresid<T, T, T, T, K>(h, d1, rT, rh);
+    if (!h->blk) {  // z = d1 + x written by the upper sweep as each row finishes
+      ilu_apply_block<T, K>(h, lu, rh, x, ysc, d1, z);
+      return;
+    }
     ilu_apply_block<T, K>(h, lu, rh, x, ysc);
-    if (h->blk) {  // per-medium stage on the residual left by the ILU(0) stage
+    {  // per-medium stage on the residual left by the ILU(0) stage
       Handle* b = h->blk.get();
       const T* blu;
       if constexpr (std::is_same<T, double>::value) blu = b->ilu.get();
       else blu = b->ilu32.get();
-      bresid<T, T, T, T, K>(h, h->rp.get(), h->ci.get(), av, x, rh, rh);
+      bresid<T, T, T, T, K>(h, x, rh, rh);
       ilu_apply_block<T, K>(b, blu, rh, xb, ysc);
       LAUNCH(h, "badd", (k_badd<T, T, T>), blocks_for(nk, kT), kT, 0, nk, x, xb, x);
     }
@@ -1194,8 +1398,7 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
   // the next step) while its fused kernels can take the basis, else CGS2
   // with three passes
   const bool two_pass = m <= kFuseMax && offset_addressable(nk, k.nb);
-  bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p, k.q,
-                                              k.r, "bresid_outer");
+  bresid<double, double, double, double, K>(h, k.p, k.q, k.r, "bresid_outer");
   bnorms<K>(h, k, k.r, S.beta);
   std::vector<double> b = read_field(h, k, S.beta, 1);
   for (int r = 0; r < K; ++r) {
@@ -1229,9 +1432,8 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
         double* uj = k.V + j * nk;
         double* zj = k.Z + j * nk;
         bstage_any<K>(h, k, uj, zj);
-        LAUNCH(h, "bspmv", (k_bspmv<double, double, double, double, K, false>),
-               xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(),
-               zj, static_cast<const double*>(nullptr), k.w);
+        aprod<double, double, double, double, K, false>(h, zj, static_cast<const double*>(nullptr),
+                                                        k.w, "bspmv");
         launch_dcgs<K>(h, false, k.nb, nk, j, k.V, nk, k.w, nullptr, 0, k.part, 2 * m + 2);
         LAUNCH(h, "breduce", k_breduce, dim3(2 * j + 2, K), 256, 0, k.nb, K, k.part, 2 * m + 2,
                k.small + S.dots, S.stride);
@@ -1262,9 +1464,8 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
       double* vj = k.V + j * nk;
       double* zj = k.Z + j * nk;
       bstage_any<K>(h, k, vj, zj);
-      LAUNCH(h, "bspmv", (k_bspmv<double, double, double, double, K, false>),
-             xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n, h->rp.get(), h->ci.get(), h->val.get(), zj,
-             static_cast<const double*>(nullptr), k.w);
+      aprod<double, double, double, double, K, false>(h, zj, static_cast<const double*>(nullptr),
+                                                      k.w, "bspmv");
       // CGS2 against V_0..V_j, per right-hand side: h = V^T w; w -= V h and
       // c = V^T w in one pass; w -= V c and ||w|| in one pass; h += c
       launch_bmdot<K>(h, "bmdot", k.nb, nk, j + 1, k.V, nk, k.w, k.part, m + 2);
@@ -1305,8 +1506,7 @@ void block_gmres(Handle* h, const BWork& k, int nr, const fams_solve_opts_t* o,
     LAUNCH(h, "bbacksolve", k_bbacksolve, 1, 64, 0, K, S, k.small, kk);
     LAUNCH(h, "bmaxpy", k_bmaxpy<K>, blocks_for(nk, kT), kT, 0, nk, jmax, k.Z, nk, k.small + S.y,
            S.stride, 1.0, k.p);
-    bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p,
-                                                k.q, k.r, "bresid_outer");
+    bresid<double, double, double, double, K>(h, k.p, k.q, k.r, "bresid_outer");
     bnorms<K>(h, k, k.r, S.beta);
     b = read_field(h, k, S.beta, 1);
     for (int r = 0; r < K; ++r)
@@ -1319,8 +1519,7 @@ void block_richardson(Handle* h, const BWork& k, int nr, const fams_solve_opts_t
                       std::vector<RhsState>& rs) {
   const int64_t nk = k.nk;
   const BState& S = k.st;
-  bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p, k.q,
-                                              k.r, "bresid_outer");
+  bresid<double, double, double, double, K>(h, k.p, k.q, k.r, "bresid_outer");
   bnorms<K>(h, k, k.r, S.beta);
   std::vector<double> b = read_field(h, k, S.beta, 1);
   for (int r = 0; r < K; ++r) {
@@ -1340,8 +1539,7 @@ void block_richardson(Handle* h, const BWork& k, int nr, const fams_solve_opts_t
     if (!mask) break;
     bstage_any<K>(h, k, k.r, k.z);
     LAUNCH(h, "baxpy", k_baxpy_mask<K>, blocks_for(nk, kT), kT, 0, nk, mask, k.z, k.p);
-    bresid<double, double, double, double, K>(h, h->rp.get(), h->ci.get(), h->val.get(), k.p,
-                                                k.q, k.r, "bresid_outer");
+    bresid<double, double, double, double, K>(h, k.p, k.q, k.r, "bresid_outer");
     bnorms<K>(h, k, k.r, S.beta);
     b = read_field(h, k, S.beta, 1);
     for (int r = 0; r < K; ++r)

@@ -1161,8 +1161,8 @@ constexpr int blk_rows() { return K <= 16 ? kBlkRows : 1024 / K; }
 template <class T, bool kUpper, int K>
 __global__ void __launch_bounds__(blk_rows<K>() * K)
 k_bsweep(const int* rows, const int* chunk, int nchunks, const int* rp, const int* ci,
-         const int* diag, const T* lu, const T* in, T* out, T* arm, int* ticket, int ncls,
-         int* err, unsigned long long limit) {
+         const int* diag, const T* lu, const T* in, T* out, T* arm, const T* add, double* sum,
+         int* ticket, int ncls, int* err, unsigned long long limit) {
   using U = typename Sentinel<T>::U;
   __shared__ int s_c;
   const int r = threadIdx.x % K, slot = threadIdx.x / K;
@@ -1182,6 +1182,8 @@ k_bsweep(const int* rows, const int* chunk, int nchunks, const int* rp, const in
       const int p1 = kUpper ? rp[i + 1] : dg;
       const int64_t o = static_cast<int64_t>(i) * K + r;
       T s = in[o];
+      // the addend is read with the row's input, off the dependency chain
+      const T ad = (kUpper && sum) ? add[o] : T(0);
       for (int pb = p0; pb < p1; pb += kDeps) {
         U u[kDeps];
         int j[kDeps];
@@ -1206,6 +1208,8 @@ k_bsweep(const int* rows, const int* chunk, int nchunks, const int* rp, const in
         reinterpret_cast<U*>(arm)[o] = Sentinel<T>::bits;
       }
       store_ready<T>(out + o, s);
+      // the two-stage sum in FP64 once the row is published (sum = add + x)
+      if (kUpper && sum) sum[o] = static_cast<double>(ad) + static_cast<double>(s);
     }
   }
 }
@@ -1237,9 +1241,9 @@ void block_chunk_table(Handle* h, Levels* L, int rows) {
 }  // namespace
 
 // x = U^{-1} L^{-1} b for K right-hand sides in lock-step (x[i * K + r]);
-// y is scratch of n * K entries
+// y is scratch of n * K entries; with `sum`, also sum = add + x in FP64
 template <class T, int K>
-void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
+void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y, const T* add, double* sum) {
   if (!h->ilu_ticket.get()) h->ilu_ticket.reset(&h->alloc, kTicketInts);
   if (!h->sweep_err.get()) {
     h->sweep_err.reset(&h->alloc, 2);   // error bits, long waits
@@ -1264,15 +1268,16 @@ void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y) {
   const int groups_up = std::min(nup, cap);
   LAUNCH(h, "bilu_lower", (k_bsweep<T, false, K>), groups_lo, rows * K, 0,
          h->lvl_lo.rows.get(), clo, nlo, h->rp.get(), h->ci.get(), h->diag.get(), lu, b, y, x,
-         tlo, std::min(groups_lo, kXcd), h->sweep_err.get(), lim);
+         static_cast<const T*>(nullptr), static_cast<double*>(nullptr), tlo,
+         std::min(groups_lo, kXcd), h->sweep_err.get(), lim);
   LAUNCH(h, "bilu_upper", (k_bsweep<T, true, K>), groups_up, rows * K, 0,
          h->lvl_up.rows.get(), cup, nup, h->rp.get(), h->ci.get(), h->diag.get(), lu,
-         static_cast<const T*>(y), x, static_cast<T*>(nullptr), tup, std::min(groups_up, kXcd),
-         h->sweep_err.get(), lim);
+         static_cast<const T*>(y), x, static_cast<T*>(nullptr), add, sum, tup,
+         std::min(groups_up, kXcd), h->sweep_err.get(), lim);
 }
 
 #define FAMS_ILU_BLOCK(T, K) \
-  template void ilu_apply_block<T, K>(Handle*, const T*, const T*, T*, T*);
+  template void ilu_apply_block<T, K>(Handle*, const T*, const T*, T*, T*, const T*, double*);
 FAMS_ILU_BLOCK(double, 2)
 FAMS_ILU_BLOCK(double, 4)
 FAMS_ILU_BLOCK(double, 8)

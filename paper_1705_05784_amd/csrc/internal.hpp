@@ -152,6 +152,28 @@ inline unsigned xcd_grid(int64_t blocks) {
   return static_cast<unsigned>((blocks + kXcd - 1) / kXcd * kXcd);
 }
 
+// Visiting order of the rows of a lock-step sparse product.  When the first
+// nm rows form a 3D grid in natural order (row = x + sy * y + sy * ny * z),
+// they are visited in slabs of yb grid lines, each slab marched along z: the
+// z neighbours a row gathers were then read yb * sy rows earlier (one slab
+// plane, ~1 MB of a 32-wide FP64 block vector) and are still in the XCD's
+// L2, where natural order re-reads them from HBM a whole grid plane later.
+// The remaining rows, and all rows when sy == 0, keep natural order.  Any
+// order gives the same results: each row is computed on its own.
+struct RowTiling {
+  int nm = 0, sy = 0, ny = 0, nz = 0, yb = 0;
+};
+
+__device__ __forceinline__ int tiled_row(const RowTiling& t, int v) {
+  if (t.sy == 0 || v >= t.nm) return v;
+  const unsigned nx = t.sy, full = static_cast<unsigned>(t.yb) * nx * t.nz;
+  const unsigned u = v, slab = u / full, rem = u - slab * full;
+  const unsigned hs = min(static_cast<unsigned>(t.yb), t.ny - slab * t.yb);
+  const unsigned plane = hs * nx, z = rem / plane, r2 = rem - z * plane;
+  const unsigned yl = r2 / nx, x = r2 - yl * nx;
+  return static_cast<int>(x + nx * (slab * t.yb + yl) + nx * t.ny * z);
+}
+
 // the handle's work-ticket words: the one-launch sweeps use the first two;
 // the lock-step sweeps one counter per XCD class and direction, each on a
 // cache line of its own, from kTicketBlock on
@@ -289,6 +311,13 @@ struct Handle {
   DBuf<double> bsmall;  // per-right-hand-side GMRES state and scalars
   DBuf<double> bpart;   // partial sums of the coarse block product
   int bK = 0, bm = 0;
+  RowTiling tiling;     // visiting order of the lock-step products with A
+  bool tiling_known = false;
+  // A in fixed width for the lock-step products: 8 (column, value) slots per
+  // row and each row's CSR position and count of the entries beyond them
+  DBuf<int> ell_col, ell_ovf;
+  DBuf<double> ell_val;
+  DBuf<float> ell_val32;
 
   fams_setup_info_t info{};
 
@@ -367,7 +396,8 @@ template <class T>
 void ilu_apply(Handle* h, const T* lu, const T* b, T* x, T* y);
 // the same for K right-hand sides in lock-step, vectors interleaved x[i * K + r]
 template <class T, int K>
-void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y);
+void ilu_apply_block(Handle* h, const T* lu, const T* b, T* x, T* y,
+                     const T* add = nullptr, double* sum = nullptr);
 // solve.hip
 fams_status_t solve_one(Handle* h, const double* q, double* p, const fams_solve_opts_t* o,
                         fams_info_t* info);

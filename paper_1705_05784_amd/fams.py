@@ -98,7 +98,8 @@ class SetupInfo(C.Structure):
                 ("ilu_levels_lower", C.c_int64), ("ilu_levels_upper", C.c_int64),
                 ("ms_setup", C.c_double), ("device_bytes", C.c_int64),
                 ("local_flops", C.c_double), ("local_subst_flops", C.c_double),
-                ("peak_device_bytes", C.c_int64), ("long_waits", C.c_int64)]
+                ("peak_device_bytes", C.c_int64), ("long_waits", C.c_int64),
+                ("tiled_rows", C.c_int64)]
 
 
 EXPORTS = {

@@ -155,3 +155,28 @@ def test_lockstep_group_of_32(outer):
         assert abs(info[r]["iterations"] - i1[0]["iterations"]) <= 1, (r, info[r], i1[0])
         assert np.linalg.norm(P[r] - p1) <= 1e-9 * np.linalg.norm(p1), r
     g.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lockstep_tiled_row_order(precision):
+    """An 80x70x12 grid: the lock-step products with A visit the matrix rows
+    in slabs of 51 grid lines marched along z (the second slab 19 lines
+    wide); every column still equals its own single solve."""
+    from paper_1705_05784_amd import fams
+    say(f"[lockstep] tiled 80x70x12 precision={precision}")
+    s, spec = small_case("cfg2s", dims=(80, 70, 12), n_frac=20)
+    wb, pr, vx, _ = fams.full_grid(s, spec["coarse"], spec["d_min"], spec["r_z"])
+    g = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=fams.COUPLED,
+                    precision=precision, alpha=1e-2)
+    assert g.setup_info()["tiled_rows"] == 0
+    Q = rhs_set(s, 5, seed=5)
+    P, info = g.solve(torch.from_numpy(Q), rtol=1e-10, max_iter=300)
+    assert g.setup_info()["tiled_rows"] == s.n_matrix == 80 * 70 * 12
+    P = P.cpu().numpy()
+    for r in range(5):
+        p1, i1 = g.solve(torch.from_numpy(Q[r]), rtol=1e-10, max_iter=300)
+        p1 = p1.cpu().numpy()
+        assert info[r]["status"] == 0 and i1[0]["status"] == 0
+        assert abs(info[r]["iterations"] - i1[0]["iterations"]) <= 1, (r, info[r], i1[0])
+        assert np.linalg.norm(P[r] - p1) <= 1e-9 * np.linalg.norm(p1), r
+    g.close()
