@@ -301,8 +301,8 @@ void coarse_setup(Handle* h) {
     }
     HIPX(hipStreamSynchronize(h->stream));
   }
-  h->ell_val.free();    // the lock-step products' copies of the values
-  h->ell_val32.free();
+  h->ell.val.free();    // the lock-step products' copies of A's values
+  h->ell.val32.free();
   if (h->precision == FAMS_PREC_MIXED) {
     h->val32.reset(al, h->nnz);
     LAUNCH(h, "d2f", k_d2f_api, blocks_for(h->nnz, 256), 256, 0, h->nnz, h->val.get(),
@@ -465,7 +465,7 @@ fams_status_t fams_footprint(int64_t n, int64_t nnz, int64_t n_coarse, int32_t p
     const double nk = static_cast<double>(n) * K;
     b += nk * 8 * (10 + 2 * restart + 1) + (mixed ? nk * 4 * 6 : 0.0);
     b += (2 + 34) * nc * K * 8 + 2048.0 * (2 * restart + 4) * K * 8;
-    b += n * (8 * (4 + 8) + 8.0) + (mixed ? n * 8 * 4.0 : 0.0);  // A in fixed width
+    b += 2 * (n * (8 * (4 + 8) + 8.0) + (mixed ? n * 8 * 4.0 : 0.0));  // A, P in fixed width
   }
   b *= 1.10;
   *bytes = static_cast<size_t>(b) + (64u << 20);

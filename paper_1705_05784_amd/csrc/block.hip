@@ -96,53 +96,13 @@ __device__ __forceinline__ void store_pair_to(T* p, double a, double b) {
   *reinterpret_cast<typename Pair<T>::V*>(p) = v;
 }
 
-template <class TV, class TX, class TB, class TY, int K, bool kResid>
-__global__ void __launch_bounds__(256)
-k_bspmv(int n, const int* rp, const int* ci, const TV* val, const TX* X, const TB* B, TY* Y,
-        RowTiling tl) {
-  constexpr int H = K / 2;
-  const int64_t e2 = xcd_block() * blockDim.x + threadIdx.x;
-  if (e2 >= static_cast<int64_t>(n) * H) return;
-  const int i = tiled_row(tl, static_cast<int>(e2 / H)), r = 2 * static_cast<int>(e2 % H);
-  double s0 = 0.0, s1 = 0.0;
-  const int p0 = rp[i], p1 = rp[i + 1];
-  for (int pb = p0; pb < p1; pb += 8) {
-    int c[8];
-    TV v[8];
-    double x0[8], x1[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (pb + k < p1) {
-        c[k] = ci[pb + k];
-        v[k] = val[pb + k];
-      }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (pb + k < p1) load_pair<TX>(X + static_cast<int64_t>(c[k]) * K + r, x0[k], x1[k]);
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (pb + k < p1) {
-        s0 += static_cast<double>(v[k]) * x0[k];
-        s1 += static_cast<double>(v[k]) * x1[k];
-      }
-  }
-  const int64_t o = static_cast<int64_t>(i) * K + r;
-  if constexpr (kResid) {
-    double b0 = 0.0, b1 = 0.0;
-    if (B) load_pair<TB>(B + o, b0, b1);
-    s0 = b0 - s0;
-    s1 = b1 - s1;
-  }
-  store_pair_to<TY>(Y + o, s0, s1);
-}
-
-// The products with A in the lock-step solves read A in a fixed-width form:
-// kEll (column, value) slots per row in CSR order, padded with (row, 0),
-// and per row the CSR position and count of the entries beyond kEll.  A
-// row's slots sit at a position computed from the row alone, so the index
-// and value loads need no row-pointer load before them: one dependent
-// memory step less per row than CSR, and wide loads.  Same terms in the
-// same order as the CSR product (padding adds +0).
+// The products with A and P in the lock-step solves read the matrix in a
+// fixed-width form: kEll (column, value) slots per row in CSR order, padded
+// with (a column of the row, 0), and per row the CSR position and count of
+// the entries beyond kEll.  A row's slots sit at a position computed from
+// the row alone, so the index and value loads need no row-pointer load
+// before them: one dependent memory step less per row than CSR, and wide
+// loads.  Same terms in the same order as the CSR product (padding adds +0).
 constexpr int kEll = 8;
 
 template <class TV>
@@ -213,12 +173,15 @@ k_bspmv_ell(int n, const int* ecol, const TV* eval, const int* ovf, const int* c
   store_pair_to<TY>(Y + o, s0, s1);
 }
 
-// columns and overflow ranges of the fixed-width form (one thread per row)
+// columns and overflow ranges of the fixed-width form (one thread per row);
+// a padding slot repeats the row's first column (column 0 for an empty row):
+// a column of the matrix whatever its shape, and a gather already made
 __global__ void k_ell_cols(int n, const int* rp, const int* ci, int* ecol, int* ovf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int p0 = rp[i], d = rp[i + 1] - p0;
-  for (int k = 0; k < kEll; ++k) ecol[static_cast<int64_t>(i) * kEll + k] = k < d ? ci[p0 + k] : i;
+  const int pad = d > 0 ? ci[p0] : 0;
+  for (int k = 0; k < kEll; ++k) ecol[static_cast<int64_t>(i) * kEll + k] = k < d ? ci[p0 + k] : pad;
   ovf[2 * i] = p0 + kEll;
   ovf[2 * i + 1] = d > kEll ? d - kEll : 0;
 }
@@ -340,6 +303,55 @@ k_bcoarse_part(int nc, int w, const double* M, const double* Y, double* part) {
 #pragma unroll
     for (int r = 0; r < K; ++r) o[r] = acc[r];
   }
+}
+
+// The same on FP64 MFMA for groups of 16 or more (K a multiple of 16): each
+// wavefront forms 16 rows x K of the chunk's partial product with
+// v_mfma_f64_16x16x4 (per instruction lane l supplies A[l%16][l/16] =
+// M[row, col] and B[l/16][l%16] = Y[col, rhs]; accumulator element q holds
+// D[4q + l/16][l%16]), its operands loaded straight from memory kBcU steps
+// of four columns ahead.  One eight-byte operand per lane and 1024
+// multiply-adds, where the vector form above reads one LDS value per
+// multiply-add and lane.
+typedef double v4d_b __attribute__((ext_vector_type(4)));
+constexpr int kBcU = 4;
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_bcoarse_mfma(int nc, int w, const double* M, const double* Y, double* part) {
+  constexpr int NT = K / 16;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int I0 = (blockIdx.x * 4 + wave) * 16;
+  if (I0 >= nc) return;  // a whole wavefront; the kernel has no barrier
+  const int c0 = blockIdx.y * w, c1 = min(nc, c0 + w);
+  const int i = I0 + lane % 16, kq = lane / 16, j = lane % 16;
+  const bool row_ok = i < nc;
+  v4d_b acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4d_b{0.0, 0.0, 0.0, 0.0};
+  for (int c = c0; c < c1; c += 4 * kBcU) {
+    double fa[kBcU], fb[kBcU][NT];
+#pragma unroll
+    for (int u = 0; u < kBcU; ++u) {
+      const int col = c + 4 * u + kq;
+      const bool ok = col < c1;
+      fa[u] = (ok && row_ok) ? M[static_cast<int64_t>(col) * nc + i] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) fb[u][t] = ok ? Y[static_cast<int64_t>(col) * K + t * 16 + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBcU; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[u][t], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = I0 + 4 * q + kq;
+      if (row < nc) part[(static_cast<int64_t>(blockIdx.y) * nc + row) * K + t * 16 + j] = acc[t][q];
+    }
 }
 
 __global__ void k_bcoarse_red(int64_t nk, int nch, const double* part, double* X) {
@@ -1208,12 +1220,6 @@ void ensure_block_workspace(Handle* h, int K, int m) {
     h->tiling_known = true;
     h->info.tiled_rows = h->tiling.sy ? h->tiling.nm : 0;
   }
-  if (!h->ell_col.get()) {
-    h->ell_col.reset(&h->alloc, static_cast<size_t>(h->n) * kEll);
-    h->ell_ovf.reset(&h->alloc, 2 * static_cast<size_t>(h->n));
-    LAUNCH(h, "bell", k_ell_cols, blocks_for(h->n, 256), 256, 0, h->n, h->rp.get(), h->ci.get(),
-           h->ell_col.get(), h->ell_ovf.get());
-  }
   if (h->bK == K && h->bm >= m && h->bwk.get()) return;
   free_block_workspace(h);
   try {
@@ -1233,33 +1239,32 @@ void ensure_block_workspace(Handle* h, int K, int m) {
   h->bm = m;
 }
 
-// A's fixed-width form with values of type TV (FP64, or FP32 in the
-// precision form), built from the CSR arrays on first use
+// the fixed-width form of the CSR matrix (rp, ci, val, val32) with values
+// of type TV, built on first use
 template <class TV>
-const TV* ell_values(Handle* h);
-template <>
-const double* ell_values<double>(Handle* h) {
-  if (!h->ell_val.get()) {
-    h->ell_val.reset(&h->alloc, static_cast<size_t>(h->n) * kEll);
-    LAUNCH(h, "bell", k_ell_vals<double>, blocks_for(h->n, 256), 256, 0, h->n, h->rp.get(),
-           h->val.get(), h->ell_val.get());
+const TV* ell_vals(Handle* h, EllMat& e, const int* rp, const int* ci, const double* val,
+                   const float* val32) {
+  const int n = h->n;
+  if (!e.col.get()) {
+    e.col.reset(&h->alloc, static_cast<size_t>(n) * kEll);
+    e.ovf.reset(&h->alloc, 2 * static_cast<size_t>(n));
+    LAUNCH(h, "bell", k_ell_cols, blocks_for(n, 256), 256, 0, n, rp, ci, e.col.get(),
+           e.ovf.get());
   }
-  return h->ell_val.get();
-}
-template <>
-const float* ell_values<float>(Handle* h) {
-  if (!h->ell_val32.get()) {
-    h->ell_val32.reset(&h->alloc, static_cast<size_t>(h->n) * kEll);
-    LAUNCH(h, "bell", k_ell_vals<float>, blocks_for(h->n, 256), 256, 0, h->n, h->rp.get(),
-           h->val32.get(), h->ell_val32.get());
+  if constexpr (std::is_same<TV, double>::value) {
+    if (!e.val.get()) {
+      e.val.reset(&h->alloc, static_cast<size_t>(n) * kEll);
+      LAUNCH(h, "bell", k_ell_vals<double>, blocks_for(n, 256), 256, 0, n, rp, val, e.val.get());
+    }
+    return e.val.get();
+  } else {
+    if (!e.val32.get()) {
+      e.val32.reset(&h->alloc, static_cast<size_t>(n) * kEll);
+      LAUNCH(h, "bell", k_ell_vals<float>, blocks_for(n, 256), 256, 0, n, rp, val32,
+             e.val32.get());
+    }
+    return e.val32.get();
   }
-  return h->ell_val32.get();
-}
-
-template <class TV>
-const TV* csr_values(Handle* h) {
-  if constexpr (std::is_same<TV, double>::value) return h->val.get();
-  else return h->val32.get();
 }
 
 // y = b - A x (kResid; "bspmv_resid" inside the stage, "bresid_outer" for the
@@ -1267,10 +1272,27 @@ const TV* csr_values(Handle* h) {
 template <class TV, class TX, class TB, class TY, int K, bool kResid>
 void aprod(Handle* h, const TX* x, const TB* b, TY* y, const char* name) {
   const int64_t nk = static_cast<int64_t>(h->n) * K;
-  const TV* ev = ell_values<TV>(h);
+  const TV* ev = ell_vals<TV>(h, h->ell, h->rp.get(), h->ci.get(), h->val.get(), h->val32.get());
+  const TV* cv;
+  if constexpr (std::is_same<TV, double>::value) cv = h->val.get();
+  else cv = h->val32.get();
   LAUNCH(h, name, (k_bspmv_ell<TV, TX, TB, TY, K, kResid>), xcd_grid(blocks_for(nk / 2, kT)), kT,
-         0, h->n, h->ell_col.get(), ev, h->ell_ovf.get(), h->ci.get(), csr_values<TV>(h), x, b, y,
-         h->tiling);
+         0, h->n, h->ell.col.get(), ev, h->ell.ovf.get(), h->ci.get(), cv, x, b, y, h->tiling);
+}
+
+// y = P x on block vectors (natural row order: the gathered coarse values
+// stay in L2 whatever the order)
+template <class TV, int K>
+void pprod(Handle* h, const double* x, TV* y) {
+  const int64_t nk = static_cast<int64_t>(h->n) * K;
+  const TV* ev = ell_vals<TV>(h, h->pell, h->p_rp.get(), h->p_ci.get(), h->p_val.get(),
+                              h->p_val32.get());
+  const TV* cv;
+  if constexpr (std::is_same<TV, double>::value) cv = h->p_val.get();
+  else cv = h->p_val32.get();
+  LAUNCH(h, "bprolong", (k_bspmv_ell<TV, double, TV, TV, K, false>),
+         xcd_grid(blocks_for(nk / 2, kT)), kT, 0, h->n, h->pell.col.get(), ev, h->pell.ovf.get(),
+         h->p_ci.get(), cv, x, static_cast<const TV*>(nullptr), y, RowTiling{});
 }
 
 template <class TV, class TX, class TB, class TY, int K>
@@ -1283,11 +1305,10 @@ template <class T, int K>
 void bstage(Handle* h, const BWork& k, const double* r, double* z) {
   const int n = h->n, nc = h->nc;
   const int64_t nk = k.nk;
-  const T *pv, *rv, *lu;
+  const T *rv, *lu;
   const T* rT;
   T *d1, *rh, *x, *ysc, *xb;
   if constexpr (std::is_same<T, double>::value) {
-    pv = h->p_val.get();
     rv = h->r_val.get();
     lu = h->ilu.get();
     rT = r;
@@ -1297,7 +1318,6 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
     ysc = k.y;
     xb = k.xb;
   } else {
-    pv = h->p_val32.get();
     rv = h->r_val32.get();
     lu = h->ilu32.get();
     LAUNCH(h, "bcast_d2f", (k_bcast<double, float>), blocks_for(nk, kT), kT, 0, nk, r, k.r32);
@@ -1311,14 +1331,19 @@ void bstage(Handle* h, const BWork& k, const double* r, double* z) {
   LAUNCH(h, "brestrict", (k_brestrict<T, T, K>), nc, 256, 0, nc, h->r_rp.get(), h->r_ci.get(),
          rv, rT, k.rc);
   {
-    dim3 grid(blocks_for(nc, 256), k.nch);
-    LAUNCH(h, "bcoarse", k_bcoarse_part<K>, grid, 256, 0, nc, k.cw, h->Ainv.get(), k.rc, k.cpart);
+    if constexpr (K % 16 == 0) {
+      dim3 grid(blocks_for(nc, 64), k.nch);
+      LAUNCH(h, "bcoarse", k_bcoarse_mfma<K>, grid, 256, 0, nc, k.cw, h->Ainv.get(), k.rc,
+             k.cpart);
+    } else {
+      dim3 grid(blocks_for(nc, 256), k.nch);
+      LAUNCH(h, "bcoarse", k_bcoarse_part<K>, grid, 256, 0, nc, k.cw, h->Ainv.get(), k.rc,
+             k.cpart);
+    }
     const int64_t nck = static_cast<int64_t>(nc) * K;
     LAUNCH(h, "bcoarse_red", k_bcoarse_red, blocks_for(nck, kT), kT, 0, nck, k.nch, k.cpart, k.xc);
   }
-  LAUNCH(h, "bprolong", (k_bspmv<T, double, T, T, K, false>), xcd_grid(blocks_for(nk / 2, kT)), kT, 0,
-         n, h->p_rp.get(), h->p_ci.get(), pv, k.xc, static_cast<const T*>(nullptr), d1,
-         RowTiling{});
+  pprod<T, K>(h, k.xc, d1);
   if (h->smoother) {
     bresid<T, T, T, T, K>(h, d1, rT, rh);
     if (!h->blk) {  // z = d1 + x written by the upper sweep as each row finishes

@@ -160,6 +160,23 @@ inline unsigned xcd_grid(int64_t blocks) {
 // L2, where natural order re-reads them from HBM a whole grid plane later.
 // The remaining rows, and all rows when sy == 0, keep natural order.  Any
 // order gives the same results: each row is computed on its own.
+// A sparse matrix in fixed width (the lock-step products): 8 (column,
+// value) slots per row in CSR order, padded with (the row's first column,
+// 0), and each row's
+// CSR position and count of the entries beyond them; the values in FP64 and,
+// for the precision form, FP32.  Built from the CSR arrays on first use.
+struct EllMat {
+  DBuf<int> col, ovf;
+  DBuf<double> val;
+  DBuf<float> val32;
+  void clear() {
+    col.free();
+    ovf.free();
+    val.free();
+    val32.free();
+  }
+};
+
 struct RowTiling {
   int nm = 0, sy = 0, ny = 0, nz = 0, yb = 0;
 };
@@ -313,11 +330,8 @@ struct Handle {
   int bK = 0, bm = 0;
   RowTiling tiling;     // visiting order of the lock-step products with A
   bool tiling_known = false;
-  // A in fixed width for the lock-step products: 8 (column, value) slots per
-  // row and each row's CSR position and count of the entries beyond them
-  DBuf<int> ell_col, ell_ovf;
-  DBuf<double> ell_val;
-  DBuf<float> ell_val32;
+  // A and P in fixed width for the lock-step products
+  EllMat ell, pell;
 
   fams_setup_info_t info{};
 

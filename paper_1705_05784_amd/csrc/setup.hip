@@ -1388,6 +1388,7 @@ void build_prolongation(Handle* h, const int8_t* wb) {
   h->info.fp32_fallback_blocks = fallbacks;
 
   // P as CSR (truncated), then R = P^T by a stable sort on the column
+  h->pell.clear();  // the lock-step products' fixed-width copy follows P
   DBuf<int> cnt(A, n);
   h->p_rp.reset(A, n + 1);
   if (mixed)
