@@ -679,51 +679,79 @@ k_gemm_mfma(int m, int p, int k, double alpha, const double* A, int lda, const d
       }
 }
 
-// Large-tile form: a workgroup forms a 128 x 128 tile, each wavefront a
-// 64 x 64 quarter of 4 x 4 blocks of v_mfma_f64_16x16x4 (16 accumulators of
-// four doubles).  The k dimension advances 16 at a time through two LDS
-// buffers: while the MFMAs consume one buffer, every thread holds the next
-// 16-wide slices of A and B in registers and stores them into the other
-// buffer after the step, so one barrier per step and the global loads
-// overlap the arithmetic.
-constexpr int kBT = 128, kBK = 32, kBPad = kBT + 4;
+// Large-tile form: a workgroup of eight wavefronts forms a 128 x 128 tile,
+// each wavefront a 64 x 32 eighth of 4 x 2 blocks of v_mfma_f64_16x16x4
+// (8 accumulators of four doubles); two wavefronts per SIMD, so one's load
+// and address work overlaps the other's MFMAs.  The k dimension advances
+// kBK at a time through two LDS buffers: while the MFMAs consume one
+// buffer, every thread holds the next kBK-wide slices of A and B in
+// registers (loaded from clamped addresses, zeroed outside the operands,
+// without branches) and stores them into the other buffer after the step,
+// so one barrier per step and the global loads overlap the arithmetic.
+// Tiles are numbered in a one-dimensional grid: workgroups go to the eight
+// XCDs in turn (b % 8), each XCD takes a contiguous run of the tile order,
+// and the order walks groups of kGroupRows row tiles column tile by column
+// tile, so the tiles an XCD runs at once share A's rows and B's columns in
+// its L2 (with the workgroups of a column of tiles spread over all XCDs,
+// every XCD streamed every operand tile from beyond its L2).
+constexpr int kBT = 128, kBK = 32, kBPad = kBT + 4, kGroupRows = 8;
 
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ void gemm_tile(int tr_n, int tc_n, int& tr, int& tc) {
+  const int T = tr_n * tc_n, b = blockIdx.x;
+  const int x = b % kXcd, s = b / kXcd;
+  const int g = x * (T / kXcd) + min(x, T % kXcd) + s;
+  const int span = kGroupRows * tc_n;
+  const int first = (g / span) * kGroupRows;
+  const int rows = min(kGroupRows, tr_n - first);
+  const int o = g - (g / span) * span;
+  tr = first + o % rows;
+  tc = o / rows;
+}
+
+constexpr int kBThreads = 512, kBWc = 2;  // threads, column blocks per wavefront
+
+__global__ void __launch_bounds__(kBThreads)
 k_gemm_mfma128(int m, int p, int k, double alpha, const double* A, int lda, const double* B,
                int ldb, double* C, int ldc, int skip0, int skip1, int overwrite) {
   __shared__ double As[2][kBK][kBPad];
   __shared__ double Bs[2][kBK][kBPad];
-  const int r0 = blockIdx.x * kBT, c0 = blockIdx.y * kBT;
+  int tr, tc;
+  gemm_tile((m + kBT - 1) / kBT, (p + kBT - 1) / kBT, tr, tc);
+  const int r0 = tr * kBT, c0 = tc * kBT;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wr = (wave % 2) * 64, wc = (wave / 2) * 64;
+  const int wr = (wave % 2) * 64, wc = (wave / 2) * (16 * kBWc);
   // global slice loads: A column-major, 128 rows x kBK k: thread t loads row
-  // t % 128 at k = t / 128 + 2u; B column-major, kBK k x 128 columns: thread t
-  // loads k = t % kBK of columns t / kBK + (256 / kBK) u; kBK / 2 of each
-  constexpr int kL = kBK / 2, kCs = 256 / kBK;
+  // t % 128 at k = t / 128 + 4u; B column-major, kBK k x 128 columns: thread t
+  // loads k = t % kBK of columns t / kBK + (512 / kBK) u; kBK / 4 of each
+  constexpr int kL = kBK * kBT / kBThreads, kAs = kBThreads / kBT, kCs = kBThreads / kBK;
   const int ar = tid % kBT, ak = tid / kBT;
   const int bk = tid % kBK, bc = tid / kBK;
   double ra[kL], rb[kL];
   auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < kL; ++u) {
-      const int kk = k0 + ak + 2 * u, rr = r0 + ar;
-      ra[u] = (rr < m && kk < k) ? A[static_cast<int64_t>(kk) * lda + rr] : 0.0;
+      const int kk = k0 + ak + kAs * u, rr = r0 + ar;
+      const bool oa = rr < m && kk < k;
+      const double va = A[oa ? static_cast<int64_t>(kk) * lda + rr : 0];
+      ra[u] = oa ? va : 0.0;
       const int kb = k0 + bk, cc = c0 + bc + kCs * u;
-      rb[u] = (cc < p && kb < k) ? B[static_cast<int64_t>(cc) * ldb + kb] : 0.0;
+      const bool ob = cc < p && kb < k;
+      const double vb = B[ob ? static_cast<int64_t>(cc) * ldb + kb : 0];
+      rb[u] = ob ? vb : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < kL; ++u) {
-      As[buf][ak + 2 * u][ar] = ra[u];
+      As[buf][ak + kAs * u][ar] = ra[u];
       Bs[buf][bk][bc + kCs * u] = rb[u];
     }
   };
-  v4d acc[4][4];
+  v4d acc[4][kBWc];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < kBWc; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
   load(0);
   store(0);
   __syncthreads();
@@ -733,16 +761,15 @@ k_gemm_mfma128(int m, int p, int k, double alpha, const double* A, int lda, cons
     if (more) load(k0 + kBK);
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
-      double fa[4], fb[4];
+      double fa[4], fb[kBWc];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        fa[t] = As[buf][kk + lane / 16][wr + t * 16 + lane % 16];
-        fb[t] = Bs[buf][kk + lane / 16][wc + t * 16 + lane % 16];
-      }
+      for (int t = 0; t < 4; ++t) fa[t] = As[buf][kk + lane / 16][wr + t * 16 + lane % 16];
+#pragma unroll
+      for (int t = 0; t < kBWc; ++t) fb[t] = Bs[buf][kk + lane / 16][wc + t * 16 + lane % 16];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < kBWc; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
     if (more) store(buf ^ 1);
@@ -752,7 +779,7 @@ k_gemm_mfma128(int m, int p, int k, double alpha, const double* A, int lda, cons
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < kBWc; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = r0 + wr + a * 16 + 4 * q + lane / 16;
@@ -771,9 +798,9 @@ void gemm_mfma(Handle* h, int m, int p, int k, double alpha, const double* A, in
   hipStream_t s = st ? st : h->stream;
   const int ow = overwrite ? 1 : 0;
   if (static_cast<int64_t>(blocks_for(m, kBT)) * blocks_for(p, kBT) >= 192) {
-    dim3 grid(blocks_for(m, kBT), blocks_for(p, kBT));
-    LAUNCH_ON(h, s, "gemm_mfma", k_gemm_mfma128, grid, 256, 0, m, p, k, alpha, A, lda, B, ldb, C,
-              ldc, skip0, skip1, ow);
+    const unsigned tiles = blocks_for(m, kBT) * blocks_for(p, kBT);
+    LAUNCH_ON(h, s, "gemm_mfma", k_gemm_mfma128, tiles, kBThreads, 0, m, p, k, alpha, A, lda, B,
+              ldb, C, ldc, skip0, skip1, ow);
   } else {  // small products: more, smaller tiles keep the device busy
     dim3 grid(blocks_for(m, kGT), blocks_for(p, kGT));
     LAUNCH_ON(h, s, "gemm_mfma", k_gemm_mfma, grid, 256, 0, m, p, k, alpha, A, lda, B, ldb, C,
