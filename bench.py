@@ -515,7 +515,8 @@ def leg_serving(args):
     cmd = [sys.executable, "-m", "paper_1705_05784_amd.serving", "--requests",
            str(args.serving_requests), "--slots", "4", "--load", "0.7"]
     try:
-        out = subprocess.run(cmd, capture_output=True, text=True, cwd=ROOT,
+        # its progress lines pass through on stderr
+        out = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, cwd=ROOT,
                              timeout=args.serving_timeout)
         return json.loads(out.stdout.strip().splitlines()[-1])
     except Exception as e:  # reported, never required for the headline

@@ -148,18 +148,19 @@ LAUNCH_NAMES = {
     "k_local_solve<float, float>": "local_solve",
     "k_sweep_ranges<float, false>": "ilu_lower", "k_sweep_ranges<float, true>": "ilu_upper",
     "k_sweep_lower<float>": "ilu_lower", "k_sweep_upper<float>": "ilu_upper",
-    # lock-step kernels of the precision form with 16 right-hand sides
-    "k_bsweep<float, false, 16>": "bilu_lower", "k_bsweep<float, true, 16>": "bilu_upper",
-    "k_bspmv<double, double, double, double, 16, true>": "bresid_outer",
-    "k_bspmv<double, double, double, double, 16, false>": "bspmv",
-    "k_bspmv<float, float, float, float, 16, true>": "bspmv_resid",
-    "k_bspmv<float, double, float, float, 16, false>": "bprolong",
-    "k_brestrict<float, float, 16>": "brestrict", "k_bcoarse_part<16>": "bcoarse",
+    # lock-step kernels of the precision form with 32 right-hand sides
+    "k_bsweep<float, false, 32>": "bilu_lower", "k_bsweep<float, true, 32>": "bilu_upper",
+    "k_bspmv_ell<double, double, double, double, 32, true>": "bresid_outer",
+    "k_bspmv_ell<double, double, double, double, 32, false>": "bspmv",
+    "k_bspmv_ell<float, float, float, float, 32, true>": "bspmv_resid",
+    "k_bspmv_ell<float, double, float, float, 32, false>": "bprolong",
+    "k_brestrict<float, float, 32>": "brestrict", "k_bcoarse_mfma<32>": "bcoarse",
+    "k_bcast<double, float>": "bcast_d2f",
     "k_gemm_mfma128": "gemm_mfma",
     # the Gram-Schmidt passes, one instantiation per basis size bucket
-    "k_bmaxpy_mdot<16,*": "bmaxpy_mdot", "k_bmaxpy_norm<16,*": "bmaxpy_norm",
-    "k_bmdot<16,*": "bmdot", "k_bmdot<16, 1>": "bdot",
-    "k_dcgs_dots<16,*": "bgs_dots", "k_dcgs_update<16,*": "bgs_update",
+    "k_bmaxpy_mdot<32,*": "bmaxpy_mdot", "k_bmaxpy_norm<32,*": "bmaxpy_norm",
+    "k_bmdot<32,*": "bmdot", "k_bmdot<32, 1>": "bdot",
+    "k_dcgs_dots<32,*": "bgs_dots", "k_dcgs_update<32,*": "bgs_update",
 }
 
 

@@ -21,6 +21,7 @@ admission logic is testable without a device.
 """
 from __future__ import annotations
 
+import sys
 import threading
 import time
 from collections import deque
@@ -245,11 +246,12 @@ class Server:
     """
 
     def __init__(self, runner, slots: int = 8, hbm_budget: int | None = None,
-                 footprint=None):
+                 footprint=None, progress: int = 0):
         self.runner = runner
         self.slots = int(slots)
         self.hbm_budget = hbm_budget
         self.footprint = footprint
+        self.progress = int(progress)  # a line on stderr every `progress` completions
         self.peak_inflight = 0
         self.peak_reserved = 0
 
@@ -294,6 +296,9 @@ class Server:
                     state["reserved"] -= need
                     state["inflight"] -= 1
                     state["done"] += 1
+                    if self.progress and state["done"] % self.progress == 0:
+                        print(f"[serving] {state['done']}/{len(reqs)} requests done at "
+                              f"{res.t_done:.1f} s", file=sys.stderr, flush=True)
                     cv.notify_all()
 
         threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(self.slots)]
@@ -394,7 +399,8 @@ def _main(argv=None):
     print(f"[serving] {len(reqs)} requests ready", file=sys.stderr, flush=True)
     mu = None
     with ProcessRunner(a.slots, prec, alpha=1e-2, rtol=1e-6) as run:
-        srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec))
+        srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec),
+                     progress=16)
         rate = a.rate
         if a.load is not None:
             probe = reqs[:max(1, min(a.probe, len(reqs)))]
@@ -408,7 +414,8 @@ def _main(argv=None):
         for r, g in zip(reqs, gaps):
             t += g / rate
             r.arrival = t
-        srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec))
+        srv = Server(run, slots=a.slots, footprint=lambda r: request_footprint(r, prec),
+                     progress=32)
         res = srv.run(reqs, realtime=True)
     a.rate = rate
     out = summarize(res, cells)
