@@ -34,6 +34,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import signal
 import subprocess
 import sys
 import time
@@ -511,16 +512,39 @@ def leg_contrast(args, dev):
 def leg_serving(args):
     """Continuous batching of a Poisson stream of setup + solve requests
     (cubes of side 32-128 with 10-300 plates, 1-16 right-hand sides each),
-    in worker processes of their own on the one GPU."""
+    in worker processes of their own on the one GPU.  The dispatcher and its
+    workers run in a session of their own; past the time limit the whole
+    process group is killed and waited for, so that nothing of this leg is
+    left on the GPU when the headline starts."""
     cmd = [sys.executable, "-m", "paper_1705_05784_amd.serving", "--requests",
            str(args.serving_requests), "--slots", "4", "--load", "0.7"]
+    # its progress lines pass through on stderr
+    proc = subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True, cwd=ROOT,
+                            start_new_session=True)
     try:
-        # its progress lines pass through on stderr
-        out = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, cwd=ROOT,
-                             timeout=args.serving_timeout)
-        return json.loads(out.stdout.strip().splitlines()[-1])
+        out, _ = proc.communicate(timeout=args.serving_timeout)
+    except subprocess.TimeoutExpired:
+        os.killpg(proc.pid, signal.SIGKILL)
+        proc.communicate()
+        _wait_group_gone(proc.pid)
+        return {"error": f"timed out after {args.serving_timeout} s", "requests":
+                args.serving_requests}
+    _wait_group_gone(proc.pid)
+    try:
+        return json.loads(out.strip().splitlines()[-1])
     except Exception as e:  # reported, never required for the headline
-        return {"error": f"{type(e).__name__}: {e}"}
+        return {"error": f"{type(e).__name__}: {e}", "rc": proc.returncode}
+
+
+def _wait_group_gone(pgid, limit_s=60.0):
+    """Wait until no process of group `pgid` is left (the serving workers)."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < limit_s:
+        try:
+            os.killpg(pgid, 0)
+        except ProcessLookupError:
+            return
+        time.sleep(0.2)
 
 
 def cpu_baseline(timeout=600):
@@ -571,8 +595,8 @@ def main():
     ap.add_argument("--legs", nargs="*", default=["config2", "contrast", "serving"],
                     choices=["config2", "contrast", "serving"])
     ap.add_argument("--contrasts", type=float, nargs="*", default=[1e2, 1e4, 1e6, 1e8])
-    ap.add_argument("--serving-requests", type=int, default=512)
-    ap.add_argument("--serving-timeout", type=int, default=420)
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-timeout", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true",

@@ -92,7 +92,7 @@ def _execute(system, grid, variant, rhs, precision, alpha, rtol, restart, flux, 
                setup_ms=0.0)
     t0 = time.perf_counter()
     solver = fams.Solver(s["row_ptr"], s["col"], s["val"], s["n_matrix"], *grid, variant=variant,
-                         precision=precision, alpha=alpha, allocator="torch")
+                         precision=precision, alpha=alpha)
     try:
         out["setup_ms"] = (time.perf_counter() - t0) * 1e3
         q = torch.from_numpy(np.ascontiguousarray(rhs)).to("cuda")
