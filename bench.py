@@ -517,7 +517,7 @@ def leg_serving(args):
     process group is killed and waited for, so that nothing of this leg is
     left on the GPU when the headline starts."""
     cmd = [sys.executable, "-m", "paper_1705_05784_amd.serving", "--requests",
-           str(args.serving_requests), "--slots", "4", "--load", "0.7"]
+           str(args.serving_requests), "--slots", "2", "--load", "0.7"]
     # its progress lines pass through on stderr
     proc = subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True, cwd=ROOT,
                             start_new_session=True)

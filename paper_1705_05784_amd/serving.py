@@ -386,7 +386,10 @@ def _main(argv=None):
                          "(overrides --rate): the first --probe requests are first run with "
                          "all arrivals at t = 0, and their completions per second set mu")
     ap.add_argument("--probe", type=int, default=48)
-    ap.add_argument("--slots", type=int, default=4)
+    # two slot processes: with four, the spin-waiting dataflow kernels of the
+    # processes stalled one another (48 requests at once: 92 s and 4 requests
+    # over the 2 s wait bound, against 12 s with one slot and 8.2 s with two)
+    ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--pool", type=int, default=8, help="distinct systems in the stream")
     ap.add_argument("--side", type=int, nargs=2, default=(32, 128))
     ap.add_argument("--seed", type=int, default=0)

@@ -24,9 +24,9 @@ def test_alone_vs_mix():
     _say("[serving] alone (1 slot process)")
     with ProcessRunner(1, fams.MIXED, **kw) as run1:
         alone = Server(run1, slots=1, footprint=fp).run(reqs, realtime=False)
-    _say("[serving] mix (4 slot processes)")
-    with ProcessRunner(4, fams.MIXED, **kw) as run4:
-        srv = Server(run4, slots=4, footprint=fp)
+    _say("[serving] mix (2 slot processes, the serving default)")
+    with ProcessRunner(2, fams.MIXED, **kw) as run2:
+        srv = Server(run2, slots=2, footprint=fp)
         mix = srv.run(reqs, realtime=False)
     assert srv.peak_inflight >= 2
     worst = 0.0
