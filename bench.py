@@ -595,7 +595,7 @@ def main():
     ap.add_argument("--legs", nargs="*", default=["config2", "contrast", "serving"],
                     choices=["config2", "contrast", "serving"])
     ap.add_argument("--contrasts", type=float, nargs="*", default=[1e2, 1e4, 1e6, 1e8])
-    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-timeout", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
