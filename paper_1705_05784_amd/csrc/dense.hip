@@ -214,6 +214,97 @@ k_rap_ap(int nc, const int* R_rp, const int* R_ci, const double* R_val, const in
   }
 }
 
+// The same rows in one pass over R's entries: the coarse row's columns J go
+// into an LDS hash table shared by the workgroup's wavefronts (kRapSlots
+// keys; a wavefront's instruction holds distinct columns, and every
+// wavefront has its own value copy), each wavefront adds its quarter of the
+// entries in R's order, and the copies are added in wavefront order, so
+// every sum is the one k_rap_ap forms.  k_rap_ap keeps a dense accumulator
+// per wavefront, at most jt columns wide for LDS, and so reads R's entries
+// and their rows of A P once per jt columns (five times at n_c = 17,810).
+// `out` must hold zeros; a row with more than kRapSlots / 2 distinct columns
+// sets *err and writes nothing (the caller then uses k_rap_ap).
+constexpr int kRapSlots = 2048;
+
+__device__ __forceinline__ int rap_slot(int* tab, int key, bool* full) {
+  unsigned hh = (static_cast<unsigned>(key) * 2654435761u) & (kRapSlots - 1);
+  for (int probe = 0; probe < kRapSlots; ++probe) {
+    const int prev = atomicCAS(&tab[hh], kApEmpty, key);
+    if (prev == kApEmpty || prev == key) return static_cast<int>(hh);
+    hh = (hh + 1) & (kRapSlots - 1);
+  }
+  *full = true;
+  return -1;
+}
+
+__global__ void __launch_bounds__(64 * kRapWaves)
+k_rap_hash(int nc, const int* R_rp, const int* R_ci, const double* R_val, const int64_t* ap_rp,
+           const int* ap_ci, const double* ap_val, double* out, int* err) {
+  __shared__ int keys[kRapSlots];
+  __shared__ double acc[kRapWaves][kRapSlots];
+  __shared__ int s_bad, s_used;
+  const int I = blockIdx.x;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  for (int k = threadIdx.x; k < kRapSlots; k += blockDim.x) {
+    keys[k] = kApEmpty;
+#pragma unroll
+    for (int w = 0; w < kRapWaves; ++w) acc[w][k] = 0.0;
+  }
+  if (threadIdx.x == 0) s_bad = s_used = 0;
+  __syncthreads();
+  const int e0 = R_rp[I], e1 = R_rp[I + 1], ne = e1 - e0;
+  const int eb = e0 + static_cast<int>(static_cast<int64_t>(ne) * wave / kRapWaves);
+  const int ee = e0 + static_cast<int>(static_cast<int64_t>(ne) * (wave + 1) / kRapWaves);
+  double* a = acc[wave];
+  bool full = false;
+  for (int e0b = eb; e0b < ee; e0b += kRapGroup) {
+    const int el = e0b + lane;
+    const bool okl = lane < kRapGroup && el < ee;
+    const int il = okl ? R_ci[el] : 0;
+    const int64_t ql0 = okl ? ap_rp[il] : 0, ql1 = okl ? ap_rp[il + 1] : 0;
+    const double wl = okl ? (R_val ? R_val[el] : 1.0) : 0.0;
+    int Jv[kRapGroup];
+    double v[kRapGroup];
+#pragma unroll
+    for (int g = 0; g < kRapGroup; ++g) {
+      const int64_t q = __shfl(ql0, g) + lane;
+      const bool ok = q < __shfl(ql1, g);
+      Jv[g] = ok ? ap_ci[q] : -1;
+      v[g] = ok ? ap_val[q] : 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < kRapGroup; ++g) {
+      const double w = __shfl(wl, g);
+      if (Jv[g] >= 0) {
+        const int sl = rap_slot(keys, Jv[g], &full);
+        if (sl >= 0) a[sl] += w * v[g];
+      }
+      const int64_t q1 = __shfl(ql1, g);
+      for (int64_t q = __shfl(ql0, g) + 64 + lane; q < q1; q += 64) {  // rows beyond 64 entries
+        const int sl = rap_slot(keys, ap_ci[q], &full);
+        if (sl >= 0) a[sl] += w * ap_val[q];
+      }
+    }
+  }
+  if (full) atomicOr(&s_bad, 1);
+  __syncthreads();
+  int used = 0;
+  for (int k = threadIdx.x; k < kRapSlots; k += blockDim.x) used += keys[k] != kApEmpty;
+  atomicAdd(&s_used, used);
+  __syncthreads();
+  if (s_bad || s_used > kRapSlots / 2) {
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
+  for (int k = threadIdx.x; k < kRapSlots; k += blockDim.x) {
+    if (keys[k] == kApEmpty) continue;
+    double t = acc[0][k];
+#pragma unroll
+    for (int w = 1; w < kRapWaves; ++w) t += acc[w][k];
+    out[static_cast<int64_t>(keys[k]) * nc + I] = t;
+  }
+}
+
 // ---- LU with partial pivoting ----------------------------------------------
 // Panel [k0, k0+nb) of rows [k0, n): pivot = first row of maximal |a|.
 __global__ void __launch_bounds__(1024)
@@ -1014,10 +1105,22 @@ void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const do
   const int jt = std::min(nc, 4096);
   build_ap(h);
   if (h->ap_state == 1) {
-    const size_t lds = static_cast<size_t>(kRapWaves) * jt * sizeof(double);
-    allow_lds(reinterpret_cast<const void*>(&k_rap_ap), lds);
-    LAUNCH(h, "rap", k_rap_ap, rows, 64 * kRapWaves, lds, nc, R_rp, R_ci, R_val,
-           h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, jt);
+    // one pass with hashed columns; rows with too many columns for the table
+    // (none in the workloads here) are redone by the tiled form
+    DBuf<int> err(&h->alloc, 1);
+    HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+    HIPX(hipMemsetAsync(out, 0, static_cast<size_t>(nc) * nc * sizeof(double), h->stream));
+    LAUNCH(h, "rap", k_rap_hash, rows, 64 * kRapWaves, 0, nc, R_rp, R_ci, R_val,
+           h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, err.get());
+    int herr = 0;
+    HIPX(hipMemcpyAsync(&herr, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    if (herr) {
+      const size_t lds = static_cast<size_t>(kRapWaves) * jt * sizeof(double);
+      allow_lds(reinterpret_cast<const void*>(&k_rap_ap), lds);
+      LAUNCH(h, "rap", k_rap_ap, rows, 64 * kRapWaves, lds, nc, R_rp, R_ci, R_val,
+             h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, jt);
+    }
   } else {  // rows of A P too wide for the table: the direct triple product
     LAUNCH(h, "rap", k_rap, rows, 64, jt * sizeof(double), nc, R_rp, R_ci, R_val, h->rp.get(),
            h->ci.get(), h->val.get(), h->p_rp.get(), h->p_ci.get(), h->p_val.get(), out, jt);
