@@ -1105,16 +1105,20 @@ void build_coarse_operator(Handle* h, const int* R_rp, const int* R_ci, const do
   const int jt = std::min(nc, 4096);
   build_ap(h);
   if (h->ap_state == 1) {
-    // one pass with hashed columns; rows with too many columns for the table
-    // (none in the workloads here) are redone by the tiled form
-    DBuf<int> err(&h->alloc, 1);
-    HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
-    HIPX(hipMemsetAsync(out, 0, static_cast<size_t>(nc) * nc * sizeof(double), h->stream));
-    LAUNCH(h, "rap", k_rap_hash, rows, 64 * kRapWaves, 0, nc, R_rp, R_ci, R_val,
-           h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, err.get());
-    int herr = 0;
-    HIPX(hipMemcpyAsync(&herr, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPX(hipStreamSynchronize(h->stream));
+    // all rows: one pass with hashed columns (the output zeroed first); rows
+    // with too many columns for the table (none in the workloads here) are
+    // redone by the tiled form, which also serves a build of fewer rows (it
+    // writes only those)
+    int herr = 1;
+    if (rows == nc) {
+      DBuf<int> err(&h->alloc, 1);
+      HIPX(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+      HIPX(hipMemsetAsync(out, 0, static_cast<size_t>(nc) * nc * sizeof(double), h->stream));
+      LAUNCH(h, "rap", k_rap_hash, rows, 64 * kRapWaves, 0, nc, R_rp, R_ci, R_val,
+             h->ap_rp.get(), h->ap_ci.get(), h->ap_val.get(), out, err.get());
+      HIPX(hipMemcpyAsync(&herr, err.get(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+    }
     if (herr) {
       const size_t lds = static_cast<size_t>(kRapWaves) * jt * sizeof(double);
       allow_lds(reinterpret_cast<const void*>(&k_rap_ap), lds);
