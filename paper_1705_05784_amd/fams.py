@@ -204,9 +204,10 @@ class Solver:
     "fv", "mix"); n_wells: the last n_wells unknowns are well pressures (each
     a coarse node of its own); nonsymmetric: A may be non-symmetric (LU local
     solves and coarse inverse; no flux reconstruction); allocator: None
-    (hipMallocAsync / hipFreeAsync on the handle's stream) or "torch" (torch's
+    (hipMallocAsync / hipFreeAsync on the handle's stream), "torch" (torch's
     caching allocator, so that handles created one after another reuse the
-    same device memory).  Arrays may be numpy or torch; the handle copies them.
+    same device memory) or an AllocatorHook of the caller's (kept alive with
+    the handle).  Arrays may be numpy or torch; the handle copies them.
     """
 
     def __init__(self, row_ptr, col, val, n_matrix, wb_type, primal, vertex, variant=DECOUPLED,
@@ -235,9 +236,14 @@ class Solver:
         opts = SetupOpts(int(variant), int(precision), float(alpha), int(merge_cap),
                          int(smoother), 1 if profile else 0, int(restriction),
                          1 if nonsymmetric else 0)
-        if allocator not in (None, "torch"):
-            raise ValueError(f"allocator must be None or 'torch', not {allocator!r}")
-        hook = C.byref(TORCH_ALLOCATOR) if allocator == "torch" else None
+        if isinstance(allocator, AllocatorHook):
+            hook = C.byref(allocator)
+        elif allocator in (None, "torch"):
+            hook = C.byref(TORCH_ALLOCATOR) if allocator == "torch" else None
+        else:
+            raise ValueError("allocator must be None, 'torch' or an AllocatorHook, "
+                             f"not {allocator!r}")
+        self._hook = allocator  # the callbacks must outlive the handle
         h = C.c_void_p()
         self._h = None
         _check(lib().fams_setup(C.byref(csr), C.byref(grid), C.byref(opts), hook, _stream(),

@@ -71,3 +71,42 @@ def test_allocator_name_is_checked():
     s, (wb, pr, vx, _) = _system()
     with pytest.raises(ValueError):
         fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, allocator="malloc")
+
+
+def test_hook_refusal_narrows_the_group():
+    """A hook that refuses every allocation above 3 GB: the 16-wide lock-step
+    work space of the 100x100x50 system (about 5.6 GB) is asked for and
+    refused, the solve falls back to groups of 8, and every column still
+    equals its own single solve."""
+    from paper_1705_05784_amd import fams
+    from workloads.serving import well_rhs
+    print("[allocator] refusing hook", flush=True)
+    s, (wb, pr, vx, _) = _system()
+    cap = 3 << 30
+    refused = []
+
+    def alloc(ctx, nbytes, stream):
+        if nbytes > cap:
+            refused.append(int(nbytes))
+            return None
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  int(stream or 0))
+
+    def free(ctx, ptr, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    hook = fams.AllocatorHook(None, fams._ALLOC_FN(alloc), fams._FREE_FN(free))
+    g = fams.Solver(s.row_ptr, s.col, s.val, s.n_matrix, wb, pr, vx, variant=fams.COUPLED,
+                    precision=fams.MIXED, alpha=1e-2, allocator=hook)
+    rng = np.random.default_rng(3)
+    Q = torch.from_numpy(np.stack([well_rhs(s, 4, rng) for _ in range(12)])).cuda()
+    P, infos = g.solve(Q, rtol=1e-10)
+    assert refused and min(refused) > cap, refused   # the 16-wide work space was refused
+    assert g.setup_info()["device_bytes"] < 2 * cap
+    for r in range(12):
+        p1, i1 = g.solve(Q[r], rtol=1e-10)
+        assert infos[r]["status"] == 0 and i1[0]["status"] == 0
+        assert abs(infos[r]["iterations"] - i1[0]["iterations"]) <= 1, (r, infos[r], i1[0])
+        err = float(torch.linalg.norm(P[r] - p1) / torch.linalg.norm(p1))
+        assert err <= 1e-9, (r, err)
+    g.close()
