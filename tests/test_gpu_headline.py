@@ -1,6 +1,6 @@
 """The 256x256x128 workload with 2000 plates at full size, in the launch
-configuration the benchmark times: Coupled-AMS, alpha 1e-2, precision form,
-64 right-hand sides on one setup in lock-step groups of 32, FGMRES(30) to a
+configuration the benchmark times: Coupled-AMS, alpha 1e-2, precision form
+and plain FP64, 64 right-hand sides on one setup in lock-step groups of 32, FGMRES(30) to a
 relative residual of 1e-6, torch's caching allocator behind the setup's
 allocation hook.  Checked on sampled outputs: every eighth column's true
 residual, computed on the host with scipy from the returned pressure
@@ -18,16 +18,25 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+_sys = {}
 
 
-def test_headline_lockstep_full_size():
+def _workload():
+    if "s" not in _sys:
+        from workloads import make_config
+        from workloads.configs import config_rhs
+        print("[headline] building the 256x256x128 workload", flush=True)
+        s = make_config(5)
+        _sys["s"] = s
+        _sys["Q"] = config_rhs(s, 5, 64)
+    return _sys["s"], _sys["Q"]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_headline_lockstep_full_size(precision):
     from paper_1705_05784_amd import fams
-    from workloads import make_config
-    from workloads.configs import config_rhs
     from workloads.edfm import system_key
-    print("[headline] building the 256x256x128 workload", flush=True)
-    s = make_config(5)
-    Q = config_rhs(s, 5, 64)
+    s, Q = _workload()
     key = system_key(s.row_ptr, s.col, s.val, Q[0])
     pref_path = os.path.join(ROOT, "oracle", "_pref", key + ".npy")
     if not os.path.exists(pref_path):
@@ -36,9 +45,10 @@ def test_headline_lockstep_full_size():
     wb, pr, vx, _ = fams.full_grid(s, (10, 10, 10), 10, 10)
     dev = torch.device("cuda", 0)
     args = [torch.from_numpy(a).to(dev) for a in (s.row_ptr, s.col, s.val, wb, pr, vx)]
-    print("[headline] setup", flush=True)
+    print(f"[headline] setup ({precision})", flush=True)
     g = fams.Solver(*args[:3], s.n_matrix, *args[3:], variant=fams.COUPLED,
-                    precision=fams.MIXED, alpha=1e-2, allocator="torch")
+                    precision=fams.MIXED if precision == "mixed" else fams.FP64, alpha=1e-2,
+                    allocator="torch")
     print("[headline] 64 right-hand sides in groups of 32", flush=True)
     P, infos = g.solve(torch.from_numpy(Q).to(dev), rtol=1e-6, max_iter=1000)
     si = g.setup_info()
